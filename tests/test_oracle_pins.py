@@ -1,0 +1,497 @@
+"""Pins of the FP64 CPU oracle against what the paper and mathematics fix.
+
+None of these tests re-types the oracle's update.  They check it against
+closed forms (leapfrog equivalence, discrete Fourier solution, exact standing
+wave, quadratic-field exactness of the boundary rules, Newmark closed-form
+sum), invariants (conservation, static patch states, mirror symmetry,
+Dirichlet pinning, synchronization) and the paper's parameter relations.
+"""
+import numpy as np
+import pytest
+
+from oracle.oracle import OraclePlate, OracleError, run_case
+from paper_2301_00228_amd import inputs as I
+
+
+def lap5(r):
+    """5-point Laplacian on a periodic grid (lattice units)."""
+    return (np.roll(r, 1, 0) + np.roll(r, -1, 0) + np.roll(r, 1, 1) + np.roll(r, -1, 1) - 4 * r)
+
+
+def leapfrog(r0, a, nsteps):
+    """Brute-force explicit finite-difference wave solve r^{n+1} = 2 r^n - r^{n-1}
+    + 2a lap5(r^n), started from rest with the second-order start r^1 = r^0 +
+    a lap5(r^0).  Courant number squared = 2a (Sec. 3,
+    eq. parameters_to_wavespeed_relation)."""
+    prev, cur = r0.copy(), r0 + a * lap5(r0)
+    if nsteps == 0:
+        return prev
+    for _ in range(nsteps - 1):
+        prev, cur = cur, 2 * cur - prev + 2 * a * lap5(cur)
+    return cur
+
+
+def fourier_solution(r0, a, n):
+    """Discrete Fourier solution of the same scheme: each mode evolves as
+    cos(n Omega) with sin^2(Omega/2) = 2a (sin^2(kx/2) + sin^2(ky/2))."""
+    ny, nx = r0.shape
+    kx = 2 * np.pi * np.fft.fftfreq(nx)
+    ky = 2 * np.pi * np.fft.fftfreq(ny)
+    s = 2 * a * (np.sin(ky[:, None] / 2) ** 2 + np.sin(kx[None, :] / 2) ** 2)
+    omega = 2 * np.arcsin(np.sqrt(np.clip(s, 0, 1)))
+    return np.real(np.fft.ifft2(np.fft.fft2(r0) * np.cos(n * omega)))
+
+
+def periodic_plate(n, a0_phi=0.0, nu=0.3, e0=None, w0=None, u0=None, v0=None, sync=0, dh=1.0):
+    lam = I.lame_lambda(nu)
+    dt = I.time_step(nu, a0_phi) * dh
+    return OraclePlate(n, n, periodic=(True, True), lam=lam, mu=1.0, rho=1.0, dh=dh, dt=dt,
+                       sync_every=sync, u0=u0, v0=v0, e0=e0, w0=w0)
+
+
+# ---------------------------------------------------------------- parameters
+
+def test_parameters_follow_the_paper():
+    nu = 0.3
+    lam = I.lame_lambda(nu)
+    dt = 0.1
+    p = OraclePlate(8, 8, periodic=(True, True), lam=lam, mu=1.0, rho=2.0, dh=0.5, dt=dt)
+    q = p.params()
+    cd = np.sqrt((lam + 2.0) / 2.0)
+    cs = np.sqrt(1.0 / 2.0)  # shear speed from mu (lambda in the printed formula is a typo)
+    assert q["c_d"] == pytest.approx(cd, rel=1e-15)
+    assert q["c_s"] == pytest.approx(cs, rel=1e-15)
+    assert q["c"] == pytest.approx(0.5 / dt, rel=1e-15)
+    # c_{s|d} = (dh/dt) sqrt(2 a): the wave-speed relation of Sec. 3
+    assert (0.5 / dt) * np.sqrt(2 * q["a_phi"]) == pytest.approx(cd, rel=1e-14)
+    assert (0.5 / dt) * np.sqrt(2 * q["a_psi"]) == pytest.approx(cs, rel=1e-14)
+    # a0 + 4a = 1 and a_psi = (cs/cd)^2 a_phi (eq. conditions-parameters)
+    assert q["a0_phi"] + 4 * q["a_phi"] == pytest.approx(1.0, abs=1e-15)
+    assert q["a0_psi"] + 4 * q["a_psi"] == pytest.approx(1.0, abs=1e-15)
+    assert q["a_psi"] == pytest.approx((cs / cd) ** 2 * q["a_phi"], rel=1e-14)
+
+
+def test_time_step_beyond_stability_is_rejected():
+    nu = 0.3
+    dt = I.time_step(nu, 0.0) * 1.01  # a0_phi < 0
+    with pytest.raises(OracleError) as ei:
+        OraclePlate(8, 8, periodic=(True, True), lam=I.lame_lambda(nu), dt=dt)
+    assert ei.value.code == -2
+    # exactly at the limit is accepted
+    OraclePlate(8, 8, periodic=(True, True), lam=I.lame_lambda(nu), dt=I.time_step(nu, 0.0))
+
+
+def test_thin_masks_and_bad_bc_are_rejected():
+    m = np.ones((8, 8), np.uint8)
+    m[:, 3] = 0
+    m[:, 5] = 0  # column 4 is a one-node strip: no neighbour on either side in x
+    with pytest.raises(OracleError):
+        OraclePlate(8, 8, mask=m, dt=0.1)
+    p = OraclePlate(8, 8, dt=0.1)
+    with pytest.raises(OracleError):  # (3, 3) is an interior node
+        p.set_bc([[3, 3]], [1], [[0.0, 0.0]])
+    p.set_bc([[0, 3]], [1], [[0.0, 0.0]])
+    p.step(1)
+    with pytest.raises(OracleError) as ei:
+        p.set_bc([[0, 4]], [1], [[0.0, 0.0]])
+    assert ei.value.code == -6
+
+
+# ----------------------------------------------------------- interior LBM
+
+@pytest.mark.parametrize("a0_phi", [0.0, 0.5, 0.9999])
+def test_interior_lbm_equals_leapfrog_16x16(a0_phi):
+    """Both fields equal the brute-force 5-point leapfrog wave solve."""
+    rng = np.random.default_rng(11)
+    e0 = rng.standard_normal((16, 16))
+    w0 = rng.standard_normal((16, 16))
+    p = periodic_plate(16, a0_phi, e0=e0, w0=w0)
+    q = p.params()
+    p.step(400)
+    f = p.fields()
+    assert np.abs(f["e"] - leapfrog(e0, q["a_phi"], 400)).max() < 1e-12
+    assert np.abs(f["omega"] - leapfrog(w0, q["a_psi"], 400)).max() < 1e-12
+
+
+def test_standing_wave_is_exact_at_the_stability_limit():
+    """At a = 1/4 the diagonal mode sin(kx) sin(ky) advances as cos(n k):
+    the continuum solution of the dilatational wave equation at the nodes."""
+    case = I.periodic_square()
+    f, _ = run_case(case)
+    n = 64
+    y, x = np.mgrid[0:n, 0:n]
+    k = 2 * np.pi / n
+    exact = np.sin(k * x) * np.sin(k * y) * np.cos(case.steps * k)
+    assert np.abs(f["e"] - exact).max() < 1e-13
+
+
+@pytest.mark.parametrize("a0_phi", [0.0, 0.9999])
+def test_fourier_closed_form_both_fields(a0_phi):
+    case = I.periodic_square(a0_phi=a0_phi, steps=300)
+    f, p = run_case(case)
+    q = p.params()
+    ref_e = fourier_solution(case.e0, q["a_phi"], case.steps)
+    ref_w = fourier_solution(case.w0, q["a_psi"], case.steps)
+    assert np.abs(f["e"] - ref_e).max() < 1e-12 * np.abs(case.e0).max()
+    assert np.abs(f["omega"] - ref_w).max() < 1e-12 * np.abs(case.w0).max() * 10
+
+
+def test_zeroth_and_first_moment_conserved_on_periodic_domain():
+    rng = np.random.default_rng(5)
+    p = periodic_plate(24, 0.3)
+    fpop = rng.standard_normal((2, 5, 24, 24))
+    p.set_pops(fpop)
+    c = p.params()["c"]
+
+    def totals(f):
+        rho = f.sum(axis=1).sum(axis=(1, 2))
+        jx = (c * (f[:, 1] - f[:, 3])).sum(axis=(1, 2))
+        jy = (c * (f[:, 2] - f[:, 4])).sum(axis=(1, 2))
+        return rho, jx, jy
+
+    r0, jx0, jy0 = totals(fpop)
+    p.step(200)
+    r1, jx1, jy1 = totals(p.pops())
+    np.testing.assert_allclose(r1, r0, atol=1e-11)
+    np.testing.assert_allclose(jx1, jx0, atol=1e-10)
+    np.testing.assert_allclose(jy1, jy0, atol=1e-10)
+
+
+def test_populations_move_along_their_lattice_velocity():
+    """Integrated continuity equation of the LBE: the centroid of the field
+    advances by dt * (total flux) per step (post-collision populations at x
+    reach x + c^alpha dt, Sec. 3, eq. LBE)."""
+    rng = np.random.default_rng(8)
+    n = 20
+    fpop = np.zeros((2, 5, n, n))
+    fpop[:, :, 6:14, 6:14] = rng.uniform(0, 1, (2, 5, 8, 8))
+    p = periodic_plate(n, 0.4)
+    p.set_pops(fpop)
+    q = p.params()
+    c, dt = q["c"], 1.0 / q["c"]  # dh = 1
+    y, x = np.mgrid[0:n, 0:n].astype(float)
+    for fl in range(2):
+        rho0 = fpop[fl].sum(axis=0)
+        jx = (c * (fpop[fl, 1] - fpop[fl, 3])).sum()
+        jy = (c * (fpop[fl, 2] - fpop[fl, 4])).sum()
+        if fl == 0:
+            p.step(1)
+            f1 = p.pops()
+        rho1 = f1[fl].sum(axis=0)
+        assert (x * rho1).sum() - (x * rho0).sum() == pytest.approx(dt * jx, abs=1e-12)
+        assert (y * rho1).sum() - (y * rho0).sum() == pytest.approx(dt * jy, abs=1e-12)
+
+
+def test_second_order_convergence_under_refinement():
+    """Periodic unit square, off-diagonal mode, a0_phi = 0.5: the error of e
+    against the continuum standing wave falls 4x per halving of dh."""
+    errs = []
+    for n in (32, 64, 128):
+        dh = 1.0 / n
+        y, x = (np.mgrid[0:n, 0:n] * dh)
+        e0 = np.sin(2 * np.pi * x) * np.sin(4 * np.pi * y)
+        p = periodic_plate(n, a0_phi=0.5, e0=e0, w0=np.zeros_like(e0), dh=dh)
+        q = p.params()
+        dt = dh * np.sqrt(2 * q["a_phi"]) / q["c_d"]
+        T = 0.35
+        steps = int(round(T / dt))
+        p.step(steps)
+        kk = 2 * np.pi * np.sqrt(1 + 4)
+        exact = e0 * np.cos(q["c_d"] * kk * steps * dt)
+        errs.append(np.abs(p.fields()["e"] - exact).max())
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.5 < r1 < 4.6 and 3.5 < r2 < 4.6, errs
+
+
+# ------------------------------------------------- displacement recovery
+
+def test_displacement_equals_newmark_closed_form_sum():
+    """u_n = u_0 + n dt v_0 + dt^2 sum_j (n - j - 1/2) a_j with a_j from the
+    Fourier-exact fields through c_d^2 grad phi - c_s^2 curl(psi e_z)."""
+    n, nsteps = 32, 60
+    rng = np.random.default_rng(3)
+    y, x = np.mgrid[0:n, 0:n] * (2 * np.pi / n)
+    e0 = np.sin(x) * np.cos(2 * y) + 0.3 * np.cos(3 * x)
+    w0 = np.cos(x + y) + 0.2 * np.sin(2 * x)
+    u0 = rng.standard_normal((2, n, n)) * 1e-2
+    v0 = rng.standard_normal((2, n, n)) * 1e-2
+    p = periodic_plate(n, 0.2, e0=e0, w0=w0, u0=u0, v0=v0)
+    q = p.params()
+    p.step(nsteps)
+    dt = I.time_step(0.3, 0.2)
+
+    def grad(r):  # central differences, lattice spacing 1
+        return np.stack([(np.roll(r, -1, 1) - np.roll(r, 1, 1)) / 2,
+                         (np.roll(r, -1, 0) - np.roll(r, 1, 0)) / 2])
+
+    acc_sum = np.zeros((2, n, n))
+    for j in range(nsteps):
+        phi = fourier_solution(e0, q["a_phi"], j)
+        psi = fourier_solution(w0, q["a_psi"], j)
+        gphi, gpsi = grad(phi), grad(psi)
+        # curl of (0, 0, psi): the z-cross product of nabla with psi e_z
+        # nabla x (psi e_z) = (grad psi) x e_z
+        curl = np.cross(np.stack([gpsi[0], gpsi[1], np.zeros_like(psi)]), [0, 0, 1], axis=0)[:2]
+        acc = q["c_d"] ** 2 * gphi - q["c_s"] ** 2 * curl
+        acc_sum += (nsteps - j - 0.5) * acc
+    u_ref = u0 + nsteps * dt * v0 + dt * dt * acc_sum
+    assert np.abs(p.fields()["u"] - u_ref).max() < 1e-12
+
+
+# --------------------------------------------------------- boundary rules
+
+def _cell(mask, i, j):
+    """Mask-rule cell of boundary node (i, j): (wx, wy, flags)."""
+    ny, nx = mask.shape
+    has = lambda ii, jj: int(0 <= ii < nx and 0 <= jj < ny and mask[jj, ii] != 0)
+    E, W, N, S = has(i + 1, j), has(i - 1, j), has(i, j + 1), has(i, j - 1)
+    return 0.5 * (E + W), 0.5 * (N + S), (E, N, W, S)
+
+
+def _external_force(mask, sigma, i, j):
+    """Exact integral of sigma n over the cell sides lying on the body's
+    boundary (they pass through the node), for a stress that is linear in x
+    and y.  sigma(x, y) -> (sxx, syy, sxy)."""
+    wx, wy, (E, N, W, S) = _cell(mask, i, j)
+    F = np.zeros(2)
+    # vertical sides at x = i span y in [j - S/2, j + N/2]
+    ym = j + 0.25 * (N - S)
+    xm = i + 0.25 * (E - W)
+    for present, sgn in ((E, 1.0), (W, -1.0)):
+        if not present:
+            sxx, syy, sxy = sigma(i, ym)
+            F += sgn * np.array([sxx, sxy]) * wy
+    for present, sgn in ((N, 1.0), (S, -1.0)):
+        if not present:
+            sxx, syy, sxy = sigma(xm, j)
+            F += sgn * np.array([sxy, syy]) * wx
+    return F
+
+
+def _boundary_nodes(mask):
+    ny, nx = mask.shape
+    out = []
+    for j in range(ny):
+        for i in range(nx):
+            if not mask[j, i]:
+                continue
+            nb = [(i + 1, j), (i - 1, j), (i, j + 1), (i, j - 1)]
+            if any(not (0 <= a < nx and 0 <= b < ny and mask[b, a]) for a, b in nb):
+                out.append((i, j))
+    return np.array(out, np.int32)
+
+
+def _quadratic_case(lam, mu, alpha, beta, mask):
+    ny, nx = mask.shape
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    u0 = np.stack([alpha * x * x, beta * y * y]) * mask[None]
+
+    def sigma(xx, yy):  # Hooke's law of the exact strain of u0
+        exx, eyy = 2 * alpha * xx, 2 * beta * yy
+        return (lam * (exx + eyy) + 2 * mu * exx, lam * (exx + eyy) + 2 * mu * eyy, 0.0)
+
+    bn = _boundary_nodes(mask)
+    F = np.array([_external_force(mask, sigma, i, j) for i, j in bn])
+    return u0, bn, F
+
+
+@pytest.mark.parametrize("use_hole", [False, True])
+def test_neumann_rule_exact_for_quadratic_displacement(use_hole):
+    """For lambda = 0 and u = (alpha x^2, beta y^2) the finite differences
+    are exact, the stress is linear and the cell balance of eq. acc_neumann
+    with the exact external traction integral returns div(sigma)/rho exactly
+    at every boundary node -- the same value eq. navier gives inside."""
+    nx, ny = 14, 11
+    mask = np.ones((ny, nx), np.uint8)
+    if use_hole:
+        mask[4:7, 5:9] = 0
+    lam, mu, rho = 0.0, 1.3, 0.8
+    alpha, beta = 1e-3, -2e-3
+    u0, bn, F = _quadratic_case(lam, mu, alpha, beta, mask)
+    p = OraclePlate(nx, ny, mask=mask, lam=lam, mu=mu, rho=rho, dh=1.0, dt=0.05, u0=u0)
+    p.set_bc(bn, np.zeros(len(bn), np.uint8), F)
+    p.step(1)
+    acc = p.last_accel()
+    exact = np.array([4 * mu * alpha / rho, 4 * mu * beta / rho])
+    inb = mask.astype(bool)
+    assert np.abs(acc[0][inb] - exact[0]).max() < 1e-14
+    assert np.abs(acc[1][inb] - exact[1]).max() < 1e-14
+    # Newmark from rest: u(dt) = u0 + dt^2/2 * acc
+    u = p.fields()["u"]
+    ref = u0 + 0.5 * 0.05 ** 2 * exact[:, None, None] * mask[None]
+    assert np.abs(u - ref).max() < 1e-16 + 1e-13 * np.abs(u0).max()
+    # boundary reset: e = div u(dt) exactly (finite differences exact)
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    e = p.fields()["e"]
+    for i, j in bn:
+        assert abs(e[j, i] - (2 * alpha * i + 2 * beta * j)) < 1e-14
+
+
+def test_neumann_rule_with_lambda_on_edges():
+    """lambda != 0, u = (alpha x^2, 0): exact at every boundary node that is
+    not a corner (where the side midpoints leave the node row/column)."""
+    nx, ny = 12, 9
+    mask = np.ones((ny, nx), np.uint8)
+    lam, mu, rho, alpha = 1.5, 1.0, 1.0, 1e-3
+    u0, bn, F = _quadratic_case(lam, mu, alpha, 0.0, mask)
+    p = OraclePlate(nx, ny, mask=mask, lam=lam, mu=mu, rho=rho, dh=1.0, dt=0.05, u0=u0)
+    p.set_bc(bn, np.zeros(len(bn), np.uint8), F)
+    p.step(1)
+    acc = p.last_accel()
+    exact = np.array([(lam + 2 * mu) * 2 * alpha / rho, 0.0])
+    corners = {(0, 0), (nx - 1, 0), (0, ny - 1), (nx - 1, ny - 1)}
+    for j in range(ny):
+        for i in range(nx):
+            if (i, j) in corners:
+                continue
+            assert abs(acc[0, j, i] - exact[0]) < 1e-14
+            assert abs(acc[1, j, i] - exact[1]) < 1e-14
+
+
+def _patch_run(u0, mask, lam=1.5, mu=1.0, F=None, steps=60, sync=0):
+    ny, nx = mask.shape
+    dt = I.time_step(0.3, 0.9999)  # the paper's stable equilibrium weight (Sec. 4)
+    p = OraclePlate(nx, ny, mask=mask, lam=lam, mu=mu, rho=1.0, dh=1.0, dt=dt, sync_every=sync,
+                    u0=u0)
+    if F is not None:
+        bn = _boundary_nodes(mask)
+        p.set_bc(bn, np.zeros(len(bn), np.uint8), F)
+    p.step(steps)
+    return p.fields()
+
+
+def _holed_mask(nx=20, ny=16):
+    m = I.hole_mask(max(nx, ny), 3.2, cx=9.3, cy=7.6)[:ny, :nx].copy()
+    return m
+
+
+def test_patch_uniform_strain_stays_static():
+    """Uniform strain with the matching traction on every free side is an
+    exact static solution (eq. acc_neumann has sum n l = 0 and the
+    differences are exact for linear u)."""
+    mask = _holed_mask()
+    ny, nx = mask.shape
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    E = np.array([[2e-3, 0.5e-3], [0.7e-3, -1e-3]])  # displacement gradient
+    u0 = np.stack([E[0, 0] * x + E[0, 1] * y, E[1, 0] * x + E[1, 1] * y]) * mask[None]
+    lam, mu = 1.5, 1.0
+    eps = 0.5 * (E + E.T)
+    sig = lam * np.trace(eps) * np.eye(2) + 2 * mu * eps
+    sigma = lambda xx, yy: (sig[0, 0], sig[1, 1], sig[0, 1])
+    bn = _boundary_nodes(mask)
+    F = np.array([_external_force(mask, sigma, i, j) for i, j in bn])
+    f = _patch_run(u0, mask, lam, mu, F, sync=17)
+    tol = 1e-14 * np.abs(u0).max()
+    assert np.abs(f["u"] - u0).max() < tol
+    assert np.abs(f["v"]).max() < tol
+    inb = mask.astype(bool)
+    assert np.abs(f["e"][inb] - np.trace(E)).max() < 1e-15
+    assert np.abs(f["omega"][inb] - (E[1, 0] - E[0, 1])).max() < 1e-15
+
+
+@pytest.mark.parametrize("kind", ["translation", "rotation"])
+def test_patch_rigid_motion_stays_static(kind):
+    mask = _holed_mask()
+    ny, nx = mask.shape
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    if kind == "translation":
+        u0 = np.stack([np.full_like(x, 3e-3), np.full_like(x, -1e-3)])
+    else:
+        th = 1e-3
+        u0 = th * np.stack([-(y - 7), x - 9])
+    u0 = u0 * mask[None]
+    f = _patch_run(u0, mask, sync=13)
+    tol = 1e-14 * np.abs(u0).max()
+    assert np.abs(f["u"] - u0).max() < tol
+    assert np.abs(f["v"]).max() < tol
+
+
+def test_mirror_symmetry_of_a_symmetric_load():
+    """Mirror-symmetric mask, boundary data and load: u_x odd, u_y even,
+    e even, omega odd under x -> nx-1-x."""
+    n = 40
+    mask = I.hole_mask(n, 6.0)
+    y, x = np.mgrid[0:n, 0:n].astype(float)
+    cx = (n - 1) / 2
+    g = 1e-3 * np.exp(-((x - cx) ** 2 + (y - 27.0) ** 2) / (2 * 3.0 ** 2))
+    u0 = np.stack([(x - cx) * g / 3.0, g]) * mask[None]
+    nu = 0.3
+    p = OraclePlate(n, n, mask=mask, lam=I.lame_lambda(nu), dt=I.time_step(nu, 0.99),
+                    sync_every=20, u0=u0)
+    bc = I.dirichlet_edges_bc(n, n, [I.LEFT, I.RIGHT, I.BOTTOM])
+    p.set_bc(bc.xy, bc.kind, bc.val)
+    p.step(150)
+    f = p.fields()
+    scale = np.abs(f["u"]).max()
+    assert scale > 1e-6
+    assert np.abs(f["u"][0] + f["u"][0][:, ::-1]).max() <= 1e-15 * scale
+    assert np.abs(f["u"][1] - f["u"][1][:, ::-1]).max() <= 1e-15 * scale
+    assert np.abs(f["e"] - f["e"][:, ::-1]).max() <= 1e-15 * np.abs(f["e"]).max()
+    assert np.abs(f["omega"] + f["omega"][:, ::-1]).max() <= 1e-15 * np.abs(f["omega"]).max()
+
+
+def test_dirichlet_nodes_follow_prescribed_displacement():
+    n = 24
+    nu = 0.3
+    dt = I.time_step(nu, 0.99)
+    p = OraclePlate(n, n, lam=I.lame_lambda(nu), dt=dt, sync_every=10)
+    bc = I.dirichlet_edges_bc(n, n, [I.LEFT])
+    ustar = np.tile([2e-3, -1e-3], (len(bc.xy), 1))
+    knots = np.array([[0.0, 0.0], [30 * dt, 1.0]])  # ramp, then held
+    p.set_bc(bc.xy, bc.kind, ustar, knots=knots)
+    for s in range(1, 61):
+        p.step(1)
+        u = p.fields()["u"]
+        g = min(s * dt / (30 * dt), 1.0)
+        got = u[:, bc.xy[:, 1], bc.xy[:, 0]].T
+        assert np.abs(got - g * ustar).max() < 8 * np.finfo(float).eps * 2e-3
+
+
+def test_synchronization_restores_consistency_and_keeps_flux():
+    case = I.clamped_plate(n=32, sigma=3.0, steps=0, a0_phi=0.99)
+
+    def make(sync):
+        p = OraclePlate(case.nx, case.ny, lam=case.lam, dt=case.dt, sync_every=sync, u0=case.u0)
+        for bc in case.bcs:
+            p.set_bc(bc.xy, bc.kind, bc.val)
+        return p
+
+    a, b = make(10), make(0)
+    a.step(10)
+    b.step(10)
+    assert b.cons_err().max() > 1e-9
+    scale = np.abs(a.fields()["e"]).max()
+    assert a.cons_err().max() < 1e-15 * max(scale, 1e-3) * 10
+    c = a.params()["c"]
+    fa, fb = a.pops(), b.pops()
+    jxa, jxb = c * (fa[:, 1] - fa[:, 3]), c * (fb[:, 1] - fb[:, 3])
+    jya, jyb = c * (fa[:, 2] - fa[:, 4]), c * (fb[:, 2] - fb[:, 4])
+    assert np.abs(jxa - jxb).max() < 1e-17 + 1e-13 * np.abs(jxb).max()
+    assert np.abs(jya - jyb).max() < 1e-17 + 1e-13 * np.abs(jyb).max()
+
+
+def test_planted_boundary_corruption_is_removed_by_the_next_sync():
+    """Failure handling of Sec. 3.2: a corrupted boundary population raises
+    the consistency error; the next synchronization brings it back to 0."""
+    case = I.clamped_plate(n=32, sigma=3.0, steps=0, a0_phi=0.99)
+    p = OraclePlate(case.nx, case.ny, lam=case.lam, dt=case.dt, sync_every=10, u0=case.u0)
+    for bc in case.bcs:
+        p.set_bc(bc.xy, bc.kind, bc.val)
+    p.step(3)
+    f = p.pops()
+    f[0, 2, 0, 5] += 1e-4  # planted on the CPU, in the oracle
+    p.set_pops(f)
+    assert p.cons_err().max() > 5e-5
+    p.step(7)
+    assert p.cons_err().max() < 1e-15
+
+
+def test_bounded_plate_needs_the_papers_small_time_step():
+    """Sec. 4 needed a0_phi = 0.9999 for stability; at the lattice stability
+    limit the bounded scheme (first-order velocity update at the Neumann
+    nodes) blows up, while 0.9999 stays bounded."""
+    for a0, ok in ((0.0, False), (0.9999, True)):
+        case = I.clamped_plate(n=48, sigma=4.0, a0_phi=a0, steps=600)
+        f, _ = run_case(case)
+        bounded = np.isfinite(f["u"]).all() and np.abs(f["u"]).max() < 1e-2
+        assert bounded == ok, a0
