@@ -1,0 +1,183 @@
+"""Throughput benchmark of the plane-strain LBM hot path on one MI355X.
+
+One "step" is one time step of the whole method (interior stream+collide
+with the u recovery, boundary reset and accelerations, second-row rule,
+synchronization every 50th step) on the workload below, with the state
+resident in HBM.  Prints ONE JSON line.
+
+Workload (FP64, the headline value): 1024 x 1024 plate, left edge clamped
+(u* = 0), other edges traction free, nu = 0.3, a0_phi = 0.9999, one seeded
+Gaussian displacement pulse (sigma 16, amplitude 1e-3), synchronization
+every 50 steps.  The same workload is also timed with the FP32 and the
+reduced (deviation) storages, each with its relative L2 error against the
+FP64 run after the same number of steps.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "GLUPS + % HBM roofline, FP64 vs FP16/FP32-storage at ≤1e-3 rel L2"
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("lbm_kernels.hip", "lbm_types.h"):
+        with open(os.path.join(ROOT, "paper_2301_00228_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(storage, nodes):
+    """HBM bytes per interior-kernel launch from the committed rocprofv3 PMC
+    summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"interior_{storage}_clamped1024_traffic.json")
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def rel_l2(a, b):
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+def cpu_baseline(case, budget_s=12.0):
+    """Time the FP64 oracle on a bounded sample of the same workload."""
+    from oracle import oracle
+
+    p = oracle.OraclePlate(case.nx, case.ny, mask=case.mask, periodic=case.periodic,
+                           lam=case.lam, mu=case.mu, rho=case.rho, dh=case.dh, dt=case.dt,
+                           sync_every=case.sync_every, u0=case.u0, v0=case.v0)
+    for bc in case.bcs:
+        p.set_bc(bc.xy, bc.kind, bc.val, cell=bc.cell, knots=bc.knots)
+    t0 = time.perf_counter()
+    p.step(5)
+    probe = time.perf_counter() - t0
+    steps = max(5, int(budget_s / max(probe / 5, 1e-6)))
+    t0 = time.perf_counter()
+    p.step(steps)
+    dt = time.perf_counter() - t0
+    nodes = case.in_body_nodes()
+    return {"value": nodes * steps / dt / 1e9, "unit": "GLUPS", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"{case.nx}x{case.ny} plate of the same workload, {steps} steps "
+                      f"(steps 6..{steps + 5}), {dt:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=200)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(plates shard across GPUs with no communication; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2301_00228_amd import inputs, lbm
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    case = inputs.clamped_plate(n=1024, steps=args.steps)
+    nodes = case.in_body_nodes()
+    K, W = args.steps, args.warmup
+
+    def timed_run(storage):
+        ctx = lbm.context_for(case, storage)
+        ctx.step(W)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.step(K)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        return ctx, dt
+
+    ctx, dt = timed_run("f64")
+    ms_per_step = dt / K * 1e3
+    glups = nodes * K / dt / 1e9
+    info = ctx.info()
+    f64_fields = ctx.fields(0)
+    # Dominant kernel (interior stream+collide): device time per launch from
+    # HIP events on the library's stream, eager launches.
+    prof = ctx.profile(args.profile_steps)
+    int_ms, int_n = prof["interior"]
+    bnd_ms, bnd_n = prof["boundary"]
+    per_launch_s = int_ms / int_n / 1e3
+    bpu = info["bytes_per_update"]
+    achieved = nodes * bpu / per_launch_s / 1e9
+    traffic = measured_traffic("f64", nodes)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic,
+                "kernel": "k_interior<f64>", "bytes_per_lup": bpu,
+                "lups_per_launch": nodes, "avg_launch_us": round(per_launch_s * 1e6, 2),
+                "boundary_kernel_avg_us": round(bnd_ms / max(bnd_n, 1) * 1e3, 2)}
+    ctx.close()
+
+    variants = {}
+    if not args.no_variants:
+        ref_u = f64_fields["u"]
+        for st in ("f32", "f32dev", "f16dev", "bf16dev"):
+            c2, d2 = timed_run(st)
+            fl = c2.fields(0)
+            pr = c2.profile(min(args.profile_steps, 100))
+            i_ms, i_n = pr["interior"]
+            bpu2 = c2.info()["bytes_per_update"]
+            ach2 = nodes * bpu2 / (i_ms / i_n / 1e3) / 1e9
+            c2.close()
+            variants[st] = {
+                "glups": round(nodes * K / d2 / 1e9, 3),
+                "ms_per_step": round(d2 / K * 1e3, 4),
+                "speedup_vs_f64": round(dt / d2, 3),
+                "interior_GBs": round(ach2, 1), "interior_frac": round(ach2 / HBM_PEAK_GBS, 4),
+                "bytes_per_lup": bpu2,
+                "rel_l2_vs_f64": {"e": rel_l2(fl["e"], f64_fields["e"]),
+                                  "omega": rel_l2(fl["omega"], f64_fields["omega"]),
+                                  "u": rel_l2(fl["u"], ref_u)},
+            }
+        del ref_u
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(case)
+
+    line = {
+        "metric": METRIC, "value": round(glups, 4), "unit": "GLUPS", "n_gpus": 1, "steps": K,
+        "warmup": W, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "clamped plate 1024x1024 (left edge u*=0, other edges traction "
+                               "free), nu 0.3, a0_phi 0.9999, Gaussian pulse sigma 16 amp 1e-3, "
+                               "sync every 50, FP64 populations and u",
+                   "nodes": nodes, "storage": "f64", "tile": [info["tile_lanes"],
+                                                              info["tile_rows"]],
+                   "graphs": True},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "variants": variants,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,212 @@
+/*
+ * lbm.h -- C ABI of the MI355X plane-strain lattice Boltzmann library.
+ *
+ * The library advances the method of Schlueter, Yan, Faust, Mueller and
+ * Mueller, "A Lattice Boltzmann Method for Elastic Solids Under Plane Strain
+ * Deformation" (arXiv 2301.00228): per time step, two D2Q5 wave-equation
+ * LBMs (dilatation phi = div u with speed c_d, rotation psi = (curl u).e_z
+ * with speed c_s; Sec. 2, eq. wave-eqs; Sec. 3), the Dirichlet and Neumann
+ * boundary rules of Sec. 3.1, the periodic synchronization of Sec. 3.2, and
+ * the recovery of the displacement u by the explicit Newmark update of
+ * eq. integration.  Many independent plates advance together.
+ *
+ * Conventions for every entry point:
+ *  - every call returns lbm_status: LBM_OK (0) or a negative error code;
+ *    nothing throws, aborts or prints; lbm_last_error() describes the last
+ *    failure of a context;
+ *  - arrays are row-major with x fastest: node (i, j) of an nx-by-ny plate
+ *    is element j*nx + i; vector fields are planar [2][ny][nx] (x component
+ *    first);
+ *  - unless an entry point says "device", pointers are host pointers; the
+ *    library copies inputs before returning and the caller keeps ownership
+ *    of everything it passes;
+ *  - units are the caller's; dh is the lattice spacing, dt the time step;
+ *  - a context must not be used from two threads at once.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_E_INVAL = -1,        /* invalid argument (sizes, mask, node lists, ...)          */
+  LBM_E_UNSTABLE_DT = -2,  /* dt gives a_{0,phi} < 0 (Sec. 3, eq. feq_req)              */
+  LBM_E_NOMEM = -3,        /* host or device allocation failed                          */
+  LBM_E_DEVICE = -4,       /* no usable GPU, or a HIP call failed                       */
+  LBM_E_NONFINITE = -5,    /* a non-finite or blown-up displacement was detected       */
+  LBM_E_STATE = -6         /* call not allowed in the current state                     */
+} lbm_status;
+
+/* Storage of the populations (Sec. 3, eq. LBE) in device memory.
+ *  F64     : 5+5 populations in FP64, FP64 arithmetic, u and du/dt in FP64.
+ *  F32     : 5+5 populations in FP32, FP32 arithmetic, u and du/dt in FP32.
+ *  F32DEV  : per field, the zeroth moment rho and flux J in FP32 and the two
+ *            remaining moments of the deviation f - f_eq(rho, J = 0) from the
+ *            local rest equilibrium (N = f1 + f3 - f2 - f4 and
+ *            Q - 4 a rho with Q = f1 + f2 + f3 + f4) in FP32;
+ *  F16DEV  : as F32DEV with the two deviation moments in IEEE FP16 (scaled
+ *            by a per-plate, per-field power of two);
+ *  BF16DEV : as F16DEV with bfloat16.
+ * The DEV variants collide in FP32 and keep u, du/dt and all boundary
+ * arithmetic in FP64.  The update itself is the same for every storage. */
+typedef enum {
+  LBM_STORE_F64 = 0,
+  LBM_STORE_F32 = 1,
+  LBM_STORE_F32DEV = 2,
+  LBM_STORE_F16DEV = 3,
+  LBM_STORE_BF16DEV = 4
+} lbm_storage;
+
+/* Boundary condition kinds for lbm_set_bc (Sec. 2: u = u* on the Dirichlet
+ * part, sigma n = t* on the Neumann part). */
+enum { LBM_BC_NEUMANN = 0, LBM_BC_DIRICHLET = 1 };
+
+/* One plate: the body B of Sec. 2 on a regular lattice (Sec. 3, Fig. 2). */
+typedef struct {
+  int32_t nx, ny;            /* lattice size, each >= 3                                  */
+  const uint8_t *mask;       /* nx*ny bytes, nonzero = node belongs to the body; NULL =
+                                the full rectangle.  Every body node needs a body
+                                neighbour on at least one side along each axis.          */
+  uint8_t periodic_x;        /* nonzero: the x axis wraps around                          */
+  uint8_t periodic_y;        /* nonzero: the y axis wraps around                          */
+  double lambda, mu, rho_m;  /* Lame parameters and mass density (Sec. 2, eq. hooke)
+                                c_d = sqrt((lambda + 2 mu)/rho_m), c_s = sqrt(mu/rho_m)   */
+  double dh, dt;             /* lattice spacing and time step; the equilibrium weights
+                                follow from a = (c dt/dh)^2 / 2 for each field
+                                (Sec. 3, eqs. parameters_to_wavespeed_relation,
+                                conditions-parameters); dt must keep a_{0,phi} =
+                                1 - 4 a_phi >= 0, i.e. dt <= dh / (sqrt(2) c_d)           */
+  int32_t sync_every;        /* l of Sec. 3.2: synchronize after every l-th step; 0 = off.
+                                All plates of one context must use the same value.        */
+  const double *u0, *v0;     /* initial displacement and velocity, planar [2][ny][nx];
+                                NULL = 0                                                   */
+  const double *e0, *w0;     /* optional initial dilatation / rotation (nx*ny); NULL =
+                                finite differences of u0 (Sec. 3, Fig. 4)                 */
+} lbm_plate;
+
+/* Optional device allocator (e.g. a framework's caching allocator).  alloc
+ * returns device memory of at least `bytes` bytes or NULL; free releases it.
+ * Both are called only from lbm_create / lbm_destroy. */
+typedef struct {
+  void *(*alloc)(size_t bytes, void *user);
+  void (*free)(void *ptr, void *user);
+  void *user;
+} lbm_alloc;
+
+/* Create a context for n_plates plates with the given population storage.
+ * hip_stream: the hipStream_t every device operation is ordered on (NULL =
+ * the null stream).  alloc: NULL = hipMalloc/hipFree.  Classifies every
+ * node (interior, boundary, second row; Sec. 3.1, Fig. 5), builds the
+ * boundary cells with the mask rule (the cell spans half a spacing towards
+ * each body neighbour and ends at the node towards a missing one), uploads
+ * the initial state and sets the populations to f_eq(field, J = 0).  All
+ * boundary nodes start traction-free Neumann.
+ * Errors: LBM_E_INVAL (sizes, mask with a node lacking both neighbours along
+ * an axis, mixed sync_every), LBM_E_UNSTABLE_DT, LBM_E_NOMEM, LBM_E_DEVICE
+ * (no GPU or HIP failure).  On error *out is NULL. */
+lbm_status lbm_create(const lbm_plate *plates, int32_t n_plates, lbm_storage storage,
+                      void *hip_stream, const lbm_alloc *alloc, lbm_ctx **out);
+
+/* Boundary data of n boundary nodes of one plate (Sec. 3.1).
+ * xy   : 2n node coordinates (i, j); each must be a boundary node (a body node
+ *        with at least one missing D2Q5 neighbour), else LBM_E_INVAL.
+ * kind : n bytes, LBM_BC_NEUMANN or LBM_BC_DIRICHLET.  Where a Dirichlet and a
+ *        Neumann edge meet, list the corner as Dirichlet.
+ * val  : 2n values.  Dirichlet: the prescribed displacement u* (eq.
+ *        acc_dirichlet, applied so that u(t+dt) = u*(t+dt)).  Neumann: the
+ *        external force integral of t* over the cell's external boundary
+ *        (eq. acc_neumann), per unit thickness.
+ * cell : NULL, or 5n values (V_C, l_E, l_N, l_W, l_S) replacing the mask-rule
+ *        cell volume and the lengths of the internal sides towards the E, N,
+ *        W, S neighbours (for boundaries that do not follow the lattice).
+ * knots: n_knots (t, g) pairs of a piecewise linear amplitude g(t) (clamped
+ *        outside the knot range, times strictly increasing) multiplying val;
+ *        NULL (n_knots = 0) means g = 1.  Neumann loads are taken at t = n dt,
+ *        Dirichlet values at t = (n+1) dt during step n.
+ * Later calls override earlier ones node by node.  At most 16 amplitude
+ * tables of at most 64 knots per plate.  Only allowed before the first
+ * lbm_step (else LBM_E_STATE). */
+lbm_status lbm_set_bc(lbm_ctx *ctx, int32_t plate, int32_t n, const int32_t *xy,
+                      const uint8_t *kind, const double *val, const double *cell,
+                      int32_t n_knots, const double *knots);
+
+/* Advance every plate by n_steps time steps (Fig. 4: accelerations,
+ * Newmark update, boundary reset, LBE with the second-row rule, and the
+ * synchronization after every l-th step).  Stream-ordered and asynchronous:
+ * returns once the work is enqueued.  A blow-up detected by earlier work is
+ * reported as LBM_E_NONFINITE by this or the next synchronizing call. */
+lbm_status lbm_step(lbm_ctx *ctx, int64_t n_steps);
+
+/* Copy one plate's state to host buffers (any may be NULL): e = sum of the
+ * dilatation populations, omega = sum of the rotation populations (eq.
+ * interpretation), each nx*ny; u, v = displacement and velocity, planar
+ * 2*nx*ny.  Nodes outside the body read 0.  Synchronizes the stream.
+ * Returns LBM_E_NONFINITE if a blow-up was detected. */
+lbm_status lbm_fields(lbm_ctx *ctx, int32_t plate, double *e, double *omega, double *u,
+                      double *v);
+
+/* As lbm_fields, but the outputs are device pointers (FP64, same layout),
+ * written in stream order without synchronizing. */
+lbm_status lbm_fields_device(lbm_ctx *ctx, int32_t plate, double *e, double *omega, double *u,
+                             double *v);
+
+/* Summary of a context.  Filled by lbm_info. */
+typedef struct {
+  int64_t nodes_in_body;      /* body nodes over all plates (lattice updates per step)       */
+  int64_t nodes_allocated;    /* nodes stored, including row padding                        */
+  int64_t boundary_nodes;     /* nodes with a missing neighbour                             */
+  int64_t second_row_nodes;   /* interior nodes with a boundary neighbour                   */
+  int64_t steps_done;
+  int64_t device_bytes;       /* device memory held                                         */
+  double bytes_per_update;    /* algorithmic HBM bytes per body node and step (read+write) */
+  int32_t n_plates;
+  int32_t storage;
+  int32_t tile_lanes, tile_rows; /* interior-kernel tile: lanes per workgroup, rows        */
+  int32_t n_tiles;
+} lbm_info_t;
+lbm_status lbm_info(const lbm_ctx *ctx, lbm_info_t *info);
+
+/* Interior-kernel tile shape: lanes per workgroup (64, 128 or 256; the tile
+ * owns lanes-2 columns) and rows per tile (>= 1).  May be changed between
+ * steps; invalidates captured step graphs. */
+lbm_status lbm_set_tiling(lbm_ctx *ctx, int32_t lanes, int32_t rows);
+
+/* Time every tile shape in a small candidate set on this context's plates
+ * (each candidate runs `steps` steps after one warm-up step on a copy of the
+ * state, which is restored afterwards) and keep the fastest.  Results are
+ * cached per (storage, plate-size bucket) for the life of the process.
+ * best_ms (nullable) receives the fastest time per step. */
+lbm_status lbm_autotune(lbm_ctx *ctx, int32_t steps, double *best_ms);
+
+/* Run n_steps steps eagerly (no graph), with a HIP event recorded on the
+ * context's stream before and after every kernel launch, and return the
+ * summed device time per kernel kind in ms: ms[0] interior stream+collide,
+ * ms[1] boundary/second-row, ms[2] synchronization, ms[3] all other; and
+ * the number of launches of each kind in launches[0..3] (nullable).
+ * Synchronizes the stream. */
+lbm_status lbm_profile(lbm_ctx *ctx, int64_t n_steps, double *ms, int64_t *launches);
+
+/* Use (nonzero) or bypass (0) captured HIP graphs in lbm_step.  Default on. */
+lbm_status lbm_use_graphs(lbm_ctx *ctx, int32_t enable);
+
+void lbm_destroy(lbm_ctx *ctx);
+
+/* Text of the last error of ctx (or of the last failed lbm_create when ctx is
+ * NULL).  The pointer stays valid until the next call on ctx. */
+const char *lbm_last_error(const lbm_ctx *ctx);
+
+/* Library version string. */
+const char *lbm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -43,6 +43,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define NQ 5
 /* D2Q5 lattice directions in units of c (Sec. 3, lattice velocities). */
@@ -591,3 +594,11 @@ void orc_params(const orc_plate *p, double *o) {
 }
 
 int64_t orc_step_count(const orc_plate *p) { return p->n; }
+
+int orc_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}

@@ -82,6 +82,9 @@ void orc_classes(const orc_plate *p, uint8_t *cls);
 void orc_params(const orc_plate *p, double *out7);
 
 int64_t orc_step_count(const orc_plate *p);
+
+/* Number of OpenMP threads the oracle's loops use. */
+int orc_threads(void);
 void orc_destroy(orc_plate *p);
 
 #ifdef __cplusplus

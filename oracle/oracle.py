@@ -50,6 +50,8 @@ def lib():
         L.orc_step_count.restype = C.c_int64
         L.orc_step_count.argtypes = [C.c_void_p]
         L.orc_destroy.argtypes = [C.c_void_p]
+        L.orc_threads.restype = C.c_int
+        L.orc_threads.argtypes = []
         _lib = L
     return _lib
 
@@ -154,6 +156,11 @@ class OraclePlate:
     @property
     def steps_done(self):
         return int(lib().orc_step_count(self._h))
+
+
+def threads():
+    """OpenMP threads used by the oracle's loops."""
+    return int(lib().orc_threads())
 
 
 def run_case(case, steps=None):

@@ -1,0 +1,940 @@
+// lbm_host.cpp -- host runtime and C ABI of the plane-strain LBM library.
+//
+// Preprocessing (Fig. 4 "Preprocessing"): node classification from the body
+// mask, boundary cells by the mask rule, second-row lists, interior tiles.
+// Runtime: device buffers, initial state, the time-step launch sequence,
+// captured HIP graphs of whole synchronization periods, tile autotuning,
+// per-kernel profiling with HIP events, blow-up detection.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "lbm_kernels.h"
+#include "lbm_types.h"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct PlateHost {
+  int nx = 0, ny = 0, pitch = 0;
+  int64_t off = 0;
+  bool px = false, py = false;
+  std::vector<uint8_t> cls;  // dense nx*ny copy of the class bytes
+  int64_t b0 = 0, b1 = 0;    // range in the boundary list
+  int nloads = 0;
+  int64_t body = 0;
+};
+
+struct Buffer {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+const char *storage_name(int st) {
+  switch (st) {
+    case LBM_STORE_F64: return "f64";
+    case LBM_STORE_F32: return "f32";
+    case LBM_STORE_F32DEV: return "f32dev";
+    case LBM_STORE_F16DEV: return "f16dev";
+    case LBM_STORE_BF16DEV: return "bf16dev";
+  }
+  return "?";
+}
+
+// Algorithmic HBM bytes per body node and step: populations read + written,
+// u and du/dt read + written.
+double bytes_per_update(int st) {
+  switch (st) {
+    case LBM_STORE_F64: return 2 * 10 * 8 + 2 * 4 * 8;   // 224
+    case LBM_STORE_F32: return 2 * 10 * 4 + 2 * 4 * 4;   // 112
+    case LBM_STORE_F32DEV: return 2 * 10 * 4 + 2 * 4 * 8; // 144
+    default: return 2 * 2 * (3 * 4 + 4) + 2 * 4 * 8;      // 128
+  }
+}
+
+int slot_count(int st) { return (st == LBM_STORE_F16DEV || st == LBM_STORE_BF16DEV) ? 4 : 5; }
+size_t slot_bytes(int st) {
+  return st == LBM_STORE_F64 ? 8 : 4;
+}
+size_t uv_bytes(int st) { return st == LBM_STORE_F32 ? 4 : 8; }
+
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int>, std::pair<int, int>> g_tune_cache;
+
+}  // namespace
+
+struct lbm_ctx {
+  int storage = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;
+  bool have_alloc = false;
+  lbm_alloc alloc{};
+  int device = 0;
+  std::string err;
+
+  std::vector<PlateHost> ph;
+  std::vector<PlateDev> pd;
+  int64_t n_alloc = 0;
+  int64_t n_body = 0;
+  int sync_every = 0;
+
+  std::vector<BndNode> bnd;
+  std::vector<SecNode> sec;
+  std::vector<LoadTable> loads;
+  std::vector<Tile> tiles;
+  int lanes = 128, rows = 32;
+
+  std::vector<Buffer> bufs;
+  DevState ds{};
+  PlateDev *d_plates = nullptr;
+  Tile *d_tiles = nullptr;
+  BndNode *d_bnd = nullptr;
+  SecNode *d_sec = nullptr;
+  LoadTable *d_loads = nullptr;
+  unsigned long long *d_counter = nullptr;
+  int *d_flag = nullptr;
+  uint8_t *d_cls = nullptr;
+  double *d_scratch = nullptr;
+  size_t scratch_bytes = 0;
+  size_t tiles_cap = 0;
+
+  int64_t step = 0;
+  bool started = false;
+  bool bnd_dirty = true;
+
+  bool use_graphs = true;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int64_t gsteps = 0;
+
+  int *h_flag = nullptr;
+  hipEvent_t flag_ev = nullptr;
+  bool flag_pending = false;
+  bool nonfinite = false;
+
+  int64_t device_bytes = 0;
+};
+
+namespace {
+
+lbm_status fail(lbm_ctx *c, lbm_status st, const std::string &msg) {
+  if (c)
+    c->err = msg;
+  else
+    g_create_error = msg;
+  return st;
+}
+
+lbm_status hip_fail(lbm_ctx *c, hipError_t e, const char *what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return fail(c, LBM_E_NOMEM, m);
+  return fail(c, LBM_E_DEVICE, m);
+}
+
+#define HIP_TRY(c, expr, what)                        \
+  do {                                                \
+    hipError_t _e = (expr);                           \
+    if (_e != hipSuccess) return hip_fail(c, _e, what); \
+  } while (0)
+
+void *dev_alloc(lbm_ctx *c, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  void *p = nullptr;
+  if (c->have_alloc) {
+    p = c->alloc.alloc(bytes, c->alloc.user);
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    p = nullptr;
+  }
+  if (p) {
+    c->bufs.push_back({p, bytes});
+    c->device_bytes += (int64_t)bytes;
+  }
+  return p;
+}
+
+void dev_free_all(lbm_ctx *c) {
+  for (auto &b : c->bufs) {
+    if (c->have_alloc)
+      c->alloc.free(b.p, c->alloc.user);
+    else
+      (void)hipFree(b.p);
+  }
+  c->bufs.clear();
+}
+
+void drop_graph(lbm_ctx *c) {
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->gexec = nullptr;
+  c->graph = nullptr;
+  c->gsteps = 0;
+}
+
+// Equilibrium weights and wave speeds (Sec. 2; Sec. 3, eqs. feq_req,
+// parameters_to_wavespeed_relation, conditions-parameters).
+lbm_status plate_params(const lbm_plate &p, PlateDev &d) {
+  if (!(p.dh > 0) || !(p.dt > 0) || !(p.rho_m > 0) || !(p.mu > 0) || !(p.lambda + 2.0 * p.mu > 0))
+    return LBM_E_INVAL;
+  const double cd = std::sqrt((p.lambda + 2.0 * p.mu) / p.rho_m);
+  const double cs = std::sqrt(p.mu / p.rho_m);
+  const double rd = cd * p.dt / p.dh, rs = cs * p.dt / p.dh;
+  d.a[0] = 0.5 * rd * rd;
+  d.a[1] = 0.5 * rs * rs;
+  d.a0[0] = 1.0 - 4.0 * d.a[0];
+  d.a0[1] = 1.0 - 4.0 * d.a[1];
+  if (d.a0[0] < -1e-12) return LBM_E_UNSTABLE_DT;
+  for (int f = 0; f < 2; f++) {
+    d.af[f] = (float)d.a[f];
+    d.a0f[f] = (float)d.a0[f];
+  }
+  d.cd2 = cd * cd;
+  d.cs2 = cs * cs;
+  d.dt = p.dt;
+  d.dh = p.dh;
+  d.rho_m = p.rho_m;
+  d.lam = p.lambda;
+  d.mu = p.mu;
+  return LBM_OK;
+}
+
+// Classification of one plate; fills the dense class bytes.  Returns false
+// for a body node without a body neighbour on either side along an axis.
+bool classify(const lbm_plate &p, PlateHost &h, std::string &why) {
+  const int nx = p.nx, ny = p.ny;
+  std::vector<uint8_t> in((size_t)nx * ny);
+  for (size_t k = 0; k < in.size(); k++) in[k] = p.mask ? (p.mask[k] != 0) : 1;
+  auto inb = [&](int i, int j) -> bool {
+    if (i < 0 || i >= nx) {
+      if (!p.periodic_x) return false;
+      i = (i + nx) % nx;
+    }
+    if (j < 0 || j >= ny) {
+      if (!p.periodic_y) return false;
+      j = (j + ny) % ny;
+    }
+    return in[(size_t)j * nx + i] != 0;
+  };
+  h.cls.assign((size_t)nx * ny, 0);
+  h.body = 0;
+  for (int j = 0; j < ny; j++)
+    for (int i = 0; i < nx; i++) {
+      const size_t k = (size_t)j * nx + i;
+      if (!in[k]) continue;
+      const bool E = inb(i + 1, j), N = inb(i, j + 1), W = inb(i - 1, j), S = inb(i, j - 1);
+      if ((!E && !W) || (!N && !S)) {
+        char buf[160];
+        snprintf(buf, sizeof buf,
+                 "node (%d, %d) has no body neighbour on either side along an axis", i, j);
+        why = buf;
+        return false;
+      }
+      uint8_t c = CL_IN | (E ? NB_E : 0) | (N ? NB_N : 0) | (W ? NB_W : 0) | (S ? NB_S : 0);
+      if ((c & NB_ALL) != NB_ALL) c |= CL_B;
+      h.cls[k] = c;
+      h.body++;
+    }
+  // second row: interior node with a boundary neighbour
+  for (int j = 0; j < ny; j++)
+    for (int i = 0; i < nx; i++) {
+      const size_t k = (size_t)j * nx + i;
+      const uint8_t c = h.cls[k];
+      if (!(c & CL_IN) || (c & CL_B)) continue;
+      const int di[4] = {1, 0, -1, 0}, dj[4] = {0, 1, 0, -1};
+      for (int d = 0; d < 4; d++) {
+        const int ii = (i + di[d] + nx) % nx, jj = (j + dj[d] + ny) % ny;
+        if (h.cls[(size_t)jj * nx + ii] & CL_B) {
+          h.cls[k] |= CL_S;
+          break;
+        }
+      }
+    }
+  return true;
+}
+
+void build_tiles(lbm_ctx *c) {
+  c->tiles.clear();
+  const int own = c->lanes - 2;
+  for (size_t p = 0; p < c->ph.size(); p++) {
+    const PlateHost &h = c->ph[p];
+    const int ns = (h.nx + own - 1) / own;
+    const int w = (h.nx + ns - 1) / ns;
+    for (int y0 = 0; y0 < h.ny; y0 += c->rows) {
+      const int y1 = std::min(h.ny, y0 + c->rows);
+      for (int s = 0; s < ns; s++) {
+        Tile t{};
+        t.plate = (int)p;
+        t.x0 = s * w;
+        t.x1 = std::min(h.nx, (s + 1) * w);
+        t.y0 = y0;
+        t.y1 = y1;
+        if (t.x1 > t.x0) c->tiles.push_back(t);
+      }
+    }
+  }
+}
+
+lbm_status upload_tiles(lbm_ctx *c) {
+  if (c->tiles.size() > c->tiles_cap) {
+    size_t cap = c->tiles.size() * 2;
+    Tile *d = (Tile *)dev_alloc(c, cap * sizeof(Tile));
+    if (!d) return fail(c, LBM_E_NOMEM, "tile list allocation failed");
+    c->d_tiles = d;
+    c->tiles_cap = cap;
+  }
+  HIP_TRY(c, hipMemcpy(c->d_tiles, c->tiles.data(), c->tiles.size() * sizeof(Tile),
+                       hipMemcpyHostToDevice),
+          "tile upload");
+  return LBM_OK;
+}
+
+lbm_status upload_boundary(lbm_ctx *c) {
+  if (!c->bnd.empty())
+    HIP_TRY(c, hipMemcpy(c->d_bnd, c->bnd.data(), c->bnd.size() * sizeof(BndNode),
+                         hipMemcpyHostToDevice),
+            "boundary upload");
+  if (!c->loads.empty())
+    HIP_TRY(c, hipMemcpy(c->d_loads, c->loads.data(), c->loads.size() * sizeof(LoadTable),
+                         hipMemcpyHostToDevice),
+            "load table upload");
+  c->bnd_dirty = false;
+  return LBM_OK;
+}
+
+// One time step (two launches, plus the synchronization after every l-th
+// step).  ev: optional events recorded around each launch for profiling.
+hipError_t enqueue_step(lbm_ctx *c, int64_t step_index, hipStream_t st, hipEvent_t *ev,
+                        double *ms, int64_t *cnt) {
+  const int cur = (int)(step_index & 1);
+  auto timed = [&](int kind, auto &&fn) -> hipError_t {
+    if (ev) (void)hipEventRecord(ev[0], st);
+    hipError_t e = fn();
+    if (ev) {
+      (void)hipEventRecord(ev[1], st);
+      (void)hipEventSynchronize(ev[1]);
+      float t = 0;
+      (void)hipEventElapsedTime(&t, ev[0], ev[1]);
+      ms[kind] += t;
+      cnt[kind] += 1;
+    }
+    return e;
+  };
+  hipError_t e = timed(0, [&] {
+    return launch_interior(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), c->lanes, cur, st);
+  });
+  if (e != hipSuccess) return e;
+  e = timed(1, [&] {
+    return launch_post(c->storage, c->ds, (int)c->bnd.size(), (int)c->sec.size(), cur, 1, st);
+  });
+  if (e != hipSuccess) return e;
+  if (c->sync_every > 0 && (step_index + 1) % c->sync_every == 0) {
+    e = timed(2, [&] {
+      return launch_sync(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), c->lanes, cur ^ 1,
+                         st);
+    });
+  }
+  return e;
+}
+
+int64_t graph_period(const lbm_ctx *c) {
+  int64_t g = c->sync_every > 0 ? c->sync_every : 64;
+  while (g % 2 != 0 || g < 32) g += (c->sync_every > 0 ? c->sync_every : 1);
+  return g;
+}
+
+lbm_status ensure_graph(lbm_ctx *c) {
+  if (c->gexec) return LBM_OK;
+  const int64_t G = graph_period(c);
+  if (!c->cap_stream)
+    HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "capture stream");
+  HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal),
+          "begin capture");
+  hipError_t e = hipSuccess;
+  for (int64_t s = 0; s < G && e == hipSuccess; s++) e = enqueue_step(c, s, c->cap_stream, nullptr, nullptr, nullptr);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
+  if (e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return hip_fail(c, e, "capture launch");
+  }
+  if (e2 != hipSuccess) return hip_fail(c, e2, "end capture");
+  hipGraphExec_t ge = nullptr;
+  e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return hip_fail(c, e, "graph instantiate");
+  }
+  c->graph = g;
+  c->gexec = ge;
+  c->gsteps = G;
+  return LBM_OK;
+}
+
+lbm_status check_flag(lbm_ctx *c, bool wait) {
+  if (c->nonfinite) return fail(c, LBM_E_NONFINITE, "non-finite or blown-up displacement");
+  if (c->flag_pending) {
+    hipError_t q = wait ? hipEventSynchronize(c->flag_ev) : hipEventQuery(c->flag_ev);
+    if (q == hipSuccess) {
+      c->flag_pending = false;
+      if (*c->h_flag) c->nonfinite = true;
+    } else if (q != hipErrorNotReady) {
+      return hip_fail(c, q, "flag event");
+    }
+  }
+  if (c->nonfinite) return fail(c, LBM_E_NONFINITE, "non-finite or blown-up displacement");
+  return LBM_OK;
+}
+
+lbm_status start(lbm_ctx *c) {
+  if (c->started) return LBM_OK;
+  if (c->bnd_dirty) {
+    lbm_status st = upload_boundary(c);
+    if (st) return st;
+  }
+  HIP_TRY(c, launch_bacc0(c->storage, c->ds, (int)c->bnd.size(), c->stream), "first boundary step");
+  c->started = true;
+  return LBM_OK;
+}
+
+// Rough magnitude of the initial fields for the 16-bit scale.
+double field_magnitude(const lbm_plate &p, const PlateHost &h, int fl) {
+  const double *given = fl == 0 ? p.e0 : p.w0;
+  const int nx = p.nx, ny = p.ny;
+  double m = 0;
+  if (given) {
+    for (size_t k = 0; k < (size_t)nx * ny; k++)
+      if (h.cls[k] & CL_IN) m = std::max(m, std::fabs(given[k]));
+    return m;
+  }
+  if (!p.u0) return 0.0;
+  const size_t N = (size_t)nx * ny;
+  for (int j = 0; j < ny; j++)
+    for (int i = 0; i < nx; i++) {
+      const size_t k = (size_t)j * nx + i;
+      if (!(h.cls[k] & CL_IN)) continue;
+      double g = 0;
+      for (int comp = 0; comp < 2; comp++) {
+        const double *u = p.u0 + comp * N;
+        if (i + 1 < nx && (h.cls[k + 1] & CL_IN)) g += std::fabs(u[k + 1] - u[k]);
+        if (j + 1 < ny && (h.cls[k + nx] & CL_IN)) g += std::fabs(u[k + nx] - u[k]);
+      }
+      m = std::max(m, 2 * g / p.dh);
+    }
+  return m;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *lbm_version(void) { return "paper_2301_00228_amd lbm 0.1 (gfx950)"; }
+
+const char *lbm_last_error(const lbm_ctx *c) {
+  return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+void lbm_destroy(lbm_ctx *c) {
+  if (!c) return;
+  if (c->stream || true) (void)hipStreamSynchronize(c->stream);
+  drop_graph(c);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  if (c->flag_ev) (void)hipEventDestroy(c->flag_ev);
+  if (c->h_flag) (void)hipHostFree(c->h_flag);
+  dev_free_all(c);
+  delete c;
+}
+
+lbm_status lbm_create(const lbm_plate *plates, int32_t n_plates, lbm_storage storage,
+                      void *hip_stream, const lbm_alloc *alloc, lbm_ctx **out) {
+  if (!out) return fail(nullptr, LBM_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (!plates || n_plates <= 0) return fail(nullptr, LBM_E_INVAL, "no plates");
+  if ((int)storage < LBM_STORE_F64 || (int)storage > LBM_STORE_BF16DEV)
+    return fail(nullptr, LBM_E_INVAL, "unknown storage");
+  if (alloc && (!alloc->alloc || !alloc->free))
+    return fail(nullptr, LBM_E_INVAL, "allocator needs alloc and free");
+
+  lbm_ctx *c = new (std::nothrow) lbm_ctx();
+  if (!c) return fail(nullptr, LBM_E_NOMEM, "context allocation failed");
+  c->storage = (int)storage;
+  c->stream = (hipStream_t)hip_stream;
+  if (alloc) {
+    c->have_alloc = true;
+    c->alloc = *alloc;
+  }
+  c->ph.resize(n_plates);
+  c->pd.resize(n_plates);
+  c->sync_every = plates[0].sync_every;
+  int64_t off = 0;
+  // ---- host-side validation and preprocessing (no HIP call yet)
+  for (int p = 0; p < n_plates; p++) {
+    const lbm_plate &pl = plates[p];
+    if (pl.nx < 3 || pl.ny < 3 || pl.nx > (1 << 20) || pl.ny > (1 << 20) || pl.sync_every < 0) {
+      delete c;
+      return fail(nullptr, LBM_E_INVAL, "plate " + std::to_string(p) + ": bad size or sync_every");
+    }
+    if (pl.sync_every != c->sync_every) {
+      delete c;
+      return fail(nullptr, LBM_E_INVAL, "all plates must share sync_every");
+    }
+    lbm_status st = plate_params(pl, c->pd[p]);
+    if (st != LBM_OK) {
+      delete c;
+      return fail(nullptr, st,
+                  st == LBM_E_UNSTABLE_DT
+                      ? "plate " + std::to_string(p) + ": dt gives a0_phi < 0 (dt > dh/(sqrt(2) c_d))"
+                      : "plate " + std::to_string(p) + ": bad material or lattice parameters");
+    }
+    PlateHost &h = c->ph[p];
+    h.nx = pl.nx;
+    h.ny = pl.ny;
+    h.px = pl.periodic_x != 0;
+    h.py = pl.periodic_y != 0;
+    h.pitch = (pl.nx + 63) / 64 * 64;
+    h.off = off;
+    std::string why;
+    if (!classify(pl, h, why)) {
+      delete c;
+      return fail(nullptr, LBM_E_INVAL, "plate " + std::to_string(p) + ": " + why);
+    }
+    off += (int64_t)h.pitch * pl.ny;
+    off = (off + 255) / 256 * 256;
+    c->n_body += h.body;
+    PlateDev &d = c->pd[p];
+    d.off = h.off;
+    d.nx = h.nx;
+    d.ny = h.ny;
+    d.pitch = h.pitch;
+    d.periodic = (h.px ? 1 : 0) | (h.py ? 2 : 0);
+    for (int fl = 0; fl < 2; fl++) {
+      const double m = field_magnitude(pl, h, fl);
+      const int e = m > 0 ? 12 - (int)std::ceil(std::log2(m)) : 14;
+      const int ec = std::max(-100, std::min(100, e));
+      d.scale[fl] = std::ldexp(1.0f, ec);
+      d.iscale[fl] = std::ldexp(1.0f, -ec);
+    }
+    // boundary and second-row lists (row-major order)
+    h.b0 = (int64_t)c->bnd.size();
+    for (int j = 0; j < h.ny; j++)
+      for (int i = 0; i < h.nx; i++) {
+        const uint8_t cl = h.cls[(size_t)j * h.nx + i];
+        const int64_t node = h.off + (int64_t)j * h.pitch + i;
+        if (cl & CL_B) {
+          BndNode b{};
+          b.node = node;
+          b.plate = p;
+          b.i = i;
+          b.j = j;
+          b.kind = LBM_BC_NEUMANN;
+          b.load = -1;
+          const int E = (cl & NB_E) ? 1 : 0, N = (cl & NB_N) ? 1 : 0, W = (cl & NB_W) ? 1 : 0,
+                    S = (cl & NB_S) ? 1 : 0;
+          const double wx = 0.5 * pl.dh * (W + E);
+          const double wy = 0.5 * pl.dh * (S + N);
+          b.cell[0] = wx * wy;
+          b.cell[1] = E ? wy : 0.0;
+          b.cell[2] = N ? wx : 0.0;
+          b.cell[3] = W ? wy : 0.0;
+          b.cell[4] = S ? wx : 0.0;
+          c->bnd.push_back(b);
+        } else if (cl & CL_S) {
+          SecNode s{};
+          s.node = node;
+          s.plate = p;
+          s.i = i;
+          s.j = j;
+          c->sec.push_back(s);
+        }
+      }
+    h.b1 = (int64_t)c->bnd.size();
+  }
+  c->n_alloc = off;
+  if (c->bnd.size() + c->sec.size() > (size_t)0x7fffffff) {
+    delete c;
+    return fail(nullptr, LBM_E_INVAL, "too many boundary nodes");
+  }
+
+  // ---- device
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+    delete c;
+    return fail(nullptr, LBM_E_DEVICE, "no HIP device available");
+  }
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return fail(nullptr, LBM_E_DEVICE, "hipGetDevice failed");
+  }
+  auto bail = [&](lbm_status st, const std::string &m) {
+    g_create_error = m;
+    lbm_destroy(c);
+    return st;
+  };
+  const int64_t N = c->n_alloc;
+  const int nsl = slot_count(c->storage);
+  for (int b = 0; b < 2; b++)
+    for (int fl = 0; fl < 2; fl++)
+      for (int sl = 0; sl < 5; sl++) {
+        if (sl >= nsl) {
+          c->ds.pop[b][fl][sl] = nullptr;
+          continue;
+        }
+        void *p = dev_alloc(c, (size_t)N * slot_bytes(c->storage));
+        if (!p) return bail(LBM_E_NOMEM, "population allocation failed");
+        c->ds.pop[b][fl][sl] = p;
+      }
+  for (int b = 0; b < 2; b++)
+    for (int comp = 0; comp < 2; comp++) {
+      c->ds.u[b][comp] = dev_alloc(c, (size_t)N * uv_bytes(c->storage));
+      c->ds.v[b][comp] = dev_alloc(c, (size_t)N * uv_bytes(c->storage));
+      if (!c->ds.u[b][comp] || !c->ds.v[b][comp]) return bail(LBM_E_NOMEM, "u/v allocation failed");
+    }
+  c->d_cls = (uint8_t *)dev_alloc(c, (size_t)N);
+  c->d_plates = (PlateDev *)dev_alloc(c, c->pd.size() * sizeof(PlateDev));
+  c->d_bnd = (BndNode *)dev_alloc(c, std::max<size_t>(1, c->bnd.size()) * sizeof(BndNode));
+  c->d_sec = (SecNode *)dev_alloc(c, std::max<size_t>(1, c->sec.size()) * sizeof(SecNode));
+  c->d_loads = (LoadTable *)dev_alloc(c, (size_t)n_plates * kMaxLoadsPerPlate * sizeof(LoadTable));
+  c->d_counter = (unsigned long long *)dev_alloc(c, 256);
+  c->d_flag = (int *)(((char *)c->d_counter) + 64);
+  if (!c->d_cls || !c->d_plates || !c->d_bnd || !c->d_sec || !c->d_loads || !c->d_counter)
+    return bail(LBM_E_NOMEM, "metadata allocation failed");
+  c->ds.cls = c->d_cls;
+  c->ds.plates = c->d_plates;
+  c->ds.loads = c->d_loads;
+  c->ds.bnd = c->d_bnd;
+  c->ds.sec = c->d_sec;
+  c->ds.counter = c->d_counter;
+  c->ds.flag = c->d_flag;
+
+  hipError_t e;
+  if ((e = hipMemset(c->d_counter, 0, 256)) != hipSuccess) return bail(LBM_E_DEVICE, "memset");
+  if ((e = hipMemset(c->d_cls, 0, (size_t)N)) != hipSuccess) return bail(LBM_E_DEVICE, "memset");
+  for (int b = 0; b < 2; b++)
+    for (int comp = 0; comp < 2; comp++) {
+      if (hipMemset(c->ds.u[b][comp], 0, (size_t)N * uv_bytes(c->storage)) != hipSuccess ||
+          hipMemset(c->ds.v[b][comp], 0, (size_t)N * uv_bytes(c->storage)) != hipSuccess)
+        return bail(LBM_E_DEVICE, "memset");
+    }
+  for (int p = 0; p < n_plates; p++) {
+    const PlateHost &h = c->ph[p];
+    if (hipMemcpy2D(c->d_cls + h.off, (size_t)h.pitch, h.cls.data(), (size_t)h.nx, (size_t)h.nx,
+                    (size_t)h.ny, hipMemcpyHostToDevice) != hipSuccess)
+      return bail(LBM_E_DEVICE, "class upload");
+  }
+  if (hipMemcpy(c->d_plates, c->pd.data(), c->pd.size() * sizeof(PlateDev),
+                hipMemcpyHostToDevice) != hipSuccess)
+    return bail(LBM_E_DEVICE, "plate upload");
+  if (!c->sec.empty() && hipMemcpy(c->d_sec, c->sec.data(), c->sec.size() * sizeof(SecNode),
+                                   hipMemcpyHostToDevice) != hipSuccess)
+    return bail(LBM_E_DEVICE, "second-row upload");
+
+  // initial state, plate by plate, through a temporary dense staging buffer
+  size_t maxn = 0;
+  for (auto &h : c->ph) maxn = std::max(maxn, (size_t)h.nx * h.ny);
+  double *stage = nullptr;
+  if (hipMalloc(&stage, maxn * 6 * sizeof(double)) != hipSuccess)
+    return bail(LBM_E_NOMEM, "staging allocation failed");
+  for (int p = 0; p < n_plates && e == hipSuccess; p++) {
+    const lbm_plate &pl = plates[p];
+    const size_t n = (size_t)pl.nx * pl.ny;
+    double *du = stage, *dv = stage + 2 * n, *de = stage + 4 * n, *dw = stage + 5 * n;
+    if (pl.u0) e = hipMemcpy(du, pl.u0, 2 * n * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess && pl.v0) e = hipMemcpy(dv, pl.v0, 2 * n * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess && pl.e0) e = hipMemcpy(de, pl.e0, n * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess && pl.w0) e = hipMemcpy(dw, pl.w0, n * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = launch_init(c->storage, c->ds, p, (int64_t)n, pl.u0 ? du : nullptr, pl.v0 ? dv : nullptr,
+                      pl.e0 ? de : nullptr, pl.w0 ? dw : nullptr, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+  }
+  (void)hipFree(stage);
+  if (e != hipSuccess) return bail(LBM_E_DEVICE, std::string("initial state: ") + hipGetErrorString(e));
+
+  // tiles (cached tuning if any)
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto key = std::make_tuple(c->storage, n_plates > 1 ? 1 : 0,
+                               (int)std::lround(std::log2((double)std::max<int64_t>(1, c->n_body))));
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      c->lanes = it->second.first;
+      c->rows = it->second.second;
+    } else {
+      c->lanes = 256;
+      c->rows = 64;
+      int64_t maxnx = 0;
+      for (auto &h : c->ph) maxnx = std::max<int64_t>(maxnx, h.nx);
+      if (maxnx <= 512) c->lanes = 128;
+      if (c->n_body < (int64_t)4 << 20) c->rows = 16;
+    }
+  }
+  build_tiles(c);
+  if (upload_tiles(c) != LBM_OK) return bail(LBM_E_DEVICE, c->err);
+  if (hipHostMalloc((void **)&c->h_flag, sizeof(int), hipHostMallocDefault) != hipSuccess)
+    return bail(LBM_E_NOMEM, "pinned flag allocation failed");
+  *c->h_flag = 0;
+  if (hipEventCreateWithFlags(&c->flag_ev, hipEventDisableTiming) != hipSuccess)
+    return bail(LBM_E_DEVICE, "event creation failed");
+  if (hipDeviceSynchronize() != hipSuccess) return bail(LBM_E_DEVICE, "synchronize");
+  *out = c;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_bc(lbm_ctx *c, int32_t plate, int32_t n, const int32_t *xy, const uint8_t *kind,
+                      const double *val, const double *cell, int32_t n_knots,
+                      const double *knots) {
+  if (!c) return LBM_E_INVAL;
+  if (c->started) return fail(c, LBM_E_STATE, "lbm_set_bc after the first step");
+  if (plate < 0 || plate >= (int)c->ph.size()) return fail(c, LBM_E_INVAL, "bad plate index");
+  if (n < 0 || (n > 0 && (!xy || !kind || !val))) return fail(c, LBM_E_INVAL, "bad node arrays");
+  if (n_knots < 0 || n_knots > kMaxKnots || (n_knots > 0 && !knots))
+    return fail(c, LBM_E_INVAL, "bad knot table");
+  for (int m = 1; m < n_knots; m++)
+    if (!(knots[2 * m] > knots[2 * m - 2])) return fail(c, LBM_E_INVAL, "knot times must increase");
+  PlateHost &h = c->ph[plate];
+  std::vector<int64_t> idx((size_t)n);
+  for (int m = 0; m < n; m++) {
+    const int i = xy[2 * m], j = xy[2 * m + 1];
+    if (i < 0 || i >= h.nx || j < 0 || j >= h.ny)
+      return fail(c, LBM_E_INVAL, "node outside the plate");
+    if (!(h.cls[(size_t)j * h.nx + i] & CL_B))
+      return fail(c, LBM_E_INVAL, "node (" + std::to_string(i) + ", " + std::to_string(j) +
+                                      ") is not a boundary node");
+    if (kind[m] > 1) return fail(c, LBM_E_INVAL, "bad boundary kind");
+    if (!std::isfinite(val[2 * m]) || !std::isfinite(val[2 * m + 1]))
+      return fail(c, LBM_E_INVAL, "non-finite boundary value");
+    if (cell && !(cell[5 * m] > 0)) return fail(c, LBM_E_INVAL, "cell volume must be positive");
+    const int64_t node = h.off + (int64_t)j * h.pitch + i;
+    auto first = c->bnd.begin() + h.b0, last = c->bnd.begin() + h.b1;
+    auto it = std::lower_bound(first, last, node,
+                               [](const BndNode &b, int64_t v) { return b.node < v; });
+    idx[m] = it - c->bnd.begin();
+  }
+  int load = -1;
+  if (n_knots > 0) {
+    if (h.nloads >= kMaxLoadsPerPlate) return fail(c, LBM_E_INVAL, "too many load tables");
+    LoadTable L{};
+    L.n = n_knots;
+    for (int m = 0; m < n_knots; m++) {
+      L.t[m] = knots[2 * m];
+      L.g[m] = knots[2 * m + 1];
+    }
+    load = (int)c->loads.size();
+    c->loads.push_back(L);
+    h.nloads++;
+  }
+  for (int m = 0; m < n; m++) {
+    BndNode &b = c->bnd[(size_t)idx[m]];
+    b.kind = kind[m];
+    b.val[0] = val[2 * m];
+    b.val[1] = val[2 * m + 1];
+    b.load = load;
+    if (cell)
+      for (int q = 0; q < 5; q++) b.cell[q] = cell[5 * m + q];
+  }
+  c->bnd_dirty = true;
+  return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx *c, int64_t n) {
+  if (!c || n < 0) return LBM_E_INVAL;
+  lbm_status st = check_flag(c, false);
+  if (st) return st;
+  st = start(c);
+  if (st) return st;
+  while (n > 0) {
+    if (c->use_graphs) {
+      const int64_t G = graph_period(c);
+      if (n >= G && c->step % G == 0) {
+        st = ensure_graph(c);
+        if (st) return st;
+        HIP_TRY(c, hipGraphLaunch(c->gexec, c->stream), "graph launch");
+        c->step += G;
+        n -= G;
+        continue;
+      }
+    }
+    HIP_TRY(c, enqueue_step(c, c->step, c->stream, nullptr, nullptr, nullptr), "step launch");
+    c->step += 1;
+    n -= 1;
+  }
+  HIP_TRY(c, hipMemcpyAsync(c->h_flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream),
+          "flag copy");
+  HIP_TRY(c, hipEventRecord(c->flag_ev, c->stream), "flag event");
+  c->flag_pending = true;
+  return LBM_OK;
+}
+
+lbm_status lbm_fields_device(lbm_ctx *c, int32_t plate, double *e, double *w, double *u,
+                             double *v) {
+  if (!c) return LBM_E_INVAL;
+  if (plate < 0 || plate >= (int)c->ph.size()) return fail(c, LBM_E_INVAL, "bad plate index");
+  const PlateHost &h = c->ph[plate];
+  HIP_TRY(c, launch_fields(c->storage, c->ds, plate, (int64_t)h.nx * h.ny, (int)(c->step & 1), e,
+                           w, u, v, c->stream),
+          "field kernel");
+  return LBM_OK;
+}
+
+lbm_status lbm_fields(lbm_ctx *c, int32_t plate, double *e, double *w, double *u, double *v) {
+  if (!c) return LBM_E_INVAL;
+  if (plate < 0 || plate >= (int)c->ph.size()) return fail(c, LBM_E_INVAL, "bad plate index");
+  const PlateHost &h = c->ph[plate];
+  const size_t n = (size_t)h.nx * h.ny;
+  const size_t need = 6 * n * sizeof(double);
+  if (need > c->scratch_bytes) {
+    double *p = (double *)dev_alloc(c, need);
+    if (!p) return fail(c, LBM_E_NOMEM, "field scratch allocation failed");
+    c->d_scratch = p;
+    c->scratch_bytes = need;
+  }
+  double *de = c->d_scratch, *dw = de + n, *du = dw + n, *dv = du + 2 * n;
+  lbm_status st = lbm_fields_device(c, plate, e ? de : nullptr, w ? dw : nullptr,
+                                    u ? du : nullptr, v ? dv : nullptr);
+  if (st) return st;
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "synchronize");
+  if (e) HIP_TRY(c, hipMemcpy(e, de, n * sizeof(double), hipMemcpyDeviceToHost), "copy e");
+  if (w) HIP_TRY(c, hipMemcpy(w, dw, n * sizeof(double), hipMemcpyDeviceToHost), "copy omega");
+  if (u) HIP_TRY(c, hipMemcpy(u, du, 2 * n * sizeof(double), hipMemcpyDeviceToHost), "copy u");
+  if (v) HIP_TRY(c, hipMemcpy(v, dv, 2 * n * sizeof(double), hipMemcpyDeviceToHost), "copy v");
+  int flag = 0;
+  HIP_TRY(c, hipMemcpy(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost), "copy flag");
+  if (flag) c->nonfinite = true;
+  return check_flag(c, true);
+}
+
+lbm_status lbm_info(const lbm_ctx *c, lbm_info_t *info) {
+  if (!c || !info) return LBM_E_INVAL;
+  std::memset(info, 0, sizeof *info);
+  info->nodes_in_body = c->n_body;
+  info->nodes_allocated = c->n_alloc;
+  info->boundary_nodes = (int64_t)c->bnd.size();
+  info->second_row_nodes = (int64_t)c->sec.size();
+  info->steps_done = c->step;
+  info->device_bytes = c->device_bytes;
+  info->bytes_per_update = bytes_per_update(c->storage);
+  info->n_plates = (int32_t)c->ph.size();
+  info->storage = c->storage;
+  info->tile_lanes = c->lanes;
+  info->tile_rows = c->rows;
+  info->n_tiles = (int32_t)c->tiles.size();
+  return LBM_OK;
+}
+
+lbm_status lbm_set_tiling(lbm_ctx *c, int32_t lanes, int32_t rows) {
+  if (!c) return LBM_E_INVAL;
+  if ((lanes != 64 && lanes != 128 && lanes != 256) || rows < 1 || rows > 65536)
+    return fail(c, LBM_E_INVAL, "lanes must be 64, 128 or 256 and rows >= 1");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "synchronize");
+  c->lanes = lanes;
+  c->rows = rows;
+  build_tiles(c);
+  lbm_status st = upload_tiles(c);
+  if (st) return st;
+  drop_graph(c);
+  return LBM_OK;
+}
+
+lbm_status lbm_use_graphs(lbm_ctx *c, int32_t enable) {
+  if (!c) return LBM_E_INVAL;
+  c->use_graphs = enable != 0;
+  return LBM_OK;
+}
+
+lbm_status lbm_profile(lbm_ctx *c, int64_t n, double *ms, int64_t *launches) {
+  if (!c || n < 0 || !ms) return LBM_E_INVAL;
+  lbm_status st = check_flag(c, false);
+  if (st) return st;
+  st = start(c);
+  if (st) return st;
+  hipEvent_t ev[2];
+  HIP_TRY(c, hipEventCreate(&ev[0]), "event");
+  HIP_TRY(c, hipEventCreate(&ev[1]), "event");
+  double acc[4] = {0, 0, 0, 0};
+  int64_t cnt[4] = {0, 0, 0, 0};
+  hipError_t e = hipSuccess;
+  for (int64_t s = 0; s < n && e == hipSuccess; s++) {
+    e = enqueue_step(c, c->step, c->stream, ev, acc, cnt);
+    if (e == hipSuccess) c->step += 1;
+  }
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  if (e != hipSuccess) return hip_fail(c, e, "profiled step");
+  for (int k = 0; k < 4; k++) {
+    ms[k] = acc[k];
+    if (launches) launches[k] = cnt[k];
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
+  if (!c || steps < 1) return LBM_E_INVAL;
+  lbm_status st = start(c);
+  if (st) return st;
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "synchronize");
+  unsigned long long saved = 0;
+  HIP_TRY(c, hipMemcpy(&saved, c->d_counter, sizeof saved, hipMemcpyDeviceToHost), "counter");
+  const int lane_set[3] = {64, 128, 256};
+  const int row_set[5] = {8, 16, 32, 64, 128};
+  hipEvent_t e0, e1;
+  HIP_TRY(c, hipEventCreate(&e0), "event");
+  HIP_TRY(c, hipEventCreate(&e1), "event");
+  const int cur = (int)(c->step & 1);
+  double best = 1e300;
+  int bl = c->lanes, br = c->rows;
+  for (int L : lane_set)
+    for (int R : row_set) {
+      c->lanes = L;
+      c->rows = R;
+      build_tiles(c);
+      if (upload_tiles(c) != LBM_OK) continue;
+      // The interior kernel reads buffer cur and writes only interior nodes
+      // of the other buffer, so repeating it leaves the state unchanged.
+      hipError_t e = launch_interior(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), L, cur,
+                                     c->stream);
+      (void)hipEventRecord(e0, c->stream);
+      for (int s = 0; s < steps && e == hipSuccess; s++)
+        e = launch_interior(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), L, cur, c->stream);
+      (void)hipEventRecord(e1, c->stream);
+      (void)hipEventSynchronize(e1);
+      if (e != hipSuccess) continue;
+      float t = 0;
+      (void)hipEventElapsedTime(&t, e0, e1);
+      const double per = t / steps;
+      if (per < best) {
+        best = per;
+        bl = L;
+        br = R;
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  HIP_TRY(c, hipMemcpy(c->d_counter, &saved, sizeof saved, hipMemcpyHostToDevice), "counter");
+  c->lanes = bl;
+  c->rows = br;
+  build_tiles(c);
+  st = upload_tiles(c);
+  if (st) return st;
+  drop_graph(c);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto key = std::make_tuple(c->storage, c->ph.size() > 1 ? 1 : 0,
+                               (int)std::lround(std::log2((double)std::max<int64_t>(1, c->n_body))));
+    g_tune_cache[key] = {bl, br};
+  }
+  if (best_ms) *best_ms = best;
+  return LBM_OK;
+}
+
+}  // extern "C"

@@ -220,6 +220,8 @@ def ellipse_holes_mask(nx, ny, area_frac, rng, a_lo=8.0, a_hi=64.0, clearance=4.
     area = 0.0
     placed = []  # (cx, cy, R)
     tries = 0
+    a_hi = min(a_hi, (min(nx, ny) - 1) / 2.0 - clearance - 3.0)
+    a_lo = min(a_lo, a_hi)
     while area < target and tries < max_tries:
         tries += 1
         a = rng.uniform(a_lo, a_hi)
@@ -244,9 +246,13 @@ def ellipse_holes_mask(nx, ny, area_frac, rng, a_lo=8.0, a_hi=64.0, clearance=4.
 
 
 def strip_with_holes(nx=65536, ny=2048, area_frac=0.05, nu=0.3, a0_phi=0.9999, steps=2000,
-                     sync_every=50, sigma=32.0, amp=1e-3, pulses=8, seed_index=4):
+                     sync_every=50, sigma=32.0, amp=1e-3, pulses=8, seed_index=4, a_lo=8.0,
+                     a_hi=64.0):
+    """Long strip with seeded elliptic traction-free holes (area_frac of the
+    plate), outer edges Dirichlet u* = 0 or free with probability 1/2,
+    several seeded pulses."""
     rng = rng_for(seed_index, 1)
-    mask = ellipse_holes_mask(nx, ny, area_frac, rng)
+    mask = ellipse_holes_mask(nx, ny, area_frac, rng, a_lo=a_lo, a_hi=a_hi)
     edges = [e for e in (LEFT, RIGHT, BOTTOM, TOP) if rng.random() < 0.5]
     u0 = np.zeros((2, ny, nx))
     lo = 6 * sigma

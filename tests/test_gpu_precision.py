@@ -1,0 +1,40 @@
+"""Reduced-storage paths against the FP64 CPU oracle: relative L2 error of
+e, omega and u after 2000 steps on a plate with a traction-free hole and
+clamped outer edges (the precision workload at a size the oracle runs in
+seconds)."""
+import numpy as np
+import pytest
+
+from oracle.oracle import run_case
+from paper_2301_00228_amd import inputs as I
+from paper_2301_00228_amd import lbm
+
+pytestmark = pytest.mark.gpu
+
+# Bound per storage on max(rel L2 of e, omega, u) after 2000 steps.
+BOUND = {"f32": 1e-3, "f32dev": 1e-3, "f16dev": 1e-3, "bf16dev": 1e-2}
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def reference():
+    import torch
+    torch.cuda.set_device(0)
+    case = I.plate_with_hole(n=256, radius=32, sigma=8.0, steps=2000, sync_every=50)
+    ref, _ = run_case(case)
+    return case, ref
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f32dev", "f16dev", "bf16dev"])
+def test_reduced_storage_error(reference, storage):
+    case, ref = reference
+    with lbm.context_for(case, storage) as ctx:
+        ctx.step(case.steps)
+        got = ctx.fields(0)
+    errs = {k: rel_l2(got[k], ref[k]) for k in ("e", "omega", "u")}
+    print(storage, {k: f"{v:.3e}" for k, v in errs.items()}, flush=True)
+    bound = 1e-12 if storage == "f64" else BOUND[storage]
+    assert max(errs.values()) <= bound, (storage, errs)
