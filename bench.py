@@ -86,6 +86,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=200)
+    ap.add_argument("--storage", default="f64", help="storage of the headline run")
+    ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
+                    help="only run a plain device copy of this many GiB 5 times (counter "
+                         "calibration for rocprofv3 --pmc) and exit")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -99,6 +103,15 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration > 0:
+        n = int(args.copy_calibration * 2**30) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 5}))
+        return
     case = inputs.clamped_plate(n=1024, steps=args.steps)
     nodes = case.in_body_nodes()
     K, W = args.steps, args.warmup
@@ -113,7 +126,7 @@ def main():
         dt = time.perf_counter() - t0
         return ctx, dt
 
-    ctx, dt = timed_run("f64")
+    ctx, dt = timed_run(args.storage)
     ms_per_step = dt / K * 1e3
     glups = nodes * K / dt / 1e9
     info = ctx.info()
@@ -126,11 +139,11 @@ def main():
     per_launch_s = int_ms / int_n / 1e3
     bpu = info["bytes_per_update"]
     achieved = nodes * bpu / per_launch_s / 1e9
-    traffic = measured_traffic("f64", nodes)
+    traffic = measured_traffic(args.storage, nodes)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic,
-                "kernel": "k_interior<f64>", "bytes_per_lup": bpu,
+                "kernel": f"k_interior<{args.storage}>", "bytes_per_lup": bpu,
                 "lups_per_launch": nodes, "avg_launch_us": round(per_launch_s * 1e6, 2),
                 "boundary_kernel_avg_us": round(bnd_ms / max(bnd_n, 1) * 1e3, 2)}
     ctx.close()
@@ -165,11 +178,11 @@ def main():
     line = {
         "metric": METRIC, "value": round(glups, 4), "unit": "GLUPS", "n_gpus": 1, "steps": K,
         "warmup": W, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": {"f64": "f64", "f32": "f32"}.get(args.storage, "f32+f64"), "data": "synthetic",
         "config": {"workload": "clamped plate 1024x1024 (left edge u*=0, other edges traction "
                                "free), nu 0.3, a0_phi 0.9999, Gaussian pulse sigma 16 amp 1e-3, "
                                "sync every 50, FP64 populations and u",
-                   "nodes": nodes, "storage": "f64", "tile": [info["tile_lanes"],
+                   "nodes": nodes, "storage": args.storage, "tile": [info["tile_lanes"],
                                                               info["tile_rows"]],
                    "graphs": True},
         "roofline": roofline,

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -79,7 +80,7 @@ std::map<std::tuple<int, int, int>, std::pair<int, int>> g_tune_cache;
 struct lbm_ctx {
   int storage = 0;
   hipStream_t stream = nullptr;
-  hipStream_t cap_stream = nullptr;
+  hipStream_t cap_stream = nullptr;  // graph capture
   bool have_alloc = false;
   lbm_alloc alloc{};
   int device = 0;
@@ -93,6 +94,17 @@ struct lbm_ctx {
 
   std::vector<BndNode> bnd;
   std::vector<SecNode> sec;
+  std::vector<Chunk> chunks;
+  std::vector<UNode> unodes;
+  std::vector<GradNode> gnodes;
+  std::vector<BTask> btasks;
+  std::vector<int64_t> btask_bnd;  // boundary record of each boundary task
+  std::vector<STask> stasks;
+  Chunk *d_chunks = nullptr;
+  UNode *d_unodes = nullptr;
+  GradNode *d_gnodes = nullptr;
+  BTask *d_btasks = nullptr;
+  STask *d_stasks = nullptr;
   std::vector<LoadTable> loads;
   std::vector<Tile> tiles;
   int lanes = 128, rows = 32;
@@ -204,6 +216,8 @@ lbm_status plate_params(const lbm_plate &p, PlateDev &d) {
   d.cs2 = cs * cs;
   d.dt = p.dt;
   d.dh = p.dh;
+  d.inv_h = 1.0 / p.dh;
+  d.inv_2h = 1.0 / (2.0 * p.dh);
   d.rho_m = p.rho_m;
   d.lam = p.lambda;
   d.mu = p.mu;
@@ -264,6 +278,202 @@ bool classify(const lbm_plate &p, PlateHost &h, std::string &why) {
   return true;
 }
 
+// Stencil code of the finite difference along axis ax at body node (i, j).
+int fd_code_host(const PlateHost &h, int i, int j, int ax) {
+  const uint8_t c0 = h.cls[(size_t)j * h.nx + i];
+  const uint8_t bp = ax == 0 ? NB_E : NB_N, bm = ax == 0 ? NB_W : NB_S;
+  const int di = ax == 0 ? 1 : 0, dj = ax == 0 ? 0 : 1;
+  if ((c0 & bp) && (c0 & bm)) return FD_CENTRAL;
+  if (c0 & bp) {
+    const int ii = (i + di) % h.nx, jj = (j + dj) % h.ny;
+    return (h.cls[(size_t)jj * h.nx + ii] & bp) ? FD_FWD3 : FD_FWD2;
+  }
+  if (c0 & bm) {
+    const int ii = (i - di + h.nx) % h.nx, jj = (j - dj + h.ny) % h.ny;
+    return (h.cls[(size_t)jj * h.nx + ii] & bm) ? FD_BWD3 : FD_BWD2;
+  }
+  return FD_NONE;
+}
+
+// Work lists of the boundary kernel.  Boundary nodes are cut in row-major
+// chunks (at most kChunkNodes, fewer where a chunk's closure would not fit
+// the block's LDS); each second-row node joins the chunk of its first
+// boundary neighbour.  Per chunk: the gradient nodes its tasks read (its
+// boundary nodes, their body neighbours, the boundary neighbours of its
+// second-row nodes) and the displacement nodes those gradients' stencils
+// touch.
+bool build_boundary_tables(lbm_ctx *c, std::string &why) {
+  static const int DI[5] = {0, 1, 0, -1, 0}, DJ[5] = {0, 0, 1, 0, -1};
+  // neighbour order of BTask.g[1..4]: E, N, W, S
+  static const int NI[4] = {1, 0, -1, 0}, NJ[4] = {0, 1, 0, -1};
+  static const uint8_t NB[4] = {NB_E, NB_N, NB_W, NB_S};
+  c->chunks.clear();
+  c->unodes.clear();
+  c->gnodes.clear();
+  c->btasks.clear();
+  c->btask_bnd.clear();
+  c->stasks.clear();
+  auto find_b = [&](const PlateHost &h, int64_t node) -> int64_t {
+    auto first = c->bnd.begin() + h.b0, last = c->bnd.begin() + h.b1;
+    auto it = std::lower_bound(first, last, node,
+                               [](const BndNode &b, int64_t v) { return b.node < v; });
+    return (it != last && it->node == node) ? (int64_t)(it - c->bnd.begin()) : -1;
+  };
+  // second-row nodes by their first boundary neighbour
+  std::vector<std::vector<int>> sec_of_b(c->bnd.size());
+  for (size_t si = 0; si < c->sec.size(); si++) {
+    const SecNode &S = c->sec[si];
+    const PlateHost &h = c->ph[S.plate];
+    for (int al = 1; al < 5; al++) {
+      const int ii = (S.i - DI[al] + h.nx) % h.nx, jj = (S.j - DJ[al] + h.ny) % h.ny;
+      if (h.cls[(size_t)jj * h.nx + ii] & CL_B) {
+        const int64_t b = find_b(h, h.off + (int64_t)jj * h.pitch + ii);
+        if (b < 0) {
+          why = "second-row node without its boundary record";
+          return false;
+        }
+        sec_of_b[(size_t)b].push_back((int)si);
+        break;
+      }
+    }
+  }
+  typedef std::pair<int64_t, std::pair<int, int>> Key;  // node, (i, j)
+  // Closure of boundary records [b0, b1) of plate p; false if too large.
+  auto closure = [&](int p, int64_t b0, int64_t b1, std::vector<Key> &g, std::vector<Key> &u) {
+    const PlateHost &h = c->ph[p];
+    g.clear();
+    u.clear();
+    auto key = [&](int i, int j) { return Key{h.off + (int64_t)j * h.pitch + i, {i, j}}; };
+    for (int64_t b = b0; b < b1; b++) {
+      const BndNode &B = c->bnd[b];
+      g.push_back(key(B.i, B.j));
+      const uint8_t cl = h.cls[(size_t)B.j * h.nx + B.i];
+      for (int d = 0; d < 4; d++)
+        if (cl & NB[d]) g.push_back(key((B.i + NI[d] + h.nx) % h.nx, (B.j + NJ[d] + h.ny) % h.ny));
+      for (int si : sec_of_b[(size_t)b]) {
+        const SecNode &S = c->sec[si];
+        for (int al = 1; al < 5; al++) {
+          const int ii = (S.i - DI[al] + h.nx) % h.nx, jj = (S.j - DJ[al] + h.ny) % h.ny;
+          if (h.cls[(size_t)jj * h.nx + ii] & CL_B) g.push_back(key(ii, jj));
+        }
+      }
+    }
+    std::sort(g.begin(), g.end());
+    g.erase(std::unique(g.begin(), g.end()), g.end());
+    for (const Key &e : g) {
+      const int i = e.second.first, j = e.second.second;
+      u.push_back(key(i, j));
+      for (int ax = 0; ax < 2; ax++) {
+        const int di = ax == 0 ? 1 : 0, dj = ax == 0 ? 0 : 1;
+        const int code = fd_code_host(h, i, j, ax);
+        auto at = [&](int m) { return key((i + m * di + 2 * h.nx) % h.nx, (j + m * dj + 2 * h.ny) % h.ny); };
+        if (code == FD_CENTRAL) { u.push_back(at(1)); u.push_back(at(-1)); }
+        if (code == FD_FWD3) { u.push_back(at(1)); u.push_back(at(2)); }
+        if (code == FD_BWD3) { u.push_back(at(-1)); u.push_back(at(-2)); }
+        if (code == FD_FWD2) u.push_back(at(1));
+        if (code == FD_BWD2) u.push_back(at(-1));
+      }
+    }
+    std::sort(u.begin(), u.end());
+    u.erase(std::unique(u.begin(), u.end()), u.end());
+    int ns = 0;
+    for (int64_t b = b0; b < b1; b++) ns += (int)sec_of_b[(size_t)b].size();
+    return (int)g.size() <= kMaxGrad && (int)u.size() <= kMaxU &&
+           (b1 - b0) + 2 * ns <= kBoundaryThreads;
+  };
+  std::vector<Key> g, u;
+  for (size_t p = 0; p < c->ph.size(); p++) {
+    const PlateHost &h = c->ph[p];
+    int64_t b = h.b0;
+    while (b < h.b1) {
+      int64_t n = std::min<int64_t>(kChunkNodes, h.b1 - b);
+      while (!closure((int)p, b, b + n, g, u)) {
+        if (n == 1) {
+          why = "boundary chunk closure does not fit a block";
+          return false;
+        }
+        n /= 2;
+      }
+      auto local = [](const std::vector<Key> &v, int64_t node) -> int {
+        auto it = std::lower_bound(v.begin(), v.end(), Key{node, {INT32_MIN, INT32_MIN}});
+        return (it != v.end() && it->first == node) ? (int)(it - v.begin()) : -1;
+      };
+      auto nodeat = [&](int i, int j) { return h.off + (int64_t)j * h.pitch + i; };
+      Chunk ch{};
+      ch.plate = (int)p;
+      ch.u0 = (int)c->unodes.size();
+      ch.g0 = (int)c->gnodes.size();
+      ch.b0 = (int)c->btasks.size();
+      ch.s0 = (int)c->stasks.size();
+      for (const Key &e : u) {
+        UNode U{};
+        U.node = e.first;
+        U.i = e.second.first;
+        U.j = e.second.second;
+        U.bnd = (h.cls[(size_t)U.j * h.nx + U.i] & CL_B) ? 1 : 0;
+        c->unodes.push_back(U);
+      }
+      for (const Key &e : g) {
+        const int i = e.second.first, j = e.second.second;
+        GradNode G{};
+        const int cx = fd_code_host(h, i, j, 0), cy = fd_code_host(h, i, j, 1);
+        G.code = cx | (cy << 3);
+        const int self = local(u, e.first);
+        for (int q = 0; q < 5; q++) G.u[q] = self;
+        for (int ax = 0; ax < 2; ax++) {
+          const int di = ax == 0 ? 1 : 0, dj = ax == 0 ? 0 : 1;
+          const int code = ax == 0 ? cx : cy;
+          auto at = [&](int m) {
+            return local(u, nodeat((i + m * di + 2 * h.nx) % h.nx, (j + m * dj + 2 * h.ny) % h.ny));
+          };
+          int a = self, bb = self;
+          if (code == FD_CENTRAL) { a = at(1); bb = at(-1); }
+          if (code == FD_FWD3) { a = at(1); bb = at(2); }
+          if (code == FD_BWD3) { a = at(-1); bb = at(-2); }
+          if (code == FD_FWD2) a = at(1);
+          if (code == FD_BWD2) a = at(-1);
+          G.u[1 + 2 * ax] = a;
+          G.u[2 + 2 * ax] = bb;
+        }
+        c->gnodes.push_back(G);
+      }
+      for (int64_t bi = b; bi < b + n; bi++) {
+        const BndNode &B = c->bnd[bi];
+        const uint8_t cl = h.cls[(size_t)B.j * h.nx + B.i];
+        BTask T{};
+        T.b = B;
+        T.g[0] = local(g, B.node);
+        for (int d = 0; d < 4; d++)
+          T.g[1 + d] = (cl & NB[d]) ? local(g, nodeat((B.i + NI[d] + h.nx) % h.nx,
+                                                      (B.j + NJ[d] + h.ny) % h.ny))
+                                    : -1;
+        c->btasks.push_back(T);
+        c->btask_bnd.push_back(bi);
+        for (int si : sec_of_b[(size_t)bi]) {
+          const SecNode &S = c->sec[si];
+          STask Q{};
+          Q.node = S.node;
+          Q.i = S.i;
+          Q.j = S.j;
+          Q.g[0] = -1;
+          for (int al = 1; al < 5; al++) {
+            const int ii = (S.i - DI[al] + h.nx) % h.nx, jj = (S.j - DJ[al] + h.ny) % h.ny;
+            Q.g[al] = (h.cls[(size_t)jj * h.nx + ii] & CL_B) ? local(g, nodeat(ii, jj)) : -1;
+          }
+          c->stasks.push_back(Q);
+        }
+      }
+      ch.u1 = (int)c->unodes.size();
+      ch.g1 = (int)c->gnodes.size();
+      ch.b1 = (int)c->btasks.size();
+      ch.s1 = (int)c->stasks.size();
+      c->chunks.push_back(ch);
+      b += n;
+    }
+  }
+  return true;
+}
+
 void build_tiles(lbm_ctx *c) {
   c->tiles.clear();
   const int own = c->lanes - 2;
@@ -305,6 +515,11 @@ lbm_status upload_boundary(lbm_ctx *c) {
     HIP_TRY(c, hipMemcpy(c->d_bnd, c->bnd.data(), c->bnd.size() * sizeof(BndNode),
                          hipMemcpyHostToDevice),
             "boundary upload");
+  for (size_t t = 0; t < c->btasks.size(); t++) c->btasks[t].b = c->bnd[(size_t)c->btask_bnd[t]];
+  if (!c->btasks.empty())
+    HIP_TRY(c, hipMemcpy(c->d_btasks, c->btasks.data(), c->btasks.size() * sizeof(BTask),
+                         hipMemcpyHostToDevice),
+            "boundary task upload");
   if (!c->loads.empty())
     HIP_TRY(c, hipMemcpy(c->d_loads, c->loads.data(), c->loads.size() * sizeof(LoadTable),
                          hipMemcpyHostToDevice),
@@ -313,8 +528,10 @@ lbm_status upload_boundary(lbm_ctx *c) {
   return LBM_OK;
 }
 
-// One time step (two launches, plus the synchronization after every l-th
-// step).  ev: optional events recorded around each launch for profiling.
+// One time step: the interior kernel, then the boundary kernel (which reads
+// the interior kernel's u(t+dt) near the boundary), then the
+// synchronization after every l-th step, all in order on st.  With ev
+// (profiling) events are recorded around each launch.
 hipError_t enqueue_step(lbm_ctx *c, int64_t step_index, hipStream_t st, hipEvent_t *ev,
                         double *ms, int64_t *cnt) {
   const int cur = (int)(step_index & 1);
@@ -336,7 +553,9 @@ hipError_t enqueue_step(lbm_ctx *c, int64_t step_index, hipStream_t st, hipEvent
   });
   if (e != hipSuccess) return e;
   e = timed(1, [&] {
-    return launch_post(c->storage, c->ds, (int)c->bnd.size(), (int)c->sec.size(), cur, 1, st);
+    return launch_boundary(c->storage, c->ds, c->d_chunks, (int)c->chunks.size(), c->d_unodes,
+                           c->d_gnodes, c->d_btasks, c->d_stasks, cur, cur ^ 1, cur, 1, 0, cur, 1,
+                           st);
   });
   if (e != hipSuccess) return e;
   if (c->sync_every > 0 && (step_index + 1) % c->sync_every == 0) {
@@ -359,10 +578,12 @@ lbm_status ensure_graph(lbm_ctx *c) {
   const int64_t G = graph_period(c);
   if (!c->cap_stream)
     HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "capture stream");
+
   HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal),
           "begin capture");
   hipError_t e = hipSuccess;
-  for (int64_t s = 0; s < G && e == hipSuccess; s++) e = enqueue_step(c, s, c->cap_stream, nullptr, nullptr, nullptr);
+  for (int64_t s = 0; s < G && e == hipSuccess; s++)
+    e = enqueue_step(c, s, c->cap_stream, nullptr, nullptr, nullptr);
   hipGraph_t g = nullptr;
   hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
   if (e != hipSuccess) {
@@ -403,7 +624,11 @@ lbm_status start(lbm_ctx *c) {
     lbm_status st = upload_boundary(c);
     if (st) return st;
   }
-  HIP_TRY(c, launch_bacc0(c->storage, c->ds, (int)c->bnd.size(), c->stream), "first boundary step");
+  // boundary accelerations of step 0: u(t_1) of the boundary nodes
+  HIP_TRY(c, launch_boundary(c->storage, c->ds, c->d_chunks, (int)c->chunks.size(), c->d_unodes,
+                             c->d_gnodes, c->d_btasks, c->d_stasks, 0, 0, 1, 0, 0, 0, 0,
+                             c->stream),
+          "first boundary step");
   c->started = true;
   return LBM_OK;
 }
@@ -447,9 +672,10 @@ const char *lbm_last_error(const lbm_ctx *c) {
 
 void lbm_destroy(lbm_ctx *c) {
   if (!c) return;
-  if (c->stream || true) (void)hipStreamSynchronize(c->stream);
+  (void)hipStreamSynchronize(c->stream);
   drop_graph(c);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+
   if (c->flag_ev) (void)hipEventDestroy(c->flag_ev);
   if (c->h_flag) (void)hipHostFree(c->h_flag);
   dev_free_all(c);
@@ -561,9 +787,16 @@ lbm_status lbm_create(const lbm_plate *plates, int32_t n_plates, lbm_storage sto
     h.b1 = (int64_t)c->bnd.size();
   }
   c->n_alloc = off;
-  if (c->bnd.size() + c->sec.size() > (size_t)0x7fffffff) {
+  if (c->bnd.size() + c->sec.size() > (size_t)0x3fffffff) {
     delete c;
     return fail(nullptr, LBM_E_INVAL, "too many boundary nodes");
+  }
+  {
+    std::string why;
+    if (!build_boundary_tables(c, why)) {
+      delete c;
+      return fail(nullptr, LBM_E_INVAL, why);
+    }
   }
 
   // ---- device
@@ -592,6 +825,8 @@ lbm_status lbm_create(const lbm_plate *plates, int32_t n_plates, lbm_storage sto
         }
         void *p = dev_alloc(c, (size_t)N * slot_bytes(c->storage));
         if (!p) return bail(LBM_E_NOMEM, "population allocation failed");
+        if (hipMemset(p, 0, (size_t)N * slot_bytes(c->storage)) != hipSuccess)
+          return bail(LBM_E_DEVICE, "memset");
         c->ds.pop[b][fl][sl] = p;
       }
   for (int b = 0; b < 2; b++)
@@ -638,6 +873,32 @@ lbm_status lbm_create(const lbm_plate *plates, int32_t n_plates, lbm_storage sto
   if (!c->sec.empty() && hipMemcpy(c->d_sec, c->sec.data(), c->sec.size() * sizeof(SecNode),
                                    hipMemcpyHostToDevice) != hipSuccess)
     return bail(LBM_E_DEVICE, "second-row upload");
+  c->d_chunks = (Chunk *)dev_alloc(c, std::max<size_t>(1, c->chunks.size()) * sizeof(Chunk));
+  c->d_unodes = (UNode *)dev_alloc(c, std::max<size_t>(1, c->unodes.size()) * sizeof(UNode));
+  c->d_gnodes = (GradNode *)dev_alloc(c, std::max<size_t>(1, c->gnodes.size()) * sizeof(GradNode));
+  c->d_btasks = (BTask *)dev_alloc(c, std::max<size_t>(1, c->btasks.size()) * sizeof(BTask));
+  c->d_stasks = (STask *)dev_alloc(c, std::max<size_t>(1, c->stasks.size()) * sizeof(STask));
+  if (!c->d_chunks || !c->d_unodes || !c->d_gnodes || !c->d_btasks || !c->d_stasks)
+    return bail(LBM_E_NOMEM, "boundary table allocation failed");
+  {
+    hipError_t e1 = hipSuccess;
+    if (!c->chunks.empty())
+      e1 = hipMemcpy(c->d_chunks, c->chunks.data(), c->chunks.size() * sizeof(Chunk),
+                     hipMemcpyHostToDevice);
+    if (e1 == hipSuccess && !c->unodes.empty())
+      e1 = hipMemcpy(c->d_unodes, c->unodes.data(), c->unodes.size() * sizeof(UNode),
+                     hipMemcpyHostToDevice);
+    if (e1 == hipSuccess && !c->gnodes.empty())
+      e1 = hipMemcpy(c->d_gnodes, c->gnodes.data(), c->gnodes.size() * sizeof(GradNode),
+                     hipMemcpyHostToDevice);
+    if (e1 == hipSuccess && !c->btasks.empty())
+      e1 = hipMemcpy(c->d_btasks, c->btasks.data(), c->btasks.size() * sizeof(BTask),
+                     hipMemcpyHostToDevice);
+    if (e1 == hipSuccess && !c->stasks.empty())
+      e1 = hipMemcpy(c->d_stasks, c->stasks.data(), c->stasks.size() * sizeof(STask),
+                     hipMemcpyHostToDevice);
+    if (e1 != hipSuccess) return bail(LBM_E_DEVICE, "boundary table upload");
+  }
 
   // initial state, plate by plate, through a temporary dense staging buffer
   size_t maxn = 0;
@@ -883,8 +1144,6 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
   lbm_status st = start(c);
   if (st) return st;
   HIP_TRY(c, hipStreamSynchronize(c->stream), "synchronize");
-  unsigned long long saved = 0;
-  HIP_TRY(c, hipMemcpy(&saved, c->d_counter, sizeof saved, hipMemcpyDeviceToHost), "counter");
   const int lane_set[3] = {64, 128, 256};
   const int row_set[5] = {8, 16, 32, 64, 128};
   hipEvent_t e0, e1;
@@ -920,7 +1179,6 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
     }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  HIP_TRY(c, hipMemcpy(c->d_counter, &saved, sizeof saved, hipMemcpyHostToDevice), "counter");
   c->lanes = bl;
   c->rows = br;
   build_tiles(c);

@@ -11,12 +11,15 @@ namespace lbm {
 // (reads buffer cur, writes cur ^ 1).  lanes: 64, 128 or 256.
 hipError_t launch_interior(int storage, const DevState &s, const Tile *tiles, int ntiles,
                            int lanes, int cur, hipStream_t stream);
-// Boundary reset, second-row pull and (if do_bacc) next-step boundary
-// accelerations; nb boundary records then ns second-row records.
-hipError_t launch_post(int storage, const DevState &s, int nb, int ns, int cur, int do_bacc,
-                       hipStream_t stream);
-// Boundary accelerations of the first step (buffer 0 -> buffer 1).
-hipError_t launch_bacc0(int storage, const DevState &s, int nb, hipStream_t stream);
+// Boundary kernel over nchunks chunks (see k_boundary): u(t+dt) from buffer
+// gb (boundary nodes) or recomputed from buffer cur (interior nodes, if
+// recompute); resets and second-row pulls (if do_reset) into buffer cur ^ 1;
+// boundary accelerations of step counter[cslot] + step_off from buffer gb
+// written into buffer ub.
+hipError_t launch_boundary(int storage, const DevState &s, const Chunk *chunks, int nchunks,
+                           const UNode *un, const GradNode *gn, const BTask *bt, const STask *stk,
+                           int cur, int gb, int ub, int do_reset, int recompute, int cslot,
+                           int step_off, hipStream_t stream);
 // Synchronization of the state held in buffer b.
 hipError_t launch_sync(int storage, const DevState &s, const Tile *tiles, int ntiles, int lanes,
                        int b, hipStream_t stream);

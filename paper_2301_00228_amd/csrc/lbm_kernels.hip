@@ -12,17 +12,22 @@
 //              acceleration of eq. navier from the neighbours' phi and psi,
 //              advance u and du/dt by eq. integration, and (unless a
 //              neighbour is a boundary node) store the streamed populations.
-//  k_post      boundary and second-row nodes: the boundary reset of
-//              eqs. psi_phi_at_bound and correction-f from finite
-//              differences of u(t+dt); the second-row pull of eq. LBE_mod
-//              with the time-averaged boundary populations; and the boundary
-//              accelerations of eqs. acc_neumann / acc_dirichlet of the next
-//              step with their Newmark update, written into the other u
-//              buffer.
+//  k_boundary  boundary and second-row nodes, one block per chunk of
+//              boundary nodes, after the interior kernel: u(t+dt) of the
+//              nodes the chunk's stencils touch and its gradients go to LDS
+//              first (optionally recomputing u(t+dt) of interior nodes, so
+//              that the kernel does not need the interior kernel of the
+//              same step); then the boundary reset of
+//              eqs. psi_phi_at_bound and correction-f, the second-row pull
+//              of eq. LBE_mod with the time-averaged boundary populations,
+//              and the boundary accelerations of eqs. acc_neumann /
+//              acc_dirichlet of the next step with their Newmark update,
+//              written into the other u buffer.
 //
 // Buffers ping-pong: step n reads populations, u and du/dt from buffer
 // cur = n & 1 and writes buffer cur ^ 1.  Boundary nodes' u(t_{n+1}) is
-// written one step ahead by k_post (or k_bacc0 before the first step).
+// written one step ahead by k_boundary (launched once in acceleration-only
+// mode before the first step).
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
@@ -77,6 +82,19 @@ template <class T>
 struct PopCodec {
   using C = T;
   using U = T;
+  using Slot = T;  // raw stored word of one slot
+  __device__ static void load_raw(const DevState &s, int b, int fl, int64_t k, Slot r[5]) {
+#pragma unroll
+    for (int q = 0; q < 5; q++) r[q] = ldg<T>(s.pop[b][fl][q], k);
+  }
+  __device__ static void raw_to_pops(const PlateDev &, int, const Slot r[5], C f[5]) {
+#pragma unroll
+    for (int q = 0; q < 5; q++) f[q] = r[q];
+  }
+  __device__ static void raw_flux(const Slot r[5], C &jx, C &jy) {
+    jx = r[1] - r[3];
+    jy = r[2] - r[4];
+  }
   __device__ static C aw(const PlateDev &P, int fl) { return (C)P.a[fl]; }
   __device__ static C a0w(const PlateDev &P, int fl) { return (C)P.a0[fl]; }
   __device__ static void load(const DevState &s, int b, int fl, int64_t k, const PlateDev &,
@@ -118,6 +136,7 @@ template <int H>
 struct DevCodec {
   using C = float;
   using U = double;
+  using Slot = uint32_t;  // raw stored word of one slot
   __device__ static C aw(const PlateDev &P, int fl) { return P.af[fl]; }
   __device__ static C a0w(const PlateDev &P, int fl) { return P.a0f[fl]; }
   __device__ static void unpack(uint32_t w, const PlateDev &P, int fl, float &n, float &d) {
@@ -153,6 +172,30 @@ struct DevCodec {
     } else {
       unpack(ldg<uint32_t>(s.pop[b][fl][3], k), P, fl, m[3], m[4]);
     }
+  }
+  __device__ static void load_raw(const DevState &s, int b, int fl, int64_t k, Slot r[5]) {
+    r[0] = ldg<uint32_t>(s.pop[b][fl][0], k);
+    r[1] = ldg<uint32_t>(s.pop[b][fl][1], k);
+    r[2] = ldg<uint32_t>(s.pop[b][fl][2], k);
+    r[3] = ldg<uint32_t>(s.pop[b][fl][3], k);
+    r[4] = H == 0 ? ldg<uint32_t>(s.pop[b][fl][4], k) : 0u;
+  }
+  __device__ static void raw_flux(const Slot r[5], C &jx, C &jy) {
+    jx = __uint_as_float(r[1]);
+    jy = __uint_as_float(r[2]);
+  }
+  __device__ static void raw_to_pops(const PlateDev &P, int fl, const Slot r[5], C f[5]) {
+    float m[5];
+    m[0] = __uint_as_float(r[0]);
+    m[1] = __uint_as_float(r[1]);
+    m[2] = __uint_as_float(r[2]);
+    if (H == 0) {
+      m[3] = __uint_as_float(r[3]);
+      m[4] = __uint_as_float(r[4]);
+    } else {
+      unpack(r[3], P, fl, m[3], m[4]);
+    }
+    moments_to_pops(P, fl, m, f);
   }
   __device__ static void moments_to_pops(const PlateDev &P, int fl, const float m[5], C f[5]) {
     const float q = m[4] + 4.0f * aw(P, fl) * m[0];
@@ -292,22 +335,6 @@ __device__ void div_curl(const DevState &s, int b, const PlateDev &P, int i, int
   cu = dxuy - dyux;
 }
 
-// Hooke's law (Sec. 2, eq. hooke) with the strain from finite differences.
-template <class U>
-__device__ void stress(const DevState &s, int b, const PlateDev &P, int i, int j, U &sxx, U &syy,
-                       U &sxy) {
-  const U *ux = static_cast<const U *>(s.u[b][0]);
-  const U *uy = static_cast<const U *>(s.u[b][1]);
-  const U exx = fd_axis<U>(s, ux, P, i, j, 0);
-  const U eyy = fd_axis<U>(s, uy, P, i, j, 1);
-  const U exy = U(0.5) * (fd_axis<U>(s, ux, P, i, j, 1) + fd_axis<U>(s, uy, P, i, j, 0));
-  const U tr = exx + eyy;
-  const U lam = (U)P.lam, mu = (U)P.mu;
-  sxx = lam * tr + U(2.0) * mu * exx;
-  syy = lam * tr + U(2.0) * mu * eyy;
-  sxy = U(2.0) * mu * exy;
-}
-
 __device__ double load_amp(const DevState &s, int li, double t) {
   if (li < 0) return 1.0;
   const LoadTable &L = s.loads[li];
@@ -324,74 +351,12 @@ __device__ double load_amp(const DevState &s, int li, double t) {
   return L.g[n - 1];
 }
 
-// Boundary acceleration of step n (eq. acc_dirichlet or eq. acc_neumann)
-// from u, du/dt in buffer sb, followed by the Newmark update of eq.
-// integration into buffer db.
-template <class U>
-__device__ void boundary_accel_update(const DevState &s, int sb, int db, const BndNode &B,
-                                      const PlateDev &P, unsigned long long n) {
-  const int64_t k = B.node;
-  const U ux = ldg<U>(s.u[sb][0], k), uy = ldg<U>(s.u[sb][1], k);
-  const U vx = ldg<U>(s.v[sb][0], k), vy = ldg<U>(s.v[sb][1], k);
-  const U dt = (U)P.dt;
-  U ax, ay;
-  if (B.kind == LBM_BC_DIRICHLET) {
-    const double g = load_amp(s, B.load, (double)(n + 1) * P.dt);
-    const U usx = (U)(g * B.val[0]), usy = (U)(g * B.val[1]);
-    ax = U(2.0) / (dt * dt) * (usx - ux) - U(2.0) / dt * vx;
-    ay = U(2.0) / (dt * dt) * (usy - uy) - U(2.0) / dt * vy;
-  } else {
-    const double g = load_amp(s, B.load, (double)n * P.dt);
-    const uint8_t c0 = s.cls[k];
-    const int i = B.i, j = B.j;
-    const U V = (U)B.cell[0], lE = (U)B.cell[1], lN = (U)B.cell[2], lW = (U)B.cell[3],
-            lS = (U)B.cell[4];
-    U sxx, syy, sxy, rxx, ryy, rxy;
-    stress<U>(s, sb, P, i, j, sxx, syy, sxy);
-    U tEx = 0, tEy = 0, tWx = 0, tWy = 0, tNx = 0, tNy = 0, tSx = 0, tSy = 0;
-    if (c0 & NB_E) {
-      stress<U>(s, sb, P, wrapc(i + 1, P.nx), j, rxx, ryy, rxy);
-      tEx = U(0.5) * (sxx + rxx) * lE;
-      tEy = U(0.5) * (sxy + rxy) * lE;
-    }
-    if (c0 & NB_W) {
-      stress<U>(s, sb, P, wrapc(i - 1, P.nx), j, rxx, ryy, rxy);
-      tWx = -(U(0.5) * (sxx + rxx)) * lW;
-      tWy = -(U(0.5) * (sxy + rxy)) * lW;
-    }
-    if (c0 & NB_N) {
-      stress<U>(s, sb, P, i, wrapc(j + 1, P.ny), rxx, ryy, rxy);
-      tNx = U(0.5) * (sxy + rxy) * lN;
-      tNy = U(0.5) * (syy + ryy) * lN;
-    }
-    if (c0 & NB_S) {
-      stress<U>(s, sb, P, i, wrapc(j - 1, P.ny), rxx, ryy, rxy);
-      tSx = -(U(0.5) * (sxy + rxy)) * lS;
-      tSy = -(U(0.5) * (syy + ryy)) * lS;
-    }
-    const U Fx = (U)(g * B.val[0]), Fy = (U)(g * B.val[1]);
-    const U m = (U)P.rho_m * V;
-    ax = (((tEx + tWx) + (tNx + tSx)) + Fx) / m;
-    ay = (((tEy + tWy) + (tNy + tSy)) + Fy) / m;
-  }
-  const U nux = ux + dt * vx + dt * dt / U(2.0) * ax;
-  const U nuy = uy + dt * vy + dt * dt / U(2.0) * ay;
-  stg<U>(s.u[db][0], k, nux);
-  stg<U>(s.u[db][1], k, nuy);
-  stg<U>(s.v[db][0], k, vx + dt * ax);
-  stg<U>(s.v[db][1], k, vy + dt * ay);
-  if (!(fabs((double)nux) < 1e30) || !(fabs((double)nuy) < 1e30)) s.flag[0] = 1;
-}
-
 // Post-collision populations f* = f - 2 (f - f_eq(f)) and zeroth moment of
-// one field at node k from buffer b (eq. LBE with dt/tau = 2).
+// one field (eq. LBE with dt/tau = 2).
 template <class CD>
-__device__ __forceinline__ void collide(const DevState &s, int b, int fl, int64_t k,
-                                        const PlateDev &P, typename CD::C &rho,
-                                        typename CD::C fs[5]) {
+__device__ __forceinline__ void collide_pops(const PlateDev &P, int fl, const typename CD::C f[5],
+                                             typename CD::C &rho, typename CD::C fs[5]) {
   using C = typename CD::C;
-  C f[5];
-  CD::load(s, b, fl, k, P, f);
   const C r = f[0] + ((f[1] + f[3]) + (f[2] + f[4]));
   const C jx = f[1] - f[3], jy = f[2] - f[4];
   C e[5];
@@ -399,6 +364,40 @@ __device__ __forceinline__ void collide(const DevState &s, int b, int fl, int64_
 #pragma unroll
   for (int q = 0; q < 5; q++) fs[q] = f[q] - C(2.0) * (f[q] - e[q]);
   rho = r;
+}
+
+template <class CD>
+__device__ __forceinline__ void collide(const DevState &s, int b, int fl, int64_t k,
+                                        const PlateDev &P, typename CD::C &rho,
+                                        typename CD::C fs[5]) {
+  typename CD::C f[5];
+  CD::load(s, b, fl, k, P, f);
+  collide_pops<CD>(P, fl, f, rho, fs);
+}
+
+// Interior acceleration of eq. navier, c_d^2 grad phi - c_s^2 curl(psi e_z)
+// with curl(psi e_z) = (d_y psi, -d_x psi) and central differences of the
+// neighbours' zeroth moments (E, W, N, S; field 0 = phi, 1 = psi), followed
+// by the Newmark update of eq. integration.  Shared by the interior kernel
+// and the boundary kernel's recomputation so both give identical values.
+// Differences are scaled by the precomputed 1/(2 dh) (exact for dh = 1).
+template <class U>
+__device__ __forceinline__ void interior_update(const PlateDev &P, U e0, U w0, U n0, U s0, U e1,
+                                                U w1, U n1, U s1, U ux, U uy, U vx, U vy, U &nux,
+                                                U &nuy, U &nvx, U &nvy) {
+  const U dt = (U)P.dt;
+  const U i2h = (U)P.inv_2h;
+  const U cd2 = (U)P.cd2, cs2 = (U)P.cs2;
+  const U dphix = (e0 - w0) * i2h;
+  const U dphiy = (n0 - s0) * i2h;
+  const U dpsix = (e1 - w1) * i2h;
+  const U dpsiy = (n1 - s1) * i2h;
+  const U ax = cd2 * dphix - cs2 * dpsiy;
+  const U ay = cd2 * dphiy - cs2 * (-dpsix);
+  nux = ux + dt * vx + dt * dt / U(2.0) * ax;
+  nuy = uy + dt * vy + dt * dt / U(2.0) * ay;
+  nvx = vx + dt * ax;
+  nvy = vy + dt * ay;
 }
 
 // -------------------------------------------------------- interior kernel
@@ -414,14 +413,15 @@ __global__ void __launch_bounds__(TWL)
   using CD = typename CodecOf<ST>::type;
   using C = typename CD::C;
   using U = typename CD::U;
+  using Slot = typename CD::Slot;
   __shared__ C ex[3][X_N][TWL];
 
-  if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(s.counter, 1ull);
+  const int nxt = cur ^ 1;
+  if (blockIdx.x == 0 && threadIdx.x == 0) s.counter[nxt] = s.counter[cur] + 1ull;
   const int tix = tile_index(blockIdx.x, q);
   if (tix >= ntiles) return;
   const Tile t = tiles[tix];
   const PlateDev P = s.plates[t.plate];
-  const int nxt = cur ^ 1;
   const int lane = threadIdx.x;
   const int w = t.x1 - t.x0;
   int x = t.x0 - 1 + lane;
@@ -435,8 +435,8 @@ __global__ void __launch_bounds__(TWL)
   const bool owned = xok && lane >= 1 && lane <= w;
   const bool py = (P.periodic & 2) != 0;
 
-  // Source values of row y for this lane's column.
-  auto source = [&](int y, uint8_t &cl, C rho[2], C fs[2][5]) {
+  // Node of row y in this lane's column; false if there is none.
+  auto row_node = [&](int y, int64_t &k) -> bool {
     bool ok = xok;
     if (y < 0 || y >= P.ny) {
       if (py)
@@ -444,15 +444,43 @@ __global__ void __launch_bounds__(TWL)
       else
         ok = false;
     }
-    cl = 0;
-    if (ok) cl = s.cls[node_of(P, x, y)];
-    if (cl & CL_IN) {
-      const int64_t k = node_of(P, x, y);
-      collide<CD>(s, cur, 0, k, P, rho[0], fs[0]);
-      collide<CD>(s, cur, 1, k, P, rho[1], fs[1]);
-    } else {
+    k = node_of(P, x, y);
+    return ok;
+  };
+  auto load_cls = [&](int y) -> uint8_t {
+    int64_t k;
+    return row_node(y, k) ? s.cls[k] : (uint8_t)0;
+  };
+  // Raw populations of row y (only for body nodes: cl from load_cls).
+  auto load_raw = [&](int y, uint8_t cl, Slot raw[2][5]) {
+    int64_t k;
+    const bool ok = row_node(y, k) && (cl & CL_IN);
 #pragma unroll
-      for (int fl = 0; fl < 2; fl++) {
+    for (int fl = 0; fl < 2; fl++)
+#pragma unroll
+      for (int qq = 0; qq < 5; qq++) raw[fl][qq] = Slot(0);
+    if (ok) {
+      CD::load_raw(s, cur, 0, k, raw[0]);
+      CD::load_raw(s, cur, 1, k, raw[1]);
+    }
+  };
+  auto load_uv = [&](int y, uint8_t cl, U uv[4]) {
+    uv[0] = uv[1] = uv[2] = uv[3] = U(0);
+    if (owned && (cl & (CL_IN | CL_B)) == CL_IN) {
+      const int64_t k = node_of(P, x, y);
+      uv[0] = ldg<U>(s.u[cur][0], k);
+      uv[1] = ldg<U>(s.u[cur][1], k);
+      uv[2] = ldg<U>(s.v[cur][0], k);
+      uv[3] = ldg<U>(s.v[cur][1], k);
+    }
+  };
+  auto collide_row = [&](uint8_t cl, const Slot raw[2][5], C rho[2], C fs[2][5]) {
+#pragma unroll
+    for (int fl = 0; fl < 2; fl++) {
+      C f[5];
+      CD::raw_to_pops(P, fl, raw[fl], f);
+      collide_pops<CD>(P, fl, f, rho[fl], fs[fl]);
+      if (!(cl & CL_IN)) {
         rho[fl] = C(0);
 #pragma unroll
         for (int qq = 0; qq < 5; qq++) fs[fl][qq] = C(0);
@@ -468,18 +496,31 @@ __global__ void __launch_bounds__(TWL)
     ex[slot][X_F3_1][lane] = fs[1][3];
   };
 
-  C pr_rho[2], pr_f2[2];  // row r-1: zeroth moments and f*_2 (moving +y)
-  C cu_f0[2], cu_rho[2], cu_f2[2];
-  uint8_t cu_cl;
+  // Software pipeline over rows: while row r is finalized, the populations
+  // of row r+2, u and du/dt of row r+1 and the class bytes of row r+3 are
+  // in flight.
+  C pr_rho[2], pr_f2[2];                 // row r-1
+  C cu_rho[2], cu_f0[2], cu_f2[2];       // row r
+  uint8_t cu_cl, cl1, cl2, cl3;          // classes of rows r, r+1, r+2, r+3
+  Slot raw1[2][5];                       // populations of row r+1
+  U uv0[4];                              // u, du/dt of row r
   {
-    uint8_t cl;
+    const uint8_t clm = load_cls(t.y0 - 1);
+    cu_cl = load_cls(t.y0);
+    cl1 = load_cls(t.y0 + 1);
+    cl2 = load_cls(t.y0 + 2);
+    Slot raw[2][5];
     C rho[2], fs[2][5];
-    source(t.y0 - 1, cl, rho, fs);
+    load_raw(t.y0 - 1, clm, raw);
+    collide_row(clm, raw, rho, fs);
     pr_rho[0] = rho[0];
     pr_rho[1] = rho[1];
     pr_f2[0] = fs[0][2];
     pr_f2[1] = fs[1][2];
-    source(t.y0, cu_cl, rho, fs);
+    load_raw(t.y0, cu_cl, raw);
+    load_raw(t.y0 + 1, cl1, raw1);
+    load_uv(t.y0, cu_cl, uv0);
+    collide_row(cu_cl, raw, rho, fs);
     publish(0, rho, fs);
     cu_rho[0] = rho[0];
     cu_rho[1] = rho[1];
@@ -489,40 +530,40 @@ __global__ void __launch_bounds__(TWL)
     cu_f2[1] = fs[1][2];
   }
   int slot = 0;
-  const U dt = (U)P.dt;
-  const U h2 = U(2.0) * (U)P.dh;
-  const U cd2 = (U)P.cd2, cs2 = (U)P.cs2;
   for (int r = t.y0; r < t.y1; r++) {
     const int nslot = slot == 2 ? 0 : slot + 1;
-    const bool fin = owned && (cu_cl & (CL_IN | CL_B)) == CL_IN;
-    const int64_t k = node_of(P, x, r);
-    U ux = 0, uy = 0, vx = 0, vy = 0;
-    if (fin) {
-      ux = ldg<U>(s.u[cur][0], k);
-      uy = ldg<U>(s.u[cur][1], k);
-      vx = ldg<U>(s.v[cur][0], k);
-      vy = ldg<U>(s.v[cur][1], k);
+    // prefetch
+    const bool more = r + 2 <= t.y1;
+    cl3 = (r + 3 <= t.y1) ? load_cls(r + 3) : (uint8_t)0;
+    Slot raw2[2][5];
+    if (more) {
+      load_raw(r + 2, cl2, raw2);
+    } else {
+#pragma unroll
+      for (int fl = 0; fl < 2; fl++)
+#pragma unroll
+        for (int qq = 0; qq < 5; qq++) raw2[fl][qq] = Slot(0);
     }
-    uint8_t nx_cl;
+    U uv1[4];
+    load_uv(r + 1, (r + 1 < t.y1) ? cl1 : (uint8_t)0, uv1);
+    // collide row r+1 and hand its values to the x-neighbours
     C nx_rho[2], nx_fs[2][5];
-    source(r + 1, nx_cl, nx_rho, nx_fs);
+    collide_row(cl1, raw1, nx_rho, nx_fs);
     publish(nslot, nx_rho, nx_fs);
     __syncthreads();
+    const bool fin = owned && (cu_cl & (CL_IN | CL_B)) == CL_IN;
     if (fin) {
+      const int64_t k = node_of(P, x, r);
       const C wr0 = ex[slot][X_RHO0][lane - 1], er0 = ex[slot][X_RHO0][lane + 1];
       const C wr1 = ex[slot][X_RHO1][lane - 1], er1 = ex[slot][X_RHO1][lane + 1];
-      // Acceleration of eq. navier: c_d^2 grad phi - c_s^2 curl(psi e_z),
-      // with curl(psi e_z) = (d_y psi, -d_x psi).
-      const U dphix = ((U)er0 - (U)wr0) / h2;
-      const U dphiy = ((U)nx_rho[0] - (U)pr_rho[0]) / h2;
-      const U dpsix = ((U)er1 - (U)wr1) / h2;
-      const U dpsiy = ((U)nx_rho[1] - (U)pr_rho[1]) / h2;
-      const U ax = cd2 * dphix - cs2 * dpsiy;
-      const U ay = cd2 * dphiy - cs2 * (-dpsix);
-      stg<U>(s.u[nxt][0], k, ux + dt * vx + dt * dt / U(2.0) * ax);
-      stg<U>(s.u[nxt][1], k, uy + dt * vy + dt * dt / U(2.0) * ay);
-      stg<U>(s.v[nxt][0], k, vx + dt * ax);
-      stg<U>(s.v[nxt][1], k, vy + dt * ay);
+      U nux, nuy, nvx, nvy;
+      interior_update<U>(P, (U)er0, (U)wr0, (U)nx_rho[0], (U)pr_rho[0], (U)er1, (U)wr1,
+                         (U)nx_rho[1], (U)pr_rho[1], uv0[0], uv0[1], uv0[2], uv0[3], nux, nuy,
+                         nvx, nvy);
+      stg<U>(s.u[nxt][0], k, nux);
+      stg<U>(s.u[nxt][1], k, nuy);
+      stg<U>(s.v[nxt][0], k, nvx);
+      stg<U>(s.v[nxt][1], k, nvy);
       if (!(cu_cl & CL_S)) {
         // Pull: f_alpha(x, t+dt) = f*_alpha(x - c^alpha dt).
 #pragma unroll
@@ -547,100 +588,256 @@ __global__ void __launch_bounds__(TWL)
     cu_f0[1] = nx_fs[1][0];
     cu_f2[0] = nx_fs[0][2];
     cu_f2[1] = nx_fs[1][2];
-    cu_cl = nx_cl;
+    cu_cl = cl1;
+    cl1 = cl2;
+    cl2 = cl3;
+#pragma unroll
+    for (int fl = 0; fl < 2; fl++)
+#pragma unroll
+      for (int qq = 0; qq < 5; qq++) raw1[fl][qq] = raw2[fl][qq];
+#pragma unroll
+    for (int qq = 0; qq < 4; qq++) uv0[qq] = uv1[qq];
     slot = nslot;
   }
 }
 
 // ------------------------------------------- boundary / second-row kernel
 
-// Boundary reset value of field fl at boundary node (i, j): the field from
-// finite differences of u(t+dt) in buffer nb, the flux of the populations
-// stored at time t in buffer cb (eqs. psi_phi_at_bound, correction-f).
-template <class CD>
-__device__ void reset_state(const DevState &s, int cb, int nb, const PlateDev &P, int i, int j,
-                            typename CD::C rho[2], typename CD::C jx[2], typename CD::C jy[2]) {
-  using U = typename CD::U;
-  using C = typename CD::C;
-  U dv, cu;
-  div_curl<U>(s, nb, P, i, j, dv, cu);
-  const int64_t k = node_of(P, i, j);
-  rho[0] = (C)dv;
-  rho[1] = (C)cu;
-  CD::flux(s, cb, 0, k, P, jx[0], jy[0]);
-  CD::flux(s, cb, 1, k, P, jx[1], jy[1]);
+// Finite difference with a precomputed stencil code from the node's value
+// q0 and the values qa, qb of the further stencil nodes, branch-free:
+// ((c0 q0 + ca qa) + cb qb) * scale with the coefficients of the code
+// (central: qa - qb, one-sided 3-point: (-3 q0 + 4 qa) - qb and its mirror,
+// 2-point: qa - q0 and q0 - qa; these sums round exactly as the written-out
+// formulas); scale is 1/(2 dh) or 1/dh.
+template <class U>
+__device__ __forceinline__ U fd_vals(int code, U q0, U qa, U qb, const PlateDev &P) {
+  const bool cen = code == FD_CENTRAL, f3 = code == FD_FWD3, b3 = code == FD_BWD3;
+  const bool f2 = code == FD_FWD2, b2 = code == FD_BWD2;
+  const U c0 = f3 ? U(-3.0) : b3 ? U(3.0) : f2 ? U(-1.0) : b2 ? U(1.0) : U(0.0);
+  const U ca = (cen || f2) ? U(1.0) : f3 ? U(4.0) : b3 ? U(-4.0) : b2 ? U(-1.0) : U(0.0);
+  const U cb = (cen || f3) ? U(-1.0) : b3 ? U(1.0) : U(0.0);
+  const U sc = (f2 || b2) ? (U)P.inv_h : (cen || f3 || b3) ? (U)P.inv_2h : U(0.0);
+  return ((c0 * q0 + ca * qa) + cb * qb) * sc;
 }
 
+// Hooke's law (Sec. 2, eq. hooke) from a displacement gradient
+// g = (d_x u_x, d_y u_x, d_x u_y, d_y u_y).
+template <class U>
+__device__ __forceinline__ void hooke(const PlateDev &P, const U g[4], U &sxx, U &syy, U &sxy) {
+  const U exx = g[0], eyy = g[3];
+  const U exy = U(0.5) * (g[1] + g[2]);
+  const U tr = exx + eyy;
+  const U lam = (U)P.lam, mu = (U)P.mu;
+  sxx = lam * tr + U(2.0) * mu * exx;
+  syy = lam * tr + U(2.0) * mu * eyy;
+  sxy = U(2.0) * mu * exy;
+}
+
+// One block per chunk of boundary nodes (all of one plate).  Phase 1 puts
+// u(t+dt) of every node the chunk's stencils touch into LDS: boundary nodes
+// read it from buffer gb; with recompute set, interior nodes rebuild it from
+// the state at t (buffer cur) with the interior update (so this kernel does
+// not depend on the interior kernel of the same step); without, every node
+// reads buffer gb.  Phase 2 forms the finite-difference gradients of u.
+// Phase 3:
+//  - boundary tasks: if do_reset, the boundary reset of eqs.
+//    psi_phi_at_bound and correction-f into the populations of buffer
+//    cur ^ 1 (field from the gradient, flux of the populations of buffer
+//    cur); then the boundary acceleration of step n (eq. acc_dirichlet or
+//    eq. acc_neumann) from u, du/dt of buffer gb and its Newmark update
+//    (eq. integration) into buffer ub;
+//  - second-row tasks (do_reset only): the pull of eq. LBE_mod, where a
+//    population leaving a boundary node is collided from the average of its
+//    populations at t (buffer cur) and t+dt (the reset value).
+// n = counter[cslot] + step_off is the index of the step whose boundary
+// accelerations are computed.
 template <int ST>
-__global__ void __launch_bounds__(256)
-    k_post(DevState s, int nb, int ns, int cur, int do_bacc) {
+__global__ void __launch_bounds__(kBoundaryThreads)
+    k_boundary(DevState s, const Chunk *__restrict__ chunks, const UNode *__restrict__ un,
+               const GradNode *__restrict__ gn, const BTask *__restrict__ btask,
+               const STask *__restrict__ stask, int cur, int gb, int ub, int do_reset,
+               int recompute, int cslot, int step_off) {
   using CD = typename CodecOf<ST>::type;
   using C = typename CD::C;
   using U = typename CD::U;
-  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  using Slot = typename CD::Slot;
+  __shared__ U uu[kMaxU][2];
+  __shared__ U grad[kMaxGrad][4];
+  const Chunk ch = chunks[blockIdx.x];
+  const PlateDev P = s.plates[ch.plate];
   const int nxt = cur ^ 1;
-  if (tid < nb) {
-    const BndNode B = s.bnd[tid];
-    const PlateDev P = s.plates[B.plate];
-    C rho[2], jx[2], jy[2];
-    reset_state<CD>(s, cur, nxt, P, B.i, B.j, rho, jx, jy);
-    CD::store_eq(s, nxt, 0, B.node, P, rho[0], jx[0], jy[0]);
-    CD::store_eq(s, nxt, 1, B.node, P, rho[1], jx[1], jy[1]);
-    if (do_bacc) {
-      const unsigned long long n = *s.counter;  // steps completed = index of the next step
-      boundary_accel_update<U>(s, nxt, cur, B, P, n);
+  const int tid = threadIdx.x;
+  const int di[5] = {0, 1, 0, -1, 0};
+  const int dj[5] = {0, 0, 1, 0, -1};
+
+  // records and the state they point at
+  const int nb = ch.b1 - ch.b0;
+  const bool hasB = tid < nb;
+  const int st_ix = (tid - nb) >> 1, sfl = (tid - nb) & 1;  // second-row task and field
+  const bool hasS = do_reset && tid >= nb && ch.s0 + st_ix < ch.s1;
+  BTask T{};
+  STask Q{};
+  if (hasB) T = btask[ch.b0 + tid];
+  if (hasS) Q = stask[ch.s0 + st_ix];
+  const int64_t k = T.b.node;
+  U ux0 = 0, uy0 = 0, vx0 = 0, vy0 = 0;
+  C jxb[2] = {0, 0}, jyb[2] = {0, 0};
+  if (hasB) {
+    ux0 = ldg<U>(s.u[gb][0], k);
+    uy0 = ldg<U>(s.u[gb][1], k);
+    vx0 = ldg<U>(s.v[gb][0], k);
+    vy0 = ldg<U>(s.v[gb][1], k);
+    if (do_reset) {
+      CD::flux(s, cur, 0, k, P, jxb[0], jyb[0]);
+      CD::flux(s, cur, 1, k, P, jxb[1], jyb[1]);
     }
-  } else if (tid < nb + ns) {
-    const SecNode S = s.sec[tid - nb];
-    const PlateDev P = s.plates[S.plate];
-    const int di[5] = {0, 1, 0, -1, 0};
-    const int dj[5] = {0, 0, 1, 0, -1};
-    C fo[2][5];
+  }
+  Slot raw[5][5];
+#pragma unroll
+  for (int al = 0; al < 5; al++)
+#pragma unroll
+    for (int qq = 0; qq < 5; qq++) raw[al][qq] = Slot(0);
+  if (hasS) {
 #pragma unroll
     for (int al = 0; al < 5; al++) {
-      // upwind node x - c^alpha dt (always in the body: x is interior)
-      const int yi = wrapc(S.i - di[al], P.nx), yj = wrapc(S.j - dj[al], P.ny);
-      const int64_t ky = node_of(P, yi, yj);
-      if (s.cls[ky] & CL_B) {
-        // eq. LBE_mod: time-averaged boundary populations, collided with the
-        // equilibrium of their own moments.
-        C rho[2], jx[2], jy[2];
-        reset_state<CD>(s, cur, nxt, P, yi, yj, rho, jx, jy);
+      // upwind node x - c^alpha dt (in the body: x is interior)
+      const int64_t ky = node_of(P, wrapc(Q.i - di[al], P.nx), wrapc(Q.j - dj[al], P.ny));
+      CD::load_raw(s, cur, sfl, ky, raw[al]);
+    }
+  }
+
+  // phase 1: u(t+dt) of the displacement nodes
+  for (int g = ch.u0 + tid; g < ch.u1; g += kBoundaryThreads) {
+    const UNode N = un[g];
+    U nux, nuy;
+    if (N.bnd || !recompute) {
+      nux = ldg<U>(s.u[gb][0], N.node);
+      nuy = ldg<U>(s.u[gb][1], N.node);
+    } else {
+      C rho[4][2];
+#pragma unroll
+      for (int d = 0; d < 4; d++) {
+        const int64_t kn = node_of(P, wrapc(N.i + di[d + 1], P.nx), wrapc(N.j + dj[d + 1], P.ny));
 #pragma unroll
         for (int fl = 0; fl < 2; fl++) {
-          C fnew[5], fold[5], fh[5];
-          CD::eq_pops(P, fl, rho[fl], jx[fl], jy[fl], fnew);
-          CD::load(s, cur, fl, ky, P, fold);
-#pragma unroll
-          for (int qq = 0; qq < 5; qq++) fh[qq] = C(0.5) * (fnew[qq] + fold[qq]);
-          const C r = fh[0] + ((fh[1] + fh[3]) + (fh[2] + fh[4]));
-          C e[5];
-          eq_populations<C>(CD::a0w(P, fl), CD::aw(P, fl), r, fh[1] - fh[3], fh[2] - fh[4], e);
-          fo[fl][al] = fh[al] - C(2.0) * (fh[al] - e[al]);
-        }
-      } else {
-#pragma unroll
-        for (int fl = 0; fl < 2; fl++) {
-          C r, fs[5];
-          collide<CD>(s, cur, fl, ky, P, r, fs);
-          fo[fl][al] = fs[al];
+          Slot rw[5];
+          C f[5];
+          CD::load_raw(s, cur, fl, kn, rw);
+          CD::raw_to_pops(P, fl, rw, f);
+          rho[d][fl] = f[0] + ((f[1] + f[3]) + (f[2] + f[4]));
         }
       }
+      U nvx, nvy;
+      // neighbour order d: E, N, W, S
+      interior_update<U>(P, (U)rho[0][0], (U)rho[2][0], (U)rho[1][0], (U)rho[3][0], (U)rho[0][1],
+                         (U)rho[2][1], (U)rho[1][1], (U)rho[3][1], ldg<U>(s.u[cur][0], N.node),
+                         ldg<U>(s.u[cur][1], N.node), ldg<U>(s.v[cur][0], N.node),
+                         ldg<U>(s.v[cur][1], N.node), nux, nuy, nvx, nvy);
     }
-    CD::store(s, nxt, 0, S.node, P, fo[0]);
-    CD::store(s, nxt, 1, S.node, P, fo[1]);
+    uu[g - ch.u0][0] = nux;
+    uu[g - ch.u0][1] = nuy;
   }
-}
+  __syncthreads();
 
-// Boundary accelerations of the first step (before any k_post has run).
-template <int ST>
-__global__ void __launch_bounds__(256) k_bacc0(DevState s, int nb) {
-  using U = typename CodecOf<ST>::type::U;
-  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid >= nb) return;
-  const BndNode B = s.bnd[tid];
-  const PlateDev P = s.plates[B.plate];
-  boundary_accel_update<U>(s, 0, 1, B, P, *s.counter);
+  // phase 2: gradients (d_x u_x, d_y u_x, d_x u_y, d_y u_y)
+  for (int g = ch.g0 + tid; g < ch.g1; g += kBoundaryThreads) {
+    const GradNode G = gn[g];
+    const int cx = G.code & 7, cy = (G.code >> 3) & 7;
+    U *d = grad[g - ch.g0];
+#pragma unroll
+    for (int c = 0; c < 2; c++) {
+      const U q0 = uu[G.u[0]][c];
+      d[2 * c + 0] = fd_vals<U>(cx, q0, uu[G.u[1]][c], uu[G.u[2]][c], P);
+      d[2 * c + 1] = fd_vals<U>(cy, q0, uu[G.u[3]][c], uu[G.u[4]][c], P);
+    }
+  }
+  __syncthreads();
+
+  // phase 3a: boundary task
+  if (hasB) {
+    const BndNode &B = T.b;
+    const U *gs = grad[T.g[0]];
+    if (do_reset) {
+      // div u and (curl u).e_z at the node
+      const U dv = gs[0] + gs[3];
+      const U cu = gs[2] - gs[1];
+      CD::store_eq(s, nxt, 0, k, P, (C)dv, jxb[0], jyb[0]);
+      CD::store_eq(s, nxt, 1, k, P, (C)cu, jxb[1], jyb[1]);
+    }
+    const unsigned long long n = s.counter[cslot] + (unsigned long long)step_off;
+    const U dt = (U)P.dt;
+    U ax, ay;
+    if (B.kind == LBM_BC_DIRICHLET) {
+      const double g = load_amp(s, B.load, (double)(n + 1) * P.dt);
+      const U usx = (U)(g * B.val[0]), usy = (U)(g * B.val[1]);
+      ax = U(2.0) / (dt * dt) * (usx - ux0) - U(2.0) / dt * vx0;
+      ay = U(2.0) / (dt * dt) * (usy - uy0) - U(2.0) / dt * vy0;
+    } else {
+      const double g = load_amp(s, B.load, (double)n * P.dt);
+      const U V = (U)B.cell[0], lE = (U)B.cell[1], lN = (U)B.cell[2], lW = (U)B.cell[3],
+              lS = (U)B.cell[4];
+      U sxx, syy, sxy, rxx, ryy, rxy;
+      hooke<U>(P, gs, sxx, syy, sxy);
+      U tEx = 0, tEy = 0, tWx = 0, tWy = 0, tNx = 0, tNy = 0, tSx = 0, tSy = 0;
+      // sigma_kr n_kr l_kr with sigma_kr the mean of the nodal stresses
+      if (T.g[1] >= 0) {
+        hooke<U>(P, grad[T.g[1]], rxx, ryy, rxy);
+        tEx = U(0.5) * (sxx + rxx) * lE;
+        tEy = U(0.5) * (sxy + rxy) * lE;
+      }
+      if (T.g[3] >= 0) {
+        hooke<U>(P, grad[T.g[3]], rxx, ryy, rxy);
+        tWx = -(U(0.5) * (sxx + rxx)) * lW;
+        tWy = -(U(0.5) * (sxy + rxy)) * lW;
+      }
+      if (T.g[2] >= 0) {
+        hooke<U>(P, grad[T.g[2]], rxx, ryy, rxy);
+        tNx = U(0.5) * (sxy + rxy) * lN;
+        tNy = U(0.5) * (syy + ryy) * lN;
+      }
+      if (T.g[4] >= 0) {
+        hooke<U>(P, grad[T.g[4]], rxx, ryy, rxy);
+        tSx = -(U(0.5) * (sxy + rxy)) * lS;
+        tSy = -(U(0.5) * (syy + ryy)) * lS;
+      }
+      const U Fx = (U)(g * B.val[0]), Fy = (U)(g * B.val[1]);
+      const U m = (U)P.rho_m * V;
+      ax = (((tEx + tWx) + (tNx + tSx)) + Fx) / m;
+      ay = (((tEy + tWy) + (tNy + tSy)) + Fy) / m;
+    }
+    const U nux = ux0 + dt * vx0 + dt * dt / U(2.0) * ax;
+    const U nuy = uy0 + dt * vy0 + dt * dt / U(2.0) * ay;
+    stg<U>(s.u[ub][0], k, nux);
+    stg<U>(s.u[ub][1], k, nuy);
+    stg<U>(s.v[ub][0], k, vx0 + dt * ax);
+    stg<U>(s.v[ub][1], k, vy0 + dt * ay);
+    if (!(fabs((double)nux) < 1e30) || !(fabs((double)nuy) < 1e30)) s.flag[0] = 1;
+  }
+
+  // phase 3b: second-row task, one field per thread
+  if (hasS) {
+    const int fl = sfl;
+    C fo[5];
+#pragma unroll
+    for (int al = 0; al < 5; al++) {
+      C f[5], r, fs[5];
+      CD::raw_to_pops(P, fl, raw[al], f);
+      if (Q.g[al] >= 0) {
+        // eq. LBE_mod: average of the populations at t and of the reset
+        // values at t+dt, collided with the equilibrium of their own moments
+        const U *gy = grad[Q.g[al]];
+        const C fld = fl == 0 ? (C)(gy[0] + gy[3]) : (C)(gy[2] - gy[1]);
+        C fnew[5], jx, jy;
+        CD::raw_flux(raw[al], jx, jy);
+        CD::eq_pops(P, fl, fld, jx, jy, fnew);
+#pragma unroll
+        for (int qq = 0; qq < 5; qq++) f[qq] = C(0.5) * (fnew[qq] + f[qq]);
+      }
+      collide_pops<CD>(P, fl, f, r, fs);
+      fo[al] = fs[al];
+    }
+    CD::store(s, nxt, fl, Q.node, P, fo);
+  }
 }
 
 // Periodic synchronization (Sec. 3.2): at every body node the fields become
@@ -808,20 +1005,15 @@ hipError_t launch_interior(int st, const DevState &s, const Tile *tiles, int nti
   return hipSuccess;
 }
 
-hipError_t launch_post(int st, const DevState &s, int nb, int ns, int cur, int do_bacc,
-                       hipStream_t stream) {
-  const int n = nb + ns;
-  if (n <= 0) return hipSuccess;
-  const dim3 grid((n + 255) / 256);
-  LBM_DISPATCH(st, hipLaunchKernelGGL((k_post<ST>), grid, dim3(256), 0, stream, s, nb, ns, cur,
-                                      do_bacc));
-  return hipGetLastError();
-}
-
-hipError_t launch_bacc0(int st, const DevState &s, int nb, hipStream_t stream) {
-  if (nb <= 0) return hipSuccess;
-  const dim3 grid((nb + 255) / 256);
-  LBM_DISPATCH(st, hipLaunchKernelGGL((k_bacc0<ST>), grid, dim3(256), 0, stream, s, nb));
+hipError_t launch_boundary(int st, const DevState &s, const Chunk *chunks, int nchunks,
+                           const UNode *un, const GradNode *gn, const BTask *bt, const STask *stk,
+                           int cur, int gb, int ub, int do_reset, int recompute, int cslot,
+                           int step_off, hipStream_t stream) {
+  if (nchunks <= 0) return hipSuccess;
+  LBM_DISPATCH(st, hipLaunchKernelGGL((k_boundary<ST>), dim3(nchunks), dim3(kBoundaryThreads), 0,
+                                      stream, s,
+                                      chunks, un, gn, bt, stk, cur, gb, ub, do_reset, recompute,
+                                      cslot, step_off));
   return hipGetLastError();
 }
 

@@ -33,6 +33,7 @@ struct PlateDev {
   int32_t nx, ny, pitch;
   int32_t periodic;  // bit 0: x wraps, bit 1: y wraps
   double dt, dh, cd2, cs2, rho_m, lam, mu;
+  double inv_h, inv_2h;  // 1/dh and 1/(2 dh)
   double a[2], a0[2];    // equilibrium weights per field (phi, psi)
   float af[2], a0f[2];   // the same in FP32
   float scale[2];        // 16-bit storage scale of the deviation moments
@@ -62,6 +63,66 @@ struct SecNode {
   int32_t plate, i, j;
 };
 
+// Finite-difference stencil along one axis at a node (the per-axis rule of
+// the boundary finite differences): central, one-sided 3-point second order
+// forwards / backwards, 2-point first order forwards / backwards, none.
+enum { FD_NONE = 0, FD_CENTRAL = 1, FD_FWD3 = 2, FD_BWD3 = 3, FD_FWD2 = 4, FD_BWD2 = 5 };
+
+constexpr int kChunkNodes = 64;    // boundary nodes per boundary-kernel block (at most)
+constexpr int kBoundaryThreads = 256;  // threads per boundary-kernel block
+constexpr int kMaxGrad = 1024;     // gradient nodes per boundary-kernel block
+constexpr int kMaxU = 1024;        // displacement nodes per boundary-kernel block
+
+// A node whose u(t+dt) a boundary-kernel block needs.  bnd: it is a
+// boundary node (its u(t+dt) is in the state); otherwise it is an interior
+// node and the block recomputes u(t+dt) from the state at t exactly as the
+// interior kernel does.
+struct UNode {
+  int64_t node;
+  int32_t i, j;
+  int32_t bnd;
+  int32_t pad;
+};
+
+// A body node where a boundary-kernel block needs the finite-difference
+// gradient of u.  code: x stencil in bits 0..2, y stencil in bits 3..5;
+// u: block-local UNode indices of the node itself, of the two further nodes
+// of its x stencil and of the two further nodes of its y stencil (the node
+// itself where a stencil uses fewer).
+struct GradNode {
+  int32_t code;
+  int32_t u[5];
+};
+
+// Work of one boundary-kernel block (all of one plate): displacement nodes
+// [u0, u1), gradient nodes [g0, g1), boundary tasks [b0, b1), second-row
+// tasks [s0, s1).  Thread t < b1 - b0 runs boundary task b0 + t; the next
+// 2 (s1 - s0) threads run the second-row tasks, one field each.
+struct Chunk {
+  int32_t u0, u1, g0, g1, b0, b1, s0, s1;
+  int32_t plate;
+  int32_t pad[3];
+};
+
+// Boundary task: the boundary record of the node and the block-local
+// gradient indices of the node itself and of its E, N, W, S neighbours
+// (-1 where the neighbour is not in the body).
+struct BTask {
+  BndNode b;
+  int32_t g[5];
+  int32_t pad[3];
+};
+
+// Second-row task: the node and, per lattice direction alpha, the
+// block-local gradient index of the upwind node x - c^alpha if that node is
+// a boundary node (-1 otherwise).
+struct STask {
+  int64_t node;
+  int32_t i, j;
+  int32_t g[5];
+  int32_t pad[3];
+};
+
 // Piecewise linear amplitude g(t).
 struct LoadTable {
   int32_t n;
@@ -83,7 +144,10 @@ struct DevState {
   const LoadTable *loads;
   const BndNode *bnd;
   const SecNode *sec;
-  unsigned long long *counter;  // completed steps (device side)
+  // Step counters, one per buffer parity: during step n (buffer cur = n & 1)
+  // counter[cur] holds n; the interior kernel of step n writes n + 1 into
+  // counter[cur ^ 1].
+  unsigned long long *counter;
   int *flag;                    // nonzero once a non-finite / blown-up u is seen
 };
 
