@@ -118,6 +118,8 @@ def main():
 
     def timed_run(storage):
         ctx = lbm.context_for(case, storage)
+        ctx.step(2)
+        ctx.autotune(5)  # tile shape and packing order of the interior kernel
         ctx.step(W)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -183,7 +185,8 @@ def main():
                                "free), nu 0.3, a0_phi 0.9999, Gaussian pulse sigma 16 amp 1e-3, "
                                "sync every 50, FP64 populations and u",
                    "nodes": nodes, "storage": args.storage, "tile": [info["tile_lanes"],
-                                                              info["tile_rows"]],
+                                                              info["tile_rows"],
+                                                              info["tile_order"]],
                    "graphs": True},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -170,20 +170,25 @@ typedef struct {
   int32_t n_plates;
   int32_t storage;
   int32_t tile_lanes, tile_rows; /* interior-kernel tile: lanes per workgroup, rows        */
+  int32_t tile_order;         /* interior-tile packing order (see lbm_set_tiling)           */
   int32_t n_tiles;
 } lbm_info_t;
 lbm_status lbm_info(const lbm_ctx *ctx, lbm_info_t *info);
 
-/* Interior-kernel tile shape: lanes per workgroup (64, 128 or 256; the tile
- * owns lanes-2 columns) and rows per tile (>= 1).  May be changed between
- * steps; invalidates captured step graphs. */
-lbm_status lbm_set_tiling(lbm_ctx *ctx, int32_t lanes, int32_t rows);
+/* Interior-kernel tiling: lanes per workgroup (64, 128 or 256; a tile owns
+ * lanes-2 columns), rows per tile (>= 1) and packing order of the tile list
+ * (0: plate by plate, row band by row band; 1: plate by plate, column strip
+ * by column strip; 2: as 0 with the largest plates first).  May be changed
+ * between steps; invalidates captured step graphs. */
+lbm_status lbm_set_tiling(lbm_ctx *ctx, int32_t lanes, int32_t rows, int32_t order);
 
-/* Time every tile shape in a small candidate set on this context's plates
- * (each candidate runs `steps` steps after one warm-up step on a copy of the
- * state, which is restored afterwards) and keep the fastest.  Results are
- * cached per (storage, plate-size bucket) for the life of the process.
- * best_ms (nullable) receives the fastest time per step. */
+/* Autotuner: time the interior kernel for every tiling of a candidate set
+ * (lanes x rows x packing order) on this context's plates, `steps` launches
+ * each, and keep the fastest.  The interior kernel leaves the state
+ * unchanged when repeated, so the state is not disturbed.  Results are
+ * cached per (storage, single/multiple plates, size bucket) for the life of
+ * the process and picked up by later contexts.  best_ms (nullable) receives
+ * the fastest time per launch. */
 lbm_status lbm_autotune(lbm_ctx *ctx, int32_t steps, double *best_ms);
 
 /* Run n_steps steps eagerly (no graph), with a HIP event recorded on the

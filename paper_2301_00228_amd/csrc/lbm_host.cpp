@@ -73,7 +73,7 @@ size_t slot_bytes(int st) {
 size_t uv_bytes(int st) { return st == LBM_STORE_F32 ? 4 : 8; }
 
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int>, std::pair<int, int>> g_tune_cache;
+std::map<std::tuple<int, int, int>, std::tuple<int, int, int>> g_tune_cache;
 
 }  // namespace
 
@@ -107,7 +107,7 @@ struct lbm_ctx {
   STask *d_stasks = nullptr;
   std::vector<LoadTable> loads;
   std::vector<Tile> tiles;
-  int lanes = 128, rows = 32;
+  int lanes = 128, rows = 32, order = 0;
 
   std::vector<Buffer> bufs;
   DevState ds{};
@@ -474,24 +474,41 @@ bool build_boundary_tables(lbm_ctx *c, std::string &why) {
   return true;
 }
 
+// Interior tiles: per plate, column strips of at most lanes-2 columns (of
+// equal width) times row bands of `rows` rows.  order 0: plate by plate, band
+// by band (strips of a band adjacent); 1: plate by plate, strip by strip
+// (bands of a strip adjacent); 2: as 0 with the plates by decreasing size.
+// Consecutive tiles land on the same XCD (see k_interior), so the order
+// decides which halo rows / columns share an L2.
 void build_tiles(lbm_ctx *c) {
   c->tiles.clear();
   const int own = c->lanes - 2;
-  for (size_t p = 0; p < c->ph.size(); p++) {
+  std::vector<int> plates(c->ph.size());
+  for (size_t p = 0; p < plates.size(); p++) plates[p] = (int)p;
+  if (c->order == 2)
+    std::stable_sort(plates.begin(), plates.end(), [&](int a, int b) {
+      return (int64_t)c->ph[a].nx * c->ph[a].ny > (int64_t)c->ph[b].nx * c->ph[b].ny;
+    });
+  for (int p : plates) {
     const PlateHost &h = c->ph[p];
     const int ns = (h.nx + own - 1) / own;
     const int w = (h.nx + ns - 1) / ns;
-    for (int y0 = 0; y0 < h.ny; y0 += c->rows) {
-      const int y1 = std::min(h.ny, y0 + c->rows);
-      for (int s = 0; s < ns; s++) {
-        Tile t{};
-        t.plate = (int)p;
-        t.x0 = s * w;
-        t.x1 = std::min(h.nx, (s + 1) * w);
-        t.y0 = y0;
-        t.y1 = y1;
-        if (t.x1 > t.x0) c->tiles.push_back(t);
-      }
+    const int nb = (h.ny + c->rows - 1) / c->rows;
+    auto add = [&](int s, int b) {
+      Tile t{};
+      t.plate = p;
+      t.x0 = s * w;
+      t.x1 = std::min(h.nx, (s + 1) * w);
+      t.y0 = b * c->rows;
+      t.y1 = std::min(h.ny, (b + 1) * c->rows);
+      if (t.x1 > t.x0) c->tiles.push_back(t);
+    };
+    if (c->order == 1) {
+      for (int s = 0; s < ns; s++)
+        for (int b = 0; b < nb; b++) add(s, b);
+    } else {
+      for (int b = 0; b < nb; b++)
+        for (int s = 0; s < ns; s++) add(s, b);
     }
   }
 }
@@ -929,8 +946,9 @@ lbm_status lbm_create(const lbm_plate *plates, int32_t n_plates, lbm_storage sto
                                (int)std::lround(std::log2((double)std::max<int64_t>(1, c->n_body))));
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
-      c->lanes = it->second.first;
-      c->rows = it->second.second;
+      c->lanes = std::get<0>(it->second);
+      c->rows = std::get<1>(it->second);
+      c->order = std::get<2>(it->second);
     } else {
       c->lanes = 256;
       c->rows = 64;
@@ -1089,17 +1107,20 @@ lbm_status lbm_info(const lbm_ctx *c, lbm_info_t *info) {
   info->storage = c->storage;
   info->tile_lanes = c->lanes;
   info->tile_rows = c->rows;
+  info->tile_order = c->order;
   info->n_tiles = (int32_t)c->tiles.size();
   return LBM_OK;
 }
 
-lbm_status lbm_set_tiling(lbm_ctx *c, int32_t lanes, int32_t rows) {
+lbm_status lbm_set_tiling(lbm_ctx *c, int32_t lanes, int32_t rows, int32_t order) {
   if (!c) return LBM_E_INVAL;
-  if ((lanes != 64 && lanes != 128 && lanes != 256) || rows < 1 || rows > 65536)
-    return fail(c, LBM_E_INVAL, "lanes must be 64, 128 or 256 and rows >= 1");
+  if ((lanes != 64 && lanes != 128 && lanes != 256) || rows < 1 || rows > 65536 || order < 0 ||
+      order > 2)
+    return fail(c, LBM_E_INVAL, "lanes must be 64, 128 or 256, rows >= 1, order 0..2");
   HIP_TRY(c, hipStreamSynchronize(c->stream), "synchronize");
   c->lanes = lanes;
   c->rows = rows;
+  c->order = order;
   build_tiles(c);
   lbm_status st = upload_tiles(c);
   if (st) return st;
@@ -1145,17 +1166,20 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
   if (st) return st;
   HIP_TRY(c, hipStreamSynchronize(c->stream), "synchronize");
   const int lane_set[3] = {64, 128, 256};
-  const int row_set[5] = {8, 16, 32, 64, 128};
+  const int row_set[6] = {4, 8, 16, 32, 64, 128};
+  const int n_orders = c->ph.size() > 1 ? 3 : 2;
   hipEvent_t e0, e1;
   HIP_TRY(c, hipEventCreate(&e0), "event");
   HIP_TRY(c, hipEventCreate(&e1), "event");
   const int cur = (int)(c->step & 1);
   double best = 1e300;
-  int bl = c->lanes, br = c->rows;
+  int bl = c->lanes, br = c->rows, bo = c->order;
+  for (int O = 0; O < n_orders; O++)
   for (int L : lane_set)
     for (int R : row_set) {
       c->lanes = L;
       c->rows = R;
+      c->order = O;
       build_tiles(c);
       if (upload_tiles(c) != LBM_OK) continue;
       // The interior kernel reads buffer cur and writes only interior nodes
@@ -1175,12 +1199,14 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
         best = per;
         bl = L;
         br = R;
+        bo = O;
       }
     }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   c->lanes = bl;
   c->rows = br;
+  c->order = bo;
   build_tiles(c);
   st = upload_tiles(c);
   if (st) return st;
@@ -1189,7 +1215,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto key = std::make_tuple(c->storage, c->ph.size() > 1 ? 1 : 0,
                                (int)std::lround(std::log2((double)std::max<int64_t>(1, c->n_body))));
-    g_tune_cache[key] = {bl, br};
+    g_tune_cache[key] = {bl, br, bo};
   }
   if (best_ms) *best_ms = best;
   return LBM_OK;

@@ -271,3 +271,34 @@ def strip_with_holes(nx=65536, ny=2048, area_frac=0.05, nu=0.3, a0_phi=0.9999, s
                 lam=lame_lambda(nu), mu=1.0, rho=1.0, dh=1.0, dt=time_step(nu, a0_phi),
                 sync_every=sync_every, u0=u0, v0=np.zeros_like(u0), e0=None, w0=None, bcs=bcs,
                 steps=steps, nu=nu, a0_phi=a0_phi)
+
+
+def mixed_plate(nx, ny, rng, nu=0.3, a0_phi=0.9999, steps=2000, sync_every=50, sigma=32.0,
+                amp=1e-3, name="plate", with_v0=False):
+    """Rectangular plate, each edge Dirichlet (u* = 0) or traction free with
+    probability 1/2, one seeded pulse."""
+    edges = [e for e in (LEFT, RIGHT, BOTTOM, TOP) if rng.random() < 0.5]
+    lo = 6 * sigma
+    cx = rng.uniform(lo, nx - 1 - lo)
+    cy = rng.uniform(lo, ny - 1 - lo)
+    theta = rng.uniform(0, 2 * np.pi)
+    u0 = gaussian_pulse(nx, ny, cx, cy, sigma, amp, theta)
+    bc = dirichlet_edges_bc(nx, ny, edges)
+    bcs = [bc] if bc is not None else []
+    _clear_dirichlet(u0, bcs)
+    return Case(name=name, nx=nx, ny=ny, mask=None, periodic=(False, False),
+                lam=lame_lambda(nu), mu=1.0, rho=1.0, dh=1.0, dt=time_step(nu, a0_phi),
+                sync_every=sync_every, u0=u0, v0=np.zeros_like(u0) if with_v0 else None, e0=None,
+                w0=None, bcs=bcs, steps=steps, nu=nu, a0_phi=a0_phi)
+
+
+def large_batch(count=64, side=4096, strip=(65536, 2048), steps=2000, seed_index=4):
+    """count plates of side x side (mixed edges, one pulse each, sigma 32)
+    plus one strip with seeded elliptic holes; v0 = 0 (not materialized)."""
+    rng = rng_for(seed_index)
+    cases = [mixed_plate(side, side, rng, steps=steps, name=f"sq{k}") for k in range(count)]
+    if strip is not None:
+        st = strip_with_holes(nx=strip[0], ny=strip[1], steps=steps, seed_index=seed_index)
+        st.v0 = None
+        cases.append(st)
+    return cases

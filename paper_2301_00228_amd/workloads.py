@@ -1,0 +1,123 @@
+"""Runs of the large workloads: throughput (GLUPS, fraction of the HBM
+roofline) and the error of the reduced storages against the FP64 path.
+
+    python -m paper_2301_00228_amd.workloads hole8192 --storage f16dev
+    python -m paper_2301_00228_amd.workloads batch256 --storage f32dev
+    python -m paper_2301_00228_amd.workloads large --storage f16dev
+
+Prints one JSON line per run.  Every input is synthetic and seeded
+(``inputs``); the state stays in HBM during the timed steps.
+"""
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+from . import inputs, lbm
+
+HBM_PEAK_GBS = 8000.0
+
+
+def cases_for(name, steps):
+    if name == "hole8192":
+        return [inputs.plate_with_hole(n=8192, radius=1024, steps=steps)]
+    if name == "batch256":
+        return inputs.plate_batch(count=256, steps=steps)
+    if name == "large":
+        return inputs.large_batch(steps=steps)
+    if name == "clamped1024":
+        return [inputs.clamped_plate(n=1024, steps=steps)]
+    raise ValueError(name)
+
+
+def rel_l2(a, b):
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+def timed(cases, storage, steps, warmup, tune=True):
+    import torch
+    t0 = time.perf_counter()
+    ctx = lbm.context_for(cases, storage)
+    setup = time.perf_counter() - t0
+    print(f"context {storage}: {setup:.1f} s", file=sys.stderr, flush=True)
+    ctx.step(2)
+    if tune:
+        ctx.autotune(3)
+        print("tuned", ctx.info()["tile_lanes"], ctx.info()["tile_rows"], file=sys.stderr,
+              flush=True)
+    ctx.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    info = ctx.info()
+    prof = ctx.profile(3)
+    i_ms, i_n = prof["interior"]
+    b_ms, b_n = prof["boundary"]
+    per = i_ms / i_n / 1e3
+    nodes = info["nodes_in_body"]
+    achieved = nodes * info["bytes_per_update"] / per / 1e9
+    res = {"storage": storage, "plates": info["n_plates"], "nodes": nodes, "steps": steps,
+           "glups": nodes * steps / dt / 1e9, "ms_per_step": dt / steps * 1e3,
+           "interior_us": per * 1e6, "interior_GBs": achieved,
+           "interior_frac": achieved / HBM_PEAK_GBS, "boundary_us": b_ms / max(b_n, 1) * 1e3,
+           "bytes_per_lup": info["bytes_per_update"], "boundary_nodes": info["boundary_nodes"],
+           "tile": [info["tile_lanes"], info["tile_rows"], info["tile_order"]],
+           "device_GB": info["device_bytes"] / 1e9, "setup_s": setup}
+    return ctx, res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("workload", choices=["hole8192", "batch256", "large", "clamped1024"])
+    ap.add_argument("--storage", default="f16dev")
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--ref", default="f64",
+                    help="storage of the reference run for the error ('' = no error)")
+    ap.add_argument("--ref-plates", type=int, default=0,
+                    help="compare only the first N plates and the last one (0 = all)")
+    args = ap.parse_args()
+
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    print(f"building {args.workload}", file=sys.stderr, flush=True)
+    cases = cases_for(args.workload, args.warmup + args.steps)
+    ctx, res = timed(cases, args.storage, args.steps, args.warmup)
+    res["workload"] = args.workload
+    print(json.dumps(res), flush=True)
+    if args.ref:
+        # Reference and reduced run plate by plate from t = 0 for the same
+        # number of steps (bounds memory: the FP64 state of the whole batch
+        # may not fit next to the reduced one).
+        ctx.close()
+        del ctx
+        picks = list(range(len(cases)))
+        if args.ref_plates and len(cases) > args.ref_plates + 1:
+            picks = list(range(args.ref_plates)) + [len(cases) - 1]
+        n_total = args.warmup + args.steps
+        worst = {"e": 0.0, "omega": 0.0, "u": 0.0}
+        per_plate = []
+        for p in picks:
+            outs = {}
+            for st in (args.ref, args.storage):
+                with lbm.context_for([cases[p]], st) as c:
+                    c.step(n_total)
+                    outs[st] = c.fields(0, want=("e", "omega", "u"))
+            errs = {k: rel_l2(outs[args.storage][k], outs[args.ref][k]) for k in worst}
+            for k in worst:
+                worst[k] = max(worst[k], errs[k])
+            per_plate.append((cases[p].name, errs))
+            print(f"plate {cases[p].name}: {errs}", file=sys.stderr, flush=True)
+        print(json.dumps({"workload": args.workload, "storage": args.storage, "ref": args.ref,
+                          "steps": n_total, "plates_compared": len(picks),
+                          "max_rel_l2": worst}), flush=True)
+
+
+if __name__ == "__main__":
+    main()
