@@ -184,9 +184,9 @@ def main():
         "config": {"workload": "clamped plate 1024x1024 (left edge u*=0, other edges traction "
                                "free), nu 0.3, a0_phi 0.9999, Gaussian pulse sigma 16 amp 1e-3, "
                                "sync every 50, FP64 populations and u",
-                   "nodes": nodes, "storage": args.storage, "tile": [info["tile_lanes"],
-                                                              info["tile_rows"],
-                                                              info["tile_order"]],
+                   "nodes": nodes, "storage": args.storage,
+                   "tile": [info["tile_lanes"], info["tile_rows"], info["tile_order"],
+                            info["tile_edge_rows"]],
                    "graphs": True},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -171,24 +171,32 @@ typedef struct {
   int32_t storage;
   int32_t tile_lanes, tile_rows; /* interior-kernel tile: lanes per workgroup, rows        */
   int32_t tile_order;         /* interior-tile packing order (see lbm_set_tiling)           */
+  int32_t tile_edge_rows;     /* rows of the tiles that carry boundary work                 */
   int32_t n_tiles;
 } lbm_info_t;
 lbm_status lbm_info(const lbm_ctx *ctx, lbm_info_t *info);
 
 /* Interior-kernel tiling: lanes per workgroup (64, 128 or 256; a tile owns
- * lanes-2 columns), rows per tile (>= 1) and packing order of the tile list
+ * lanes-2 columns), rows per tile (>= 1), packing order of the tile list
  * (0: plate by plate, row band by row band; 1: plate by plate, column strip
- * by column strip; 2: as 0 with the largest plates first).  May be changed
- * between steps; invalidates captured step graphs. */
-lbm_status lbm_set_tiling(lbm_ctx *ctx, int32_t lanes, int32_t rows, int32_t order);
+ * by column strip; 2: as 0 with the largest plates first) and edge_rows, the
+ * rows of the tiles whose area or one-node halo ring holds boundary or
+ * second-row nodes (those tiles finish the previous step's boundary work
+ * before their march; 0 or >= rows: no shorter tiles).  Any tiling gives
+ * bitwise the same results.  May be changed between steps; invalidates
+ * captured step graphs.  LBM_E_INVAL on values out of range. */
+lbm_status lbm_set_tiling(lbm_ctx *ctx, int32_t lanes, int32_t rows, int32_t order,
+                          int32_t edge_rows);
 
-/* Autotuner: time the interior kernel for every tiling of a candidate set
- * (lanes x rows x packing order) on this context's plates, `steps` launches
- * each, and keep the fastest.  The interior kernel leaves the state
- * unchanged when repeated, so the state is not disturbed.  Results are
- * cached per (storage, single/multiple plates, size bucket) for the life of
- * the process and picked up by later contexts.  best_ms (nullable) receives
- * the fastest time per launch. */
+/* Autotuner: time one step's interior launch (with the boundary work it
+ * carries) for every tiling of a candidate set (lanes x rows x packing order
+ * x edge rows) on this context's plates, `steps` launches each, and keep the
+ * fastest.  Repeating that launch leaves the state unchanged, except at step
+ * 0 and at a synchronization step, where the autotuner first takes one real
+ * step (steps_done grows by one; the trajectory is the same as without the
+ * autotuner).  Results are cached per (storage, single/multiple plates,
+ * size bucket) for the life of the process and picked up by later
+ * contexts.  best_ms (nullable) receives the fastest time per launch. */
 lbm_status lbm_autotune(lbm_ctx *ctx, int32_t steps, double *best_ms);
 
 /* Run n_steps steps eagerly (no graph), with a HIP event recorded on the

@@ -37,6 +37,9 @@ struct PlateHost {
   int64_t b0 = 0, b1 = 0;    // range in the boundary list
   int nloads = 0;
   int64_t body = 0;
+  int ns = 0, sw = 1;  // interior tiles: column strips and their width
+  // per strip: (first row, tile index) of its tiles, by increasing row
+  std::vector<std::vector<std::pair<int, int>>> strips;
 };
 
 struct Buffer {
@@ -73,7 +76,7 @@ size_t slot_bytes(int st) {
 size_t uv_bytes(int st) { return st == LBM_STORE_F32 ? 4 : 8; }
 
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int>, std::tuple<int, int, int>> g_tune_cache;
+std::map<std::tuple<int, int, int>, std::tuple<int, int, int, int>> g_tune_cache;
 
 }  // namespace
 
@@ -102,12 +105,24 @@ struct lbm_ctx {
   std::vector<STask> stasks;
   Chunk *d_chunks = nullptr;
   UNode *d_unodes = nullptr;
+  // prologue work lists of the interior tiles
+  std::vector<TileChunk> tchunks;
+  std::vector<TGradNode> tgn;
+  std::vector<BTask> tbt;
+  std::vector<int64_t> tbt_bnd;
+  std::vector<STask> tst;
+  TileChunk *d_tchunks = nullptr;
+  TGradNode *d_tgn = nullptr;
+  BTask *d_tbt = nullptr;
+  STask *d_tst = nullptr;
+  void *d_tgrad = nullptr;
+  size_t cap_tchunks = 0, cap_tgn = 0, cap_tbt = 0, cap_tst = 0, cap_tgrad = 0;
   GradNode *d_gnodes = nullptr;
   BTask *d_btasks = nullptr;
   STask *d_stasks = nullptr;
   std::vector<LoadTable> loads;
   std::vector<Tile> tiles;
-  int lanes = 128, rows = 32, order = 0;
+  int lanes = 128, rows = 32, order = 0, edge_rows = 0;
 
   std::vector<Buffer> bufs;
   DevState ds{};
@@ -175,6 +190,31 @@ void *dev_alloc(lbm_ctx *c, size_t bytes) {
     c->device_bytes += (int64_t)bytes;
   }
   return p;
+}
+
+void dev_free(lbm_ctx *c, void *p) {
+  if (!p) return;
+  for (size_t k = 0; k < c->bufs.size(); k++)
+    if (c->bufs[k].p == p) {
+      if (c->have_alloc)
+        c->alloc.free(p, c->alloc.user);
+      else
+        (void)hipFree(p);
+      c->device_bytes -= (int64_t)c->bufs[k].bytes;
+      c->bufs.erase(c->bufs.begin() + (long)k);
+      return;
+    }
+}
+
+// Grow a device array to hold n elements of T (contents not kept).
+template <class T>
+bool dev_reserve(lbm_ctx *c, T *&ptr, size_t &cap, size_t n) {
+  if (n <= cap && ptr) return true;
+  dev_free(c, ptr);
+  const size_t want = std::max<size_t>(1, n + n / 4);
+  ptr = (T *)dev_alloc(c, want * sizeof(T));
+  cap = ptr ? want : 0;
+  return ptr != nullptr;
 }
 
 void dev_free_all(lbm_ctx *c) {
@@ -456,6 +496,7 @@ bool build_boundary_tables(lbm_ctx *c, std::string &why) {
           Q.i = S.i;
           Q.j = S.j;
           Q.g[0] = -1;
+          Q.si = si;
           for (int al = 1; al < 5; al++) {
             const int ii = (S.i - DI[al] + h.nx) % h.nx, jj = (S.j - DJ[al] + h.ny) % h.ny;
             Q.g[al] = (h.cls[(size_t)jj * h.nx + ii] & CL_B) ? local(g, nodeat(ii, jj)) : -1;
@@ -474,34 +515,91 @@ bool build_boundary_tables(lbm_ctx *c, std::string &why) {
   return true;
 }
 
+// v within [lo - 1, hi] (an owned range of a tile plus its halo ring), with
+// wrap-around on a periodic axis of length n.
+bool in_ring(int v, int lo, int hi, int n, bool per) {
+  if (!per) return v >= lo - 1 && v <= hi;
+  const int d = ((v - (lo - 1)) % n + n) % n;
+  return d <= hi - lo + 1;
+}
+
+// Row bands of height `rows` on a plate of ny rows; the band holding row j.
+int band_of(int j, int rows, int nb) { return std::min(j / rows, nb - 1); }
+
 // Interior tiles: per plate, column strips of at most lanes-2 columns (of
-// equal width) times row bands of `rows` rows.  order 0: plate by plate, band
-// by band (strips of a band adjacent); 1: plate by plate, strip by strip
-// (bands of a strip adjacent); 2: as 0 with the plates by decreasing size.
-// Consecutive tiles land on the same XCD (see k_interior), so the order
-// decides which halo rows / columns share an L2.
+// equal width) times row bands of `rows` rows; a band piece whose area or
+// halo ring holds boundary or second-row nodes (a tile with a prologue) is
+// cut into pieces of edge_rows rows, so that its boundary work plus its
+// shorter march ends with the other tiles' marches.  order 0: plate by
+// plate, band by band (strips of a band adjacent); 1: plate by plate, strip
+// by strip (bands of a strip adjacent); 2: as 0 with the plates by decreasing
+// size.  Consecutive tiles land on the same XCD (see k_interior), so the
+// order decides which halo rows / columns share an L2.
 void build_tiles(lbm_ctx *c) {
   c->tiles.clear();
   const int own = c->lanes - 2;
+  const int rows = c->rows;
+  const int er = (c->edge_rows > 0 && c->edge_rows < rows) ? c->edge_rows : rows;
   std::vector<int> plates(c->ph.size());
   for (size_t p = 0; p < plates.size(); p++) plates[p] = (int)p;
   if (c->order == 2)
     std::stable_sort(plates.begin(), plates.end(), [&](int a, int b) {
       return (int64_t)c->ph[a].nx * c->ph[a].ny > (int64_t)c->ph[b].nx * c->ph[b].ny;
     });
+  // band pieces with boundary work, per plate (strip-major)
+  std::vector<std::vector<uint8_t>> work(c->ph.size());
+  for (size_t p = 0; p < c->ph.size(); p++) {
+    PlateHost &h = c->ph[p];
+    h.ns = (h.nx + own - 1) / own;
+    h.sw = (h.nx + h.ns - 1) / h.ns;
+    const int nb = (h.ny + rows - 1) / rows;
+    if (er < rows) work[p].assign((size_t)h.ns * nb, 0);
+  }
+  if (er < rows) {
+    auto mark = [&](int p, int i, int j) {
+      const PlateHost &h = c->ph[(size_t)p];
+      const int nb = (h.ny + rows - 1) / rows;
+      const int s0 = std::min(i / h.sw, h.ns - 1), b0 = band_of(j, rows, nb);
+      for (int ds = -1; ds <= 1; ds++)
+        for (int db = -1; db <= 1; db++) {
+          int s = s0 + ds, b = b0 + db;
+          if (s < 0 || s >= h.ns) {
+            if (!h.px) continue;
+            s = (s + h.ns) % h.ns;
+          }
+          if (b < 0 || b >= nb) {
+            if (!h.py) continue;
+            b = (b + nb) % nb;
+          }
+          const int x0 = s * h.sw, x1 = std::min(h.nx, (s + 1) * h.sw);
+          const int y0 = b * rows, y1 = std::min(h.ny, (b + 1) * rows);
+          if (in_ring(i, x0, x1, h.nx, h.px) && in_ring(j, y0, y1, h.ny, h.py))
+            work[(size_t)p][(size_t)s * nb + b] = 1;
+        }
+    };
+    for (const BndNode &B : c->bnd) mark(B.plate, B.i, B.j);
+    for (const SecNode &S : c->sec) mark(S.plate, S.i, S.j);
+  }
   for (int p : plates) {
-    const PlateHost &h = c->ph[p];
-    const int ns = (h.nx + own - 1) / own;
-    const int w = (h.nx + ns - 1) / ns;
-    const int nb = (h.ny + c->rows - 1) / c->rows;
+    PlateHost &h = c->ph[p];
+    const int ns = h.ns, w = h.sw;
+    const int nb = (h.ny + rows - 1) / rows;
+    h.strips.assign((size_t)ns, {});
     auto add = [&](int s, int b) {
-      Tile t{};
-      t.plate = p;
-      t.x0 = s * w;
-      t.x1 = std::min(h.nx, (s + 1) * w);
-      t.y0 = b * c->rows;
-      t.y1 = std::min(h.ny, (b + 1) * c->rows);
-      if (t.x1 > t.x0) c->tiles.push_back(t);
+      const int x0 = s * w, x1 = std::min(h.nx, (s + 1) * w);
+      const int y0 = b * rows, y1 = std::min(h.ny, (b + 1) * rows);
+      const int hgt = (er < rows && work[(size_t)p][(size_t)s * nb + b]) ? er : rows;
+      for (int y = y0; y < y1; y += hgt) {
+        Tile t{};
+        t.plate = p;
+        t.chunk = -1;
+        t.x0 = x0;
+        t.x1 = x1;
+        t.y0 = y;
+        t.y1 = std::min(y1, y + hgt);
+        h.strips[(size_t)s].push_back({y, (int)c->tiles.size()});
+        c->tiles.push_back(t);
+      }
     };
     if (c->order == 1) {
       for (int s = 0; s < ns; s++)
@@ -511,6 +609,173 @@ void build_tiles(lbm_ctx *c) {
         for (int s = 0; s < ns; s++) add(s, b);
     }
   }
+}
+
+// Prologue work lists.  A boundary or second-row node belongs to every tile
+// whose owned area or one-node halo ring contains it (the march reads the
+// populations of the ring).  Per tile: the boundary tasks (all reset, owned
+// ones also accelerate), the second-row tasks, and the gradient nodes they
+// read (their boundary nodes, the body neighbours of owned boundary nodes,
+// the boundary neighbours of the second-row nodes).
+void build_tile_tables(lbm_ctx *c) {
+  static const int DI[5] = {0, 1, 0, -1, 0}, DJ[5] = {0, 0, 1, 0, -1};
+  static const int NI[4] = {1, 0, -1, 0}, NJ[4] = {0, 1, 0, -1};
+  static const uint8_t NB[4] = {NB_E, NB_N, NB_W, NB_S};
+  c->tchunks.clear();
+  c->tgn.clear();
+  c->tbt.clear();
+  c->tbt_bnd.clear();
+  c->tst.clear();
+  for (Tile &t : c->tiles) t.chunk = -1;
+  std::vector<std::vector<std::pair<int64_t, int>>> tb(c->tiles.size());  // (bnd index, owned)
+  std::vector<std::vector<int>> ts(c->tiles.size());                       // sec index
+  // visit the tiles whose owned area or halo ring holds node (i, j): those
+  // of the three strips around column i that hold row j - 1, j or j + 1
+  auto visit = [&](int p, int i, int j, auto &&fn) {
+    const PlateHost &h = c->ph[p];
+    const int s0 = std::min(i / h.sw, h.ns - 1);
+    int cand[9], nc = 0;
+    for (int ds = -1; ds <= 1; ds++) {
+      int s = s0 + ds;
+      if (s < 0 || s >= h.ns) {
+        if (!h.px) continue;
+        s = (s + h.ns) % h.ns;
+      }
+      const auto &col = h.strips[(size_t)s];
+      for (int dj = -1; dj <= 1; dj++) {
+        int y = j + dj;
+        if (y < 0 || y >= h.ny) {
+          if (!h.py) continue;
+          y = (y + h.ny) % h.ny;
+        }
+        auto it = std::upper_bound(col.begin(), col.end(), std::make_pair(y, INT32_MAX));
+        const int ti = std::prev(it)->second;
+        bool dup = false;
+        for (int q = 0; q < nc; q++) dup = dup || cand[q] == ti;
+        if (!dup) cand[nc++] = ti;
+      }
+    }
+    for (int q = 0; q < nc; q++) {
+      const Tile &t = c->tiles[cand[q]];
+      if (!in_ring(i, t.x0, t.x1, h.nx, h.px) || !in_ring(j, t.y0, t.y1, h.ny, h.py)) continue;
+      const bool owned = i >= t.x0 && i < t.x1 && j >= t.y0 && j < t.y1;
+      fn(cand[q], owned);
+    }
+  };
+  for (size_t b = 0; b < c->bnd.size(); b++) {
+    const BndNode &B = c->bnd[b];
+    visit(B.plate, B.i, B.j, [&](int ti, bool owned) { tb[ti].push_back({(int64_t)b, owned ? 1 : 0}); });
+  }
+  for (size_t si = 0; si < c->sec.size(); si++) {
+    const SecNode &S = c->sec[si];
+    visit(S.plate, S.i, S.j, [&](int ti, bool) { ts[ti].push_back((int)si); });
+  }
+  typedef std::pair<int64_t, std::pair<int, int>> Key;
+  std::vector<Key> g;
+  for (size_t ti = 0; ti < c->tiles.size(); ti++) {
+    if (tb[ti].empty() && ts[ti].empty()) continue;
+    Tile &t = c->tiles[ti];
+    const PlateHost &h = c->ph[t.plate];
+    auto key = [&](int i, int j) { return Key{h.off + (int64_t)j * h.pitch + i, {i, j}}; };
+    auto nodeat = [&](int i, int j) { return h.off + (int64_t)j * h.pitch + i; };
+    g.clear();
+    for (auto &e : tb[ti]) {
+      const BndNode &B = c->bnd[(size_t)e.first];
+      g.push_back(key(B.i, B.j));
+      if (!e.second) continue;
+      const uint8_t cl = h.cls[(size_t)B.j * h.nx + B.i];
+      for (int d = 0; d < 4; d++)
+        if (cl & NB[d]) g.push_back(key((B.i + NI[d] + h.nx) % h.nx, (B.j + NJ[d] + h.ny) % h.ny));
+    }
+    for (int si : ts[ti]) {
+      const SecNode &S = c->sec[si];
+      for (int al = 1; al < 5; al++) {
+        const int ii = (S.i - DI[al] + h.nx) % h.nx, jj = (S.j - DJ[al] + h.ny) % h.ny;
+        if (h.cls[(size_t)jj * h.nx + ii] & CL_B) g.push_back(key(ii, jj));
+      }
+    }
+    std::sort(g.begin(), g.end());
+    g.erase(std::unique(g.begin(), g.end()), g.end());
+    auto local = [&](int64_t node) -> int {
+      auto it = std::lower_bound(g.begin(), g.end(), Key{node, {INT32_MIN, INT32_MIN}});
+      return (it != g.end() && it->first == node) ? (int)(it - g.begin()) : -1;
+    };
+    TileChunk ch{};
+    ch.plate = t.plate;
+    ch.g0 = (int)c->tgn.size();
+    ch.b0 = (int)c->tbt.size();
+    ch.s0 = (int)c->tst.size();
+    for (const Key &e : g) {
+      TGradNode G{};
+      G.node = e.first;
+      G.i = e.second.first;
+      G.j = e.second.second;
+      G.code = fd_code_host(h, G.i, G.j, 0) | (fd_code_host(h, G.i, G.j, 1) << 3);
+      c->tgn.push_back(G);
+    }
+    for (auto &e : tb[ti]) {
+      const BndNode &B = c->bnd[(size_t)e.first];
+      const uint8_t cl = h.cls[(size_t)B.j * h.nx + B.i];
+      BTask T{};
+      T.b = B;
+      T.accel = e.second;
+      T.g[0] = local(B.node);
+      for (int d = 0; d < 4; d++)
+        T.g[1 + d] = (e.second && (cl & NB[d]))
+                         ? local(nodeat((B.i + NI[d] + h.nx) % h.nx, (B.j + NJ[d] + h.ny) % h.ny))
+                         : -1;
+      c->tbt.push_back(T);
+      c->tbt_bnd.push_back(e.first);
+    }
+    for (int si : ts[ti]) {
+      const SecNode &S = c->sec[si];
+      STask Q{};
+      Q.node = S.node;
+      Q.i = S.i;
+      Q.j = S.j;
+      Q.g[0] = -1;
+      Q.si = si;
+      for (int al = 1; al < 5; al++) {
+        const int ii = (S.i - DI[al] + h.nx) % h.nx, jj = (S.j - DJ[al] + h.ny) % h.ny;
+        Q.g[al] = (h.cls[(size_t)jj * h.nx + ii] & CL_B) ? local(nodeat(ii, jj)) : -1;
+      }
+      c->tst.push_back(Q);
+    }
+    ch.g1 = (int)c->tgn.size();
+    ch.b1 = (int)c->tbt.size();
+    ch.s1 = (int)c->tst.size();
+    t.chunk = (int)c->tchunks.size();
+    c->tchunks.push_back(ch);
+  }
+}
+
+lbm_status upload_tile_tables(lbm_ctx *c) {
+  for (size_t k = 0; k < c->tbt.size(); k++) c->tbt[k].b = c->bnd[(size_t)c->tbt_bnd[k]];
+  const size_t gsz = c->storage == LBM_STORE_F32 ? 4 : 8;
+  if (!dev_reserve(c, c->d_tchunks, c->cap_tchunks, c->tchunks.size()) ||
+      !dev_reserve(c, c->d_tgn, c->cap_tgn, c->tgn.size()) ||
+      !dev_reserve(c, c->d_tbt, c->cap_tbt, c->tbt.size()) ||
+      !dev_reserve(c, c->d_tst, c->cap_tst, c->tst.size()))
+    return fail(c, LBM_E_NOMEM, "prologue table allocation failed");
+  if (c->tgn.size() * 4 * gsz > c->cap_tgrad || !c->d_tgrad) {
+    dev_free(c, c->d_tgrad);
+    c->cap_tgrad = std::max<size_t>(256, c->tgn.size() * 4 * gsz);
+    c->d_tgrad = dev_alloc(c, c->cap_tgrad);
+    if (!c->d_tgrad) return fail(c, LBM_E_NOMEM, "prologue scratch allocation failed");
+  }
+  if (!c->tchunks.empty())
+    HIP_TRY(c, hipMemcpy(c->d_tchunks, c->tchunks.data(), c->tchunks.size() * sizeof(TileChunk),
+                         hipMemcpyHostToDevice), "prologue table upload");
+  if (!c->tgn.empty())
+    HIP_TRY(c, hipMemcpy(c->d_tgn, c->tgn.data(), c->tgn.size() * sizeof(TGradNode),
+                         hipMemcpyHostToDevice), "prologue table upload");
+  if (!c->tbt.empty())
+    HIP_TRY(c, hipMemcpy(c->d_tbt, c->tbt.data(), c->tbt.size() * sizeof(BTask),
+                         hipMemcpyHostToDevice), "prologue table upload");
+  if (!c->tst.empty())
+    HIP_TRY(c, hipMemcpy(c->d_tst, c->tst.data(), c->tst.size() * sizeof(STask),
+                         hipMemcpyHostToDevice), "prologue table upload");
+  return LBM_OK;
 }
 
 lbm_status upload_tiles(lbm_ctx *c) {
@@ -533,6 +798,10 @@ lbm_status upload_boundary(lbm_ctx *c) {
                          hipMemcpyHostToDevice),
             "boundary upload");
   for (size_t t = 0; t < c->btasks.size(); t++) c->btasks[t].b = c->bnd[(size_t)c->btask_bnd[t]];
+  {
+    lbm_status st = upload_tile_tables(c);
+    if (st) return st;
+  }
   if (!c->btasks.empty())
     HIP_TRY(c, hipMemcpy(c->d_btasks, c->btasks.data(), c->btasks.size() * sizeof(BTask),
                          hipMemcpyHostToDevice),
@@ -545,13 +814,26 @@ lbm_status upload_boundary(lbm_ctx *c) {
   return LBM_OK;
 }
 
-// One time step: the interior kernel, then the boundary kernel (which reads
-// the interior kernel's u(t+dt) near the boundary), then the
-// synchronization after every l-th step, all in order on st.  With ev
-// (profiling) events are recorded around each launch.
-hipError_t enqueue_step(lbm_ctx *c, int64_t step_index, hipStream_t st, hipEvent_t *ev,
-                        double *ms, int64_t *cnt) {
-  const int cur = (int)(step_index & 1);
+Prologue make_prologue(const lbm_ctx *c, int64_t n, bool enabled) {
+  Prologue p{};
+  p.chunks = c->d_tchunks;
+  p.gn = c->d_tgn;
+  p.bt = c->d_tbt;
+  p.st = c->d_tst;
+  p.grad = c->d_tgrad;
+  p.enabled = enabled && !c->tchunks.empty();
+  return p;
+}
+
+// Steps [s, s + k) from a complete state at t_s (populations of t_s at every
+// body node, u and du/dt of t_s, boundary nodes' u and du/dt of t_{s+1}):
+// k interior launches, the later ones with the prologue that finishes the
+// previous step's boundary work; then one boundary launch finishing step
+// s + k - 1, which leaves the state complete at t_{s+k}; then the
+// synchronization if s + k is a multiple of l.  ev: events around each launch
+// for profiling (kind 0 interior, 1 boundary, 2 synchronization).
+hipError_t enqueue_segment(lbm_ctx *c, int64_t s, int64_t k, hipStream_t st, hipEvent_t *ev,
+                           double *ms, int64_t *cnt) {
   auto timed = [&](int kind, auto &&fn) -> hipError_t {
     if (ev) (void)hipEventRecord(ev[0], st);
     hipError_t e = fn();
@@ -565,28 +847,43 @@ hipError_t enqueue_step(lbm_ctx *c, int64_t step_index, hipStream_t st, hipEvent
     }
     return e;
   };
-  hipError_t e = timed(0, [&] {
-    return launch_interior(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), c->lanes, cur, st);
-  });
+  hipError_t e = hipSuccess;
+  for (int64_t n = s; n < s + k && e == hipSuccess; n++) {
+    const Prologue pro = make_prologue(c, n, n > s);
+    e = timed(0, [&] {
+      return launch_interior(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), c->lanes,
+                             (int)(n & 1), pro, st);
+    });
+  }
   if (e != hipSuccess) return e;
+  const int64_t m = s + k - 1;  // the step whose boundary work closes the segment
   e = timed(1, [&] {
     return launch_boundary(c->storage, c->ds, c->d_chunks, (int)c->chunks.size(), c->d_unodes,
-                           c->d_gnodes, c->d_btasks, c->d_stasks, cur, cur ^ 1, cur, 1, 0, cur, 1,
-                           st);
+                           c->d_gnodes, c->d_btasks, c->d_stasks, (int)((m + 1) & 1), 1, st);
   });
   if (e != hipSuccess) return e;
-  if (c->sync_every > 0 && (step_index + 1) % c->sync_every == 0) {
+  if (c->sync_every > 0 && (s + k) % c->sync_every == 0) {
     e = timed(2, [&] {
-      return launch_sync(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), c->lanes, cur ^ 1,
-                         st);
+      return launch_sync(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), c->lanes,
+                         (int)((s + k) & 1), st);
     });
   }
   return e;
 }
 
+// Length of the segment starting at step s (ends at the next synchronization).
+int64_t segment_limit(const lbm_ctx *c, int64_t s, int64_t n) {
+  if (c->sync_every <= 0) return n;
+  return std::min<int64_t>(n, c->sync_every - s % c->sync_every);
+}
+
+// Steps per captured graph: even (buffer parity) and a multiple of l.
 int64_t graph_period(const lbm_ctx *c) {
-  int64_t g = c->sync_every > 0 ? c->sync_every : 64;
-  while (g % 2 != 0 || g < 32) g += (c->sync_every > 0 ? c->sync_every : 1);
+  int64_t g = 64;
+  if (c->sync_every > 0) {
+    g = c->sync_every % 2 ? 2 * c->sync_every : c->sync_every;
+    while (g < 32) g *= 2;
+  }
   return g;
 }
 
@@ -599,8 +896,11 @@ lbm_status ensure_graph(lbm_ctx *c) {
   HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal),
           "begin capture");
   hipError_t e = hipSuccess;
-  for (int64_t s = 0; s < G && e == hipSuccess; s++)
-    e = enqueue_step(c, s, c->cap_stream, nullptr, nullptr, nullptr);
+  for (int64_t s = 0; s < G && e == hipSuccess;) {
+    const int64_t k = segment_limit(c, s, G - s);
+    e = enqueue_segment(c, s, k, c->cap_stream, nullptr, nullptr, nullptr);
+    s += k;
+  }
   hipGraph_t g = nullptr;
   hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
   if (e != hipSuccess) {
@@ -643,8 +943,7 @@ lbm_status start(lbm_ctx *c) {
   }
   // boundary accelerations of step 0: u(t_1) of the boundary nodes
   HIP_TRY(c, launch_boundary(c->storage, c->ds, c->d_chunks, (int)c->chunks.size(), c->d_unodes,
-                             c->d_gnodes, c->d_btasks, c->d_stasks, 0, 0, 1, 0, 0, 0, 0,
-                             c->stream),
+                             c->d_gnodes, c->d_btasks, c->d_stasks, 0, 0, c->stream),
           "first boundary step");
   c->started = true;
   return LBM_OK;
@@ -846,6 +1145,23 @@ lbm_status lbm_create(const lbm_plate *plates, int32_t n_plates, lbm_storage sto
           return bail(LBM_E_DEVICE, "memset");
         c->ds.pop[b][fl][sl] = p;
       }
+  {
+    // second-row side buffers and the node -> second-row index map
+    const int64_t ns = (int64_t)c->sec.size();
+    const size_t cb = c->storage == LBM_STORE_F64 ? sizeof(double) : sizeof(float);
+    for (int b = 0; b < 2; b++) {
+      c->ds.side[b] = dev_alloc(c, (size_t)std::max<int64_t>(1, ns) * 10 * cb);
+      if (!c->ds.side[b]) return bail(LBM_E_NOMEM, "side buffer allocation failed");
+    }
+    c->ds.nsec = ns;
+    std::vector<int32_t> sidx((size_t)N, -1);
+    for (int64_t q = 0; q < ns; q++) sidx[(size_t)c->sec[(size_t)q].node] = (int32_t)q;
+    int32_t *d = (int32_t *)dev_alloc(c, (size_t)N * sizeof(int32_t));
+    if (!d) return bail(LBM_E_NOMEM, "second-row index allocation failed");
+    if (hipMemcpy(d, sidx.data(), (size_t)N * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess)
+      return bail(LBM_E_DEVICE, "second-row index upload");
+    c->ds.sidx = d;
+  }
   for (int b = 0; b < 2; b++)
     for (int comp = 0; comp < 2; comp++) {
       c->ds.u[b][comp] = dev_alloc(c, (size_t)N * uv_bytes(c->storage));
@@ -949,6 +1265,7 @@ lbm_status lbm_create(const lbm_plate *plates, int32_t n_plates, lbm_storage sto
       c->lanes = std::get<0>(it->second);
       c->rows = std::get<1>(it->second);
       c->order = std::get<2>(it->second);
+      c->edge_rows = std::get<3>(it->second);
     } else {
       c->lanes = 256;
       c->rows = 64;
@@ -956,10 +1273,13 @@ lbm_status lbm_create(const lbm_plate *plates, int32_t n_plates, lbm_storage sto
       for (auto &h : c->ph) maxnx = std::max<int64_t>(maxnx, h.nx);
       if (maxnx <= 512) c->lanes = 128;
       if (c->n_body < (int64_t)4 << 20) c->rows = 16;
+      c->edge_rows = 4;
     }
   }
   build_tiles(c);
-  if (upload_tiles(c) != LBM_OK) return bail(LBM_E_DEVICE, c->err);
+  build_tile_tables(c);
+  if (upload_tiles(c) != LBM_OK || upload_tile_tables(c) != LBM_OK)
+    return bail(LBM_E_NOMEM, c->err);
   if (hipHostMalloc((void **)&c->h_flag, sizeof(int), hipHostMallocDefault) != hipSuccess)
     return bail(LBM_E_NOMEM, "pinned flag allocation failed");
   *c->h_flag = 0;
@@ -1044,9 +1364,11 @@ lbm_status lbm_step(lbm_ctx *c, int64_t n) {
         continue;
       }
     }
-    HIP_TRY(c, enqueue_step(c, c->step, c->stream, nullptr, nullptr, nullptr), "step launch");
-    c->step += 1;
-    n -= 1;
+    const int64_t k = segment_limit(c, c->step, n);
+    HIP_TRY(c, enqueue_segment(c, c->step, k, c->stream, nullptr, nullptr, nullptr),
+            "step launch");
+    c->step += k;
+    n -= k;
   }
   HIP_TRY(c, hipMemcpyAsync(c->h_flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream),
           "flag copy");
@@ -1108,21 +1430,28 @@ lbm_status lbm_info(const lbm_ctx *c, lbm_info_t *info) {
   info->tile_lanes = c->lanes;
   info->tile_rows = c->rows;
   info->tile_order = c->order;
+  info->tile_edge_rows = (c->edge_rows > 0 && c->edge_rows < c->rows) ? c->edge_rows : c->rows;
   info->n_tiles = (int32_t)c->tiles.size();
   return LBM_OK;
 }
 
-lbm_status lbm_set_tiling(lbm_ctx *c, int32_t lanes, int32_t rows, int32_t order) {
+lbm_status lbm_set_tiling(lbm_ctx *c, int32_t lanes, int32_t rows, int32_t order,
+                          int32_t edge_rows) {
   if (!c) return LBM_E_INVAL;
   if ((lanes != 64 && lanes != 128 && lanes != 256) || rows < 1 || rows > 65536 || order < 0 ||
-      order > 2)
-    return fail(c, LBM_E_INVAL, "lanes must be 64, 128 or 256, rows >= 1, order 0..2");
+      order > 2 || edge_rows < 0)
+    return fail(c, LBM_E_INVAL,
+                "lanes must be 64, 128 or 256, rows >= 1, order 0..2, edge_rows >= 0");
   HIP_TRY(c, hipStreamSynchronize(c->stream), "synchronize");
   c->lanes = lanes;
   c->rows = rows;
   c->order = order;
+  c->edge_rows = edge_rows;
   build_tiles(c);
+  build_tile_tables(c);
   lbm_status st = upload_tiles(c);
+  if (st) return st;
+  st = upload_tile_tables(c);
   if (st) return st;
   drop_graph(c);
   return LBM_OK;
@@ -1146,9 +1475,13 @@ lbm_status lbm_profile(lbm_ctx *c, int64_t n, double *ms, int64_t *launches) {
   double acc[4] = {0, 0, 0, 0};
   int64_t cnt[4] = {0, 0, 0, 0};
   hipError_t e = hipSuccess;
-  for (int64_t s = 0; s < n && e == hipSuccess; s++) {
-    e = enqueue_step(c, c->step, c->stream, ev, acc, cnt);
-    if (e == hipSuccess) c->step += 1;
+  while (n > 0 && e == hipSuccess) {
+    const int64_t k = segment_limit(c, c->step, n);
+    e = enqueue_segment(c, c->step, k, c->stream, ev, acc, cnt);
+    if (e == hipSuccess) {
+      c->step += k;
+      n -= k;
+    }
   }
   (void)hipEventDestroy(ev[0]);
   (void)hipEventDestroy(ev[1]);
@@ -1162,60 +1495,86 @@ lbm_status lbm_profile(lbm_ctx *c, int64_t n, double *ms, int64_t *launches) {
 
 lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
   if (!c || steps < 1) return LBM_E_INVAL;
-  lbm_status st = start(c);
+  lbm_status st = check_flag(c, false);
   if (st) return st;
+  st = start(c);
+  if (st) return st;
+  // The timed launch is the interior kernel of step n with its prologue
+  // (the boundary work of step n - 1).  From a complete state at t_n it
+  // rewrites the boundary values of t_n and t_{n+1} with the values they
+  // already hold and the t_{n+1} buffers from the t_n ones, so repeating it
+  // leaves the state unchanged -- unless there is no t_{n-1} (n = 0) or the
+  // state of t_n comes from a synchronization: then one real step is taken
+  // first.
+  const bool syncs_now = c->sync_every > 0 && c->step % c->sync_every == 0;
+  if (c->step == 0 || (syncs_now && c->sync_every > 1)) {
+    HIP_TRY(c, enqueue_segment(c, c->step, 1, c->stream, nullptr, nullptr, nullptr), "step launch");
+    c->step += 1;
+  }
+  const bool with_prologue = !(c->sync_every > 0 && c->step % c->sync_every == 0);
   HIP_TRY(c, hipStreamSynchronize(c->stream), "synchronize");
   const int lane_set[3] = {64, 128, 256};
   const int row_set[6] = {4, 8, 16, 32, 64, 128};
+  const int edge_set[4] = {0, 8, 4, 2};
   const int n_orders = c->ph.size() > 1 ? 3 : 2;
   hipEvent_t e0, e1;
   HIP_TRY(c, hipEventCreate(&e0), "event");
   HIP_TRY(c, hipEventCreate(&e1), "event");
-  const int cur = (int)(c->step & 1);
+  const int64_t n = c->step;
   double best = 1e300;
-  int bl = c->lanes, br = c->rows, bo = c->order;
+  int bl = c->lanes, br = c->rows, bo = c->order, be = c->edge_rows;
   for (int O = 0; O < n_orders; O++)
-  for (int L : lane_set)
-    for (int R : row_set) {
-      c->lanes = L;
-      c->rows = R;
-      c->order = O;
-      build_tiles(c);
-      if (upload_tiles(c) != LBM_OK) continue;
-      // The interior kernel reads buffer cur and writes only interior nodes
-      // of the other buffer, so repeating it leaves the state unchanged.
-      hipError_t e = launch_interior(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), L, cur,
-                                     c->stream);
-      (void)hipEventRecord(e0, c->stream);
-      for (int s = 0; s < steps && e == hipSuccess; s++)
-        e = launch_interior(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), L, cur, c->stream);
-      (void)hipEventRecord(e1, c->stream);
-      (void)hipEventSynchronize(e1);
-      if (e != hipSuccess) continue;
-      float t = 0;
-      (void)hipEventElapsedTime(&t, e0, e1);
-      const double per = t / steps;
-      if (per < best) {
-        best = per;
-        bl = L;
-        br = R;
-        bo = O;
-      }
-    }
+    for (int L : lane_set)
+      for (int R : row_set)
+        for (int E : edge_set) {
+          if (E != 0 && E >= R) continue;  // same tiling as E = 0
+          c->lanes = L;
+          c->rows = R;
+          c->order = O;
+          c->edge_rows = E;
+          build_tiles(c);
+          build_tile_tables(c);
+          if (upload_tiles(c) != LBM_OK || upload_tile_tables(c) != LBM_OK) continue;
+          const Prologue pro = make_prologue(c, n, with_prologue);
+          auto launch = [&] {
+            return launch_interior(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), L,
+                                   (int)(n & 1), pro, c->stream);
+          };
+          hipError_t e = launch();
+          (void)hipEventRecord(e0, c->stream);
+          for (int k = 0; k < steps && e == hipSuccess; k++) e = launch();
+          (void)hipEventRecord(e1, c->stream);
+          (void)hipEventSynchronize(e1);
+          if (e != hipSuccess) continue;
+          float t = 0;
+          (void)hipEventElapsedTime(&t, e0, e1);
+          const double per = t / steps;
+          if (per < best) {
+            best = per;
+            bl = L;
+            br = R;
+            bo = O;
+            be = E;
+          }
+        }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   c->lanes = bl;
   c->rows = br;
   c->order = bo;
+  c->edge_rows = be;
   build_tiles(c);
+  build_tile_tables(c);
   st = upload_tiles(c);
+  if (st) return st;
+  st = upload_tile_tables(c);
   if (st) return st;
   drop_graph(c);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto key = std::make_tuple(c->storage, c->ph.size() > 1 ? 1 : 0,
                                (int)std::lround(std::log2((double)std::max<int64_t>(1, c->n_body))));
-    g_tune_cache[key] = {bl, br, bo};
+    g_tune_cache[key] = {bl, br, bo, be};
   }
   if (best_ms) *best_ms = best;
   return LBM_OK;

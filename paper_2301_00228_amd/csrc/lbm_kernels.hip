@@ -1,7 +1,7 @@
 // lbm_kernels.hip -- gfx950 kernels of the plane-strain LBM
 // (Schlueter et al., arXiv 2301.00228).
 //
-// One time step is two launches (plus the synchronization every l steps):
+// One time step is one launch of k_interior:
 //
 //  k_interior  every body node of every plate, tiled.  A workgroup owns a
 //              strip of columns and marches up a band of rows.  Each lane
@@ -12,22 +12,25 @@
 //              acceleration of eq. navier from the neighbours' phi and psi,
 //              advance u and du/dt by eq. integration, and (unless a
 //              neighbour is a boundary node) store the streamed populations.
-//  k_boundary  boundary and second-row nodes, one block per chunk of
-//              boundary nodes, after the interior kernel: u(t+dt) of the
-//              nodes the chunk's stencils touch and its gradients go to LDS
-//              first (optionally recomputing u(t+dt) of interior nodes, so
-//              that the kernel does not need the interior kernel of the
-//              same step); then the boundary reset of
-//              eqs. psi_phi_at_bound and correction-f, the second-row pull
-//              of eq. LBE_mod with the time-averaged boundary populations,
-//              and the boundary accelerations of eqs. acc_neumann /
-//              acc_dirichlet of the next step with their Newmark update,
-//              written into the other u buffer.
+//              Workgroups whose tile or halo ring holds boundary or
+//              second-row nodes first finish the previous step there (the
+//              prologue): the boundary reset of eqs. psi_phi_at_bound and
+//              correction-f, the second-row pull of eq. LBE_mod with the
+//              time-averaged boundary populations, and the boundary
+//              accelerations of eqs. acc_neumann / acc_dirichlet with their
+//              Newmark update.  The latency of that work hides behind the
+//              other workgroups' streaming.
+//  k_boundary  the same boundary work for every boundary node, one block
+//              per chunk of boundary nodes; it closes each run of steps (and
+//              precedes every synchronization) so the state is complete.
+//  k_sync      the synchronization of Sec. 3.2 every l steps.
 //
-// Buffers ping-pong: step n reads populations, u and du/dt from buffer
-// cur = n & 1 and writes buffer cur ^ 1.  Boundary nodes' u(t_{n+1}) is
-// written one step ahead by k_boundary (launched once in acceleration-only
-// mode before the first step).
+// Populations, u and du/dt ping-pong through two buffers (step n keeps t_n
+// in buffer n & 1).  The march never writes boundary or second-row nodes:
+// boundary nodes keep their populations of t_{n-1} in buffer b ^ 1, which
+// the prologue reads, and second-row nodes' pulls go to a small side buffer
+// (also two of them) that the next step's boundary work completes.
+// Boundary nodes' u(t_{n+1}) is written one step ahead.
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
@@ -375,6 +378,271 @@ __device__ __forceinline__ void collide(const DevState &s, int b, int fl, int64_
   collide_pops<CD>(P, fl, f, rho, fs);
 }
 
+// ------------------------------------------- boundary / second-row work
+
+// Finite difference with a precomputed stencil code from the node's value
+// q0 and the values qa, qb of the further stencil nodes, branch-free:
+// ((c0 q0 + ca qa) + cb qb) * scale with the coefficients of the code
+// (central: qa - qb, one-sided 3-point: (-3 q0 + 4 qa) - qb and its mirror,
+// 2-point: qa - q0 and q0 - qa; these sums round exactly as the written-out
+// formulas); scale is 1/(2 dh) or 1/dh.
+template <class U>
+__device__ __forceinline__ U fd_vals(int code, U q0, U qa, U qb, const PlateDev &P) {
+  const bool cen = code == FD_CENTRAL, f3 = code == FD_FWD3, b3 = code == FD_BWD3;
+  const bool f2 = code == FD_FWD2, b2 = code == FD_BWD2;
+  const U c0 = f3 ? U(-3.0) : b3 ? U(3.0) : f2 ? U(-1.0) : b2 ? U(1.0) : U(0.0);
+  const U ca = (cen || f2) ? U(1.0) : f3 ? U(4.0) : b3 ? U(-4.0) : b2 ? U(-1.0) : U(0.0);
+  const U cb = (cen || f3) ? U(-1.0) : b3 ? U(1.0) : U(0.0);
+  const U sc = (f2 || b2) ? (U)P.inv_h : (cen || f3 || b3) ? (U)P.inv_2h : U(0.0);
+  return ((c0 * q0 + ca * qa) + cb * qb) * sc;
+}
+
+// The same finite difference read straight from q at node (i, j).  Every
+// index touched lies in the body (the code was built from the mask).
+template <class U>
+__device__ __forceinline__ U fd_code(const U *q, const PlateDev &P, int i, int j, int ax,
+                                     int code) {
+  const int di = ax == 0 ? 1 : 0, dj = ax == 0 ? 0 : 1;
+  const int64_t k0 = node_of(P, i, j);
+  int64_t ka = k0, kb = k0;
+  if (code == FD_CENTRAL || code == FD_FWD3 || code == FD_FWD2) {
+    const int ip = wrapc(i + di, P.nx), jp = wrapc(j + dj, P.ny);
+    ka = node_of(P, ip, jp);
+    if (code == FD_CENTRAL) kb = node_of(P, wrapc(i - di, P.nx), wrapc(j - dj, P.ny));
+    if (code == FD_FWD3) kb = node_of(P, wrapc(ip + di, P.nx), wrapc(jp + dj, P.ny));
+  } else if (code == FD_BWD3 || code == FD_BWD2) {
+    const int im = wrapc(i - di, P.nx), jm = wrapc(j - dj, P.ny);
+    ka = node_of(P, im, jm);
+    if (code == FD_BWD3) kb = node_of(P, wrapc(im - di, P.nx), wrapc(jm - dj, P.ny));
+  }
+  return fd_vals<U>(code, q[k0], q[ka], q[kb], P);
+}
+
+// Hooke's law (Sec. 2, eq. hooke) from a displacement gradient
+// g = (d_x u_x, d_y u_x, d_x u_y, d_y u_y).
+template <class U>
+__device__ __forceinline__ void hooke(const PlateDev &P, const U *g, U &sxx, U &syy, U &sxy) {
+  const U exx = g[0], eyy = g[3];
+  const U exy = U(0.5) * (g[1] + g[2]);
+  const U tr = exx + eyy;
+  const U lam = (U)P.lam, mu = (U)P.mu;
+  sxx = lam * tr + U(2.0) * mu * exx;
+  syy = lam * tr + U(2.0) * mu * eyy;
+  sxy = U(2.0) * mu * exy;
+}
+
+// One boundary node.  grad: rows of 4 gradient values (d_x u_x, d_y u_x,
+// d_x u_y, d_y u_y) of u at time t, indexed by the task's g[].
+//  reset (eqs. psi_phi_at_bound, correction-f): populations at t from the
+//    field div u / (curl u).e_z and the flux of the populations at t - dt
+//    (buffer po), written to buffer pn;
+//  accel (eq. acc_dirichlet or eq. acc_neumann, step n with loads at n dt /
+//    (n+1) dt): u, du/dt at t from buffer ua, Newmark update (eq.
+//    integration) into buffer ub.
+template <class CD>
+__device__ void boundary_task(const DevState &s, const PlateDev &P, const BTask &T,
+                              const typename CD::U *grad, int po, int pn, bool reset, bool accel,
+                              int ua, int ub, unsigned long long n) {
+  using C = typename CD::C;
+  using U = typename CD::U;
+  const BndNode &B = T.b;
+  const int64_t k = B.node;
+  const U *gs = grad + 4 * T.g[0];
+  if (reset) {
+    const U dv = gs[0] + gs[3];
+    const U cu = gs[2] - gs[1];
+    C jx, jy;
+    CD::flux(s, po, 0, k, P, jx, jy);
+    CD::store_eq(s, pn, 0, k, P, (C)dv, jx, jy);
+    CD::flux(s, po, 1, k, P, jx, jy);
+    CD::store_eq(s, pn, 1, k, P, (C)cu, jx, jy);
+  }
+  if (!accel) return;
+  const U ux0 = ldg<U>(s.u[ua][0], k), uy0 = ldg<U>(s.u[ua][1], k);
+  const U vx0 = ldg<U>(s.v[ua][0], k), vy0 = ldg<U>(s.v[ua][1], k);
+  const U dt = (U)P.dt;
+  U ax, ay;
+  if (B.kind == LBM_BC_DIRICHLET) {
+    const double g = load_amp(s, B.load, (double)(n + 1) * P.dt);
+    const U usx = (U)(g * B.val[0]), usy = (U)(g * B.val[1]);
+    ax = U(2.0) / (dt * dt) * (usx - ux0) - U(2.0) / dt * vx0;
+    ay = U(2.0) / (dt * dt) * (usy - uy0) - U(2.0) / dt * vy0;
+  } else {
+    const double g = load_amp(s, B.load, (double)n * P.dt);
+    const U V = (U)B.cell[0], lE = (U)B.cell[1], lN = (U)B.cell[2], lW = (U)B.cell[3],
+            lS = (U)B.cell[4];
+    U sxx, syy, sxy, rxx, ryy, rxy;
+    hooke<U>(P, gs, sxx, syy, sxy);
+    U tEx = 0, tEy = 0, tWx = 0, tWy = 0, tNx = 0, tNy = 0, tSx = 0, tSy = 0;
+    // sigma_kr n_kr l_kr with sigma_kr the mean of the nodal stresses
+    if (T.g[1] >= 0) {
+      hooke<U>(P, grad + 4 * T.g[1], rxx, ryy, rxy);
+      tEx = U(0.5) * (sxx + rxx) * lE;
+      tEy = U(0.5) * (sxy + rxy) * lE;
+    }
+    if (T.g[3] >= 0) {
+      hooke<U>(P, grad + 4 * T.g[3], rxx, ryy, rxy);
+      tWx = -(U(0.5) * (sxx + rxx)) * lW;
+      tWy = -(U(0.5) * (sxy + rxy)) * lW;
+    }
+    if (T.g[2] >= 0) {
+      hooke<U>(P, grad + 4 * T.g[2], rxx, ryy, rxy);
+      tNx = U(0.5) * (sxy + rxy) * lN;
+      tNy = U(0.5) * (syy + ryy) * lN;
+    }
+    if (T.g[4] >= 0) {
+      hooke<U>(P, grad + 4 * T.g[4], rxx, ryy, rxy);
+      tSx = -(U(0.5) * (sxy + rxy)) * lS;
+      tSy = -(U(0.5) * (syy + ryy)) * lS;
+    }
+    const U Fx = (U)(g * B.val[0]), Fy = (U)(g * B.val[1]);
+    const U m = (U)P.rho_m * V;
+    ax = (((tEx + tWx) + (tNx + tSx)) + Fx) / m;
+    ay = (((tEy + tWy) + (tNy + tSy)) + Fy) / m;
+  }
+  const U nux = ux0 + dt * vx0 + dt * dt / U(2.0) * ax;
+  const U nuy = uy0 + dt * vy0 + dt * dt / U(2.0) * ay;
+  stg<U>(s.u[ub][0], k, nux);
+  stg<U>(s.u[ub][1], k, nuy);
+  stg<U>(s.v[ub][0], k, vx0 + dt * ax);
+  stg<U>(s.v[ub][1], k, vy0 + dt * ay);
+  if (!(fabs((double)nux) < 1e30) || !(fabs((double)nuy) < 1e30)) s.flag[0] = 1;
+}
+
+// One field of one second-row node: its populations at t, pulled from the
+// upwind nodes at t - dt.  Those pulled from non-boundary upwind nodes were
+// left in side buffer sr by the march of the previous step; one leaving a
+// boundary node follows eq. LBE_mod: the average of the boundary node's
+// populations at t - dt (buffer po) and of their reset values at t (field
+// from grad, flux of the populations at t - dt), collided with the
+// equilibrium of their own moments.  Written to buffer pn.
+template <class CD>
+__device__ void second_row_task(const DevState &s, const PlateDev &P, const STask &Q, int fl,
+                                const typename CD::U *grad, int po, int pn, int sr) {
+  using C = typename CD::C;
+  using U = typename CD::U;
+  using Slot = typename CD::Slot;
+  const int di[5] = {0, 1, 0, -1, 0};
+  const int dj[5] = {0, 0, 1, 0, -1};
+  const C *side = static_cast<const C *>(s.side[sr]);
+  C fo[5];
+  Slot raw[5][5];
+#pragma unroll
+  for (int al = 0; al < 5; al++) {
+    fo[al] = side[(int64_t)(fl * 5 + al) * s.nsec + Q.si];
+    if (Q.g[al] >= 0) {
+      // upwind boundary node x - c^alpha dt
+      const int64_t ky = node_of(P, wrapc(Q.i - di[al], P.nx), wrapc(Q.j - dj[al], P.ny));
+      CD::load_raw(s, po, fl, ky, raw[al]);
+    }
+  }
+#pragma unroll
+  for (int al = 0; al < 5; al++) {
+    if (Q.g[al] < 0) continue;
+    C f[5], r, fs[5];
+    CD::raw_to_pops(P, fl, raw[al], f);
+    const U *gy = grad + 4 * Q.g[al];
+    const C fld = fl == 0 ? (C)(gy[0] + gy[3]) : (C)(gy[2] - gy[1]);
+    C fnew[5], jx, jy;
+    CD::raw_flux(raw[al], jx, jy);
+    CD::eq_pops(P, fl, fld, jx, jy, fnew);
+#pragma unroll
+    for (int qq = 0; qq < 5; qq++) f[qq] = C(0.5) * (fnew[qq] + f[qq]);
+    collide_pops<CD>(P, fl, f, r, fs);
+    fo[al] = fs[al];
+  }
+  CD::store(s, pn, fl, Q.node, P, fo);
+}
+
+// Prologue of an interior tile at step n (parity b = n & 1): the boundary
+// work of step n - 1 for the boundary and second-row nodes of the tile and
+// its halo ring (resets and pulls into buffer b, which the march then
+// reads, from the populations at t_{n-1} in buffer b ^ 1 and the side
+// buffer b) and the next boundary accelerations of the tile's own boundary
+// nodes (u buffer b to b ^ 1).  Gradients of u(t_n) go through a per-tile
+// scratch area.
+template <class CD>
+__device__ void prologue(const DevState &s, const Prologue &pro, int chunk, int b, int tid,
+                         int nthreads) {
+  using U = typename CD::U;
+  const TileChunk ch = pro.chunks[chunk];
+  const PlateDev P = s.plates[ch.plate];
+  U *grad = static_cast<U *>(pro.grad) + (int64_t)4 * ch.g0;
+  const U *ux = static_cast<const U *>(s.u[b][0]);
+  const U *uy = static_cast<const U *>(s.u[b][1]);
+  for (int g = ch.g0 + tid; g < ch.g1; g += nthreads) {
+    const TGradNode G = pro.gn[g];
+    const int cx = G.code & 7, cy = (G.code >> 3) & 7;
+    U *d = grad + 4 * (g - ch.g0);
+    d[0] = fd_code<U>(ux, P, G.i, G.j, 0, cx);
+    d[1] = fd_code<U>(ux, P, G.i, G.j, 1, cy);
+    d[2] = fd_code<U>(uy, P, G.i, G.j, 0, cx);
+    d[3] = fd_code<U>(uy, P, G.i, G.j, 1, cy);
+  }
+  __syncthreads();
+  const unsigned long long n = s.counter[b];
+  for (int t = ch.b0 + tid; t < ch.b1; t += nthreads) {
+    const BTask T = pro.bt[t];
+    boundary_task<CD>(s, P, T, grad, b ^ 1, b, true, T.accel != 0, b, b ^ 1, n);
+  }
+  const int nst = 2 * (ch.s1 - ch.s0);
+  for (int t = tid; t < nst; t += nthreads) {
+    const STask Q = pro.st[ch.s0 + (t >> 1)];
+    second_row_task<CD>(s, P, Q, t & 1, grad, b ^ 1, b, b);
+  }
+  __syncthreads();
+}
+
+// Boundary work of step n - 1 (b = n & 1) for every boundary node, one
+// block per chunk of boundary nodes (all of one plate): the same work as the
+// prologues of step n.  Phase 1 puts u(t_n) (buffer b) of every node the
+// chunk's stencils touch into LDS, phase 2 the finite-difference gradients;
+// phase 3 runs the boundary tasks (reset into population buffer b from the
+// populations at t_{n-1} in buffer b ^ 1 if do_reset; acceleration from u
+// buffer b into b ^ 1) and, if do_reset, the second-row tasks (one field per
+// thread).
+template <int ST>
+__global__ void __launch_bounds__(kBoundaryThreads)
+    k_boundary(DevState s, const Chunk *__restrict__ chunks, const UNode *__restrict__ un,
+               const GradNode *__restrict__ gn, const BTask *__restrict__ btask,
+               const STask *__restrict__ stask, int b, int do_reset) {
+  using CD = typename CodecOf<ST>::type;
+  using U = typename CD::U;
+  __shared__ U uu[kMaxU][2];
+  __shared__ U grad[kMaxGrad][4];
+  const Chunk ch = chunks[blockIdx.x];
+  const PlateDev P = s.plates[ch.plate];
+  const int tid = threadIdx.x;
+  for (int g = ch.u0 + tid; g < ch.u1; g += kBoundaryThreads) {
+    const int64_t k = un[g].node;
+    uu[g - ch.u0][0] = ldg<U>(s.u[b][0], k);
+    uu[g - ch.u0][1] = ldg<U>(s.u[b][1], k);
+  }
+  __syncthreads();
+  for (int g = ch.g0 + tid; g < ch.g1; g += kBoundaryThreads) {
+    const GradNode G = gn[g];
+    const int cx = G.code & 7, cy = (G.code >> 3) & 7;
+    U *d = grad[g - ch.g0];
+#pragma unroll
+    for (int c = 0; c < 2; c++) {
+      const U q0 = uu[G.u[0]][c];
+      d[2 * c + 0] = fd_vals<U>(cx, q0, uu[G.u[1]][c], uu[G.u[2]][c], P);
+      d[2 * c + 1] = fd_vals<U>(cy, q0, uu[G.u[3]][c], uu[G.u[4]][c], P);
+    }
+  }
+  __syncthreads();
+  const unsigned long long n = s.counter[b];
+  const int nb = ch.b1 - ch.b0;
+  if (tid < nb) {
+    const BTask T = btask[ch.b0 + tid];
+    boundary_task<CD>(s, P, T, &grad[0][0], b ^ 1, b, do_reset != 0, true, b, b ^ 1, n);
+  } else if (do_reset) {
+    const int t = tid - nb;
+    if (ch.s0 + (t >> 1) < ch.s1)
+      second_row_task<CD>(s, P, stask[ch.s0 + (t >> 1)], t & 1, &grad[0][0], b ^ 1, b, b);
+  }
+}
+
 // Interior acceleration of eq. navier, c_d^2 grad phi - c_s^2 curl(psi e_z)
 // with curl(psi e_z) = (d_y psi, -d_x psi) and central differences of the
 // neighbours' zeroth moments (E, W, N, S; field 0 = phi, 1 = psi), followed
@@ -409,18 +677,21 @@ __device__ __forceinline__ int tile_index(int b, int q) { return (b & 7) * q + (
 
 template <int ST, int TWL>
 __global__ void __launch_bounds__(TWL)
-    k_interior(DevState s, const Tile *__restrict__ tiles, int ntiles, int q, int cur) {
+    k_interior(DevState s, const Tile *__restrict__ tiles, int ntiles, int q, int b,
+               Prologue pro) {
   using CD = typename CodecOf<ST>::type;
   using C = typename CD::C;
   using U = typename CD::U;
   using Slot = typename CD::Slot;
   __shared__ C ex[3][X_N][TWL];
 
-  const int nxt = cur ^ 1;
-  if (blockIdx.x == 0 && threadIdx.x == 0) s.counter[nxt] = s.counter[cur] + 1ull;
+  // populations and u, du/dt of t_n in buffers b, of t_{n+1} in b ^ 1
+  const int pc = b, pn = b ^ 1, uc = b, un = b ^ 1;
+  if (blockIdx.x == 0 && threadIdx.x == 0) s.counter[un] = s.counter[uc] + 1ull;
   const int tix = tile_index(blockIdx.x, q);
   if (tix >= ntiles) return;
   const Tile t = tiles[tix];
+  if (pro.enabled && t.chunk >= 0) prologue<CD>(s, pro, t.chunk, b, (int)threadIdx.x, TWL);
   const PlateDev P = s.plates[t.plate];
   const int lane = threadIdx.x;
   const int w = t.x1 - t.x0;
@@ -460,18 +731,18 @@ __global__ void __launch_bounds__(TWL)
 #pragma unroll
       for (int qq = 0; qq < 5; qq++) raw[fl][qq] = Slot(0);
     if (ok) {
-      CD::load_raw(s, cur, 0, k, raw[0]);
-      CD::load_raw(s, cur, 1, k, raw[1]);
+      CD::load_raw(s, pc, 0, k, raw[0]);
+      CD::load_raw(s, pc, 1, k, raw[1]);
     }
   };
   auto load_uv = [&](int y, uint8_t cl, U uv[4]) {
     uv[0] = uv[1] = uv[2] = uv[3] = U(0);
     if (owned && (cl & (CL_IN | CL_B)) == CL_IN) {
       const int64_t k = node_of(P, x, y);
-      uv[0] = ldg<U>(s.u[cur][0], k);
-      uv[1] = ldg<U>(s.u[cur][1], k);
-      uv[2] = ldg<U>(s.v[cur][0], k);
-      uv[3] = ldg<U>(s.v[cur][1], k);
+      uv[0] = ldg<U>(s.u[uc][0], k);
+      uv[1] = ldg<U>(s.u[uc][1], k);
+      uv[2] = ldg<U>(s.v[uc][0], k);
+      uv[3] = ldg<U>(s.v[uc][1], k);
     }
   };
   auto collide_row = [&](uint8_t cl, const Slot raw[2][5], C rho[2], C fs[2][5]) {
@@ -560,21 +831,29 @@ __global__ void __launch_bounds__(TWL)
       interior_update<U>(P, (U)er0, (U)wr0, (U)nx_rho[0], (U)pr_rho[0], (U)er1, (U)wr1,
                          (U)nx_rho[1], (U)pr_rho[1], uv0[0], uv0[1], uv0[2], uv0[3], nux, nuy,
                          nvx, nvy);
-      stg<U>(s.u[nxt][0], k, nux);
-      stg<U>(s.u[nxt][1], k, nuy);
-      stg<U>(s.v[nxt][0], k, nvx);
-      stg<U>(s.v[nxt][1], k, nvy);
-      if (!(cu_cl & CL_S)) {
-        // Pull: f_alpha(x, t+dt) = f*_alpha(x - c^alpha dt).
+      stg<U>(s.u[un][0], k, nux);
+      stg<U>(s.u[un][1], k, nuy);
+      stg<U>(s.v[un][0], k, nvx);
+      stg<U>(s.v[un][1], k, nvy);
+      // Pull: f_alpha(x, t+dt) = f*_alpha(x - c^alpha dt).  A second-row
+      // node keeps it in the side buffer; the next step's boundary work
+      // replaces the populations that leave boundary nodes and stores it.
+      const bool sec = (cu_cl & CL_S) != 0;
+      const int64_t si = sec ? (int64_t)s.sidx[k] : 0;
+      C *side = static_cast<C *>(s.side[pn]);
 #pragma unroll
-        for (int fl = 0; fl < 2; fl++) {
-          C f[5];
-          f[0] = cu_f0[fl];
-          f[1] = ex[slot][fl == 0 ? X_F1_0 : X_F1_1][lane - 1];
-          f[2] = pr_f2[fl];
-          f[3] = ex[slot][fl == 0 ? X_F3_0 : X_F3_1][lane + 1];
-          f[4] = nx_fs[fl][4];
-          CD::store(s, nxt, fl, k, P, f);
+      for (int fl = 0; fl < 2; fl++) {
+        C f[5];
+        f[0] = cu_f0[fl];
+        f[1] = ex[slot][fl == 0 ? X_F1_0 : X_F1_1][lane - 1];
+        f[2] = pr_f2[fl];
+        f[3] = ex[slot][fl == 0 ? X_F3_0 : X_F3_1][lane + 1];
+        f[4] = nx_fs[fl][4];
+        if (!sec) {
+          CD::store(s, pn, fl, k, P, f);
+        } else {
+#pragma unroll
+          for (int qq = 0; qq < 5; qq++) side[(int64_t)(fl * 5 + qq) * s.nsec + si] = f[qq];
         }
       }
     }
@@ -598,245 +877,6 @@ __global__ void __launch_bounds__(TWL)
 #pragma unroll
     for (int qq = 0; qq < 4; qq++) uv0[qq] = uv1[qq];
     slot = nslot;
-  }
-}
-
-// ------------------------------------------- boundary / second-row kernel
-
-// Finite difference with a precomputed stencil code from the node's value
-// q0 and the values qa, qb of the further stencil nodes, branch-free:
-// ((c0 q0 + ca qa) + cb qb) * scale with the coefficients of the code
-// (central: qa - qb, one-sided 3-point: (-3 q0 + 4 qa) - qb and its mirror,
-// 2-point: qa - q0 and q0 - qa; these sums round exactly as the written-out
-// formulas); scale is 1/(2 dh) or 1/dh.
-template <class U>
-__device__ __forceinline__ U fd_vals(int code, U q0, U qa, U qb, const PlateDev &P) {
-  const bool cen = code == FD_CENTRAL, f3 = code == FD_FWD3, b3 = code == FD_BWD3;
-  const bool f2 = code == FD_FWD2, b2 = code == FD_BWD2;
-  const U c0 = f3 ? U(-3.0) : b3 ? U(3.0) : f2 ? U(-1.0) : b2 ? U(1.0) : U(0.0);
-  const U ca = (cen || f2) ? U(1.0) : f3 ? U(4.0) : b3 ? U(-4.0) : b2 ? U(-1.0) : U(0.0);
-  const U cb = (cen || f3) ? U(-1.0) : b3 ? U(1.0) : U(0.0);
-  const U sc = (f2 || b2) ? (U)P.inv_h : (cen || f3 || b3) ? (U)P.inv_2h : U(0.0);
-  return ((c0 * q0 + ca * qa) + cb * qb) * sc;
-}
-
-// Hooke's law (Sec. 2, eq. hooke) from a displacement gradient
-// g = (d_x u_x, d_y u_x, d_x u_y, d_y u_y).
-template <class U>
-__device__ __forceinline__ void hooke(const PlateDev &P, const U g[4], U &sxx, U &syy, U &sxy) {
-  const U exx = g[0], eyy = g[3];
-  const U exy = U(0.5) * (g[1] + g[2]);
-  const U tr = exx + eyy;
-  const U lam = (U)P.lam, mu = (U)P.mu;
-  sxx = lam * tr + U(2.0) * mu * exx;
-  syy = lam * tr + U(2.0) * mu * eyy;
-  sxy = U(2.0) * mu * exy;
-}
-
-// One block per chunk of boundary nodes (all of one plate).  Phase 1 puts
-// u(t+dt) of every node the chunk's stencils touch into LDS: boundary nodes
-// read it from buffer gb; with recompute set, interior nodes rebuild it from
-// the state at t (buffer cur) with the interior update (so this kernel does
-// not depend on the interior kernel of the same step); without, every node
-// reads buffer gb.  Phase 2 forms the finite-difference gradients of u.
-// Phase 3:
-//  - boundary tasks: if do_reset, the boundary reset of eqs.
-//    psi_phi_at_bound and correction-f into the populations of buffer
-//    cur ^ 1 (field from the gradient, flux of the populations of buffer
-//    cur); then the boundary acceleration of step n (eq. acc_dirichlet or
-//    eq. acc_neumann) from u, du/dt of buffer gb and its Newmark update
-//    (eq. integration) into buffer ub;
-//  - second-row tasks (do_reset only): the pull of eq. LBE_mod, where a
-//    population leaving a boundary node is collided from the average of its
-//    populations at t (buffer cur) and t+dt (the reset value).
-// n = counter[cslot] + step_off is the index of the step whose boundary
-// accelerations are computed.
-template <int ST>
-__global__ void __launch_bounds__(kBoundaryThreads)
-    k_boundary(DevState s, const Chunk *__restrict__ chunks, const UNode *__restrict__ un,
-               const GradNode *__restrict__ gn, const BTask *__restrict__ btask,
-               const STask *__restrict__ stask, int cur, int gb, int ub, int do_reset,
-               int recompute, int cslot, int step_off) {
-  using CD = typename CodecOf<ST>::type;
-  using C = typename CD::C;
-  using U = typename CD::U;
-  using Slot = typename CD::Slot;
-  __shared__ U uu[kMaxU][2];
-  __shared__ U grad[kMaxGrad][4];
-  const Chunk ch = chunks[blockIdx.x];
-  const PlateDev P = s.plates[ch.plate];
-  const int nxt = cur ^ 1;
-  const int tid = threadIdx.x;
-  const int di[5] = {0, 1, 0, -1, 0};
-  const int dj[5] = {0, 0, 1, 0, -1};
-
-  // records and the state they point at
-  const int nb = ch.b1 - ch.b0;
-  const bool hasB = tid < nb;
-  const int st_ix = (tid - nb) >> 1, sfl = (tid - nb) & 1;  // second-row task and field
-  const bool hasS = do_reset && tid >= nb && ch.s0 + st_ix < ch.s1;
-  BTask T{};
-  STask Q{};
-  if (hasB) T = btask[ch.b0 + tid];
-  if (hasS) Q = stask[ch.s0 + st_ix];
-  const int64_t k = T.b.node;
-  U ux0 = 0, uy0 = 0, vx0 = 0, vy0 = 0;
-  C jxb[2] = {0, 0}, jyb[2] = {0, 0};
-  if (hasB) {
-    ux0 = ldg<U>(s.u[gb][0], k);
-    uy0 = ldg<U>(s.u[gb][1], k);
-    vx0 = ldg<U>(s.v[gb][0], k);
-    vy0 = ldg<U>(s.v[gb][1], k);
-    if (do_reset) {
-      CD::flux(s, cur, 0, k, P, jxb[0], jyb[0]);
-      CD::flux(s, cur, 1, k, P, jxb[1], jyb[1]);
-    }
-  }
-  Slot raw[5][5];
-#pragma unroll
-  for (int al = 0; al < 5; al++)
-#pragma unroll
-    for (int qq = 0; qq < 5; qq++) raw[al][qq] = Slot(0);
-  if (hasS) {
-#pragma unroll
-    for (int al = 0; al < 5; al++) {
-      // upwind node x - c^alpha dt (in the body: x is interior)
-      const int64_t ky = node_of(P, wrapc(Q.i - di[al], P.nx), wrapc(Q.j - dj[al], P.ny));
-      CD::load_raw(s, cur, sfl, ky, raw[al]);
-    }
-  }
-
-  // phase 1: u(t+dt) of the displacement nodes
-  for (int g = ch.u0 + tid; g < ch.u1; g += kBoundaryThreads) {
-    const UNode N = un[g];
-    U nux, nuy;
-    if (N.bnd || !recompute) {
-      nux = ldg<U>(s.u[gb][0], N.node);
-      nuy = ldg<U>(s.u[gb][1], N.node);
-    } else {
-      C rho[4][2];
-#pragma unroll
-      for (int d = 0; d < 4; d++) {
-        const int64_t kn = node_of(P, wrapc(N.i + di[d + 1], P.nx), wrapc(N.j + dj[d + 1], P.ny));
-#pragma unroll
-        for (int fl = 0; fl < 2; fl++) {
-          Slot rw[5];
-          C f[5];
-          CD::load_raw(s, cur, fl, kn, rw);
-          CD::raw_to_pops(P, fl, rw, f);
-          rho[d][fl] = f[0] + ((f[1] + f[3]) + (f[2] + f[4]));
-        }
-      }
-      U nvx, nvy;
-      // neighbour order d: E, N, W, S
-      interior_update<U>(P, (U)rho[0][0], (U)rho[2][0], (U)rho[1][0], (U)rho[3][0], (U)rho[0][1],
-                         (U)rho[2][1], (U)rho[1][1], (U)rho[3][1], ldg<U>(s.u[cur][0], N.node),
-                         ldg<U>(s.u[cur][1], N.node), ldg<U>(s.v[cur][0], N.node),
-                         ldg<U>(s.v[cur][1], N.node), nux, nuy, nvx, nvy);
-    }
-    uu[g - ch.u0][0] = nux;
-    uu[g - ch.u0][1] = nuy;
-  }
-  __syncthreads();
-
-  // phase 2: gradients (d_x u_x, d_y u_x, d_x u_y, d_y u_y)
-  for (int g = ch.g0 + tid; g < ch.g1; g += kBoundaryThreads) {
-    const GradNode G = gn[g];
-    const int cx = G.code & 7, cy = (G.code >> 3) & 7;
-    U *d = grad[g - ch.g0];
-#pragma unroll
-    for (int c = 0; c < 2; c++) {
-      const U q0 = uu[G.u[0]][c];
-      d[2 * c + 0] = fd_vals<U>(cx, q0, uu[G.u[1]][c], uu[G.u[2]][c], P);
-      d[2 * c + 1] = fd_vals<U>(cy, q0, uu[G.u[3]][c], uu[G.u[4]][c], P);
-    }
-  }
-  __syncthreads();
-
-  // phase 3a: boundary task
-  if (hasB) {
-    const BndNode &B = T.b;
-    const U *gs = grad[T.g[0]];
-    if (do_reset) {
-      // div u and (curl u).e_z at the node
-      const U dv = gs[0] + gs[3];
-      const U cu = gs[2] - gs[1];
-      CD::store_eq(s, nxt, 0, k, P, (C)dv, jxb[0], jyb[0]);
-      CD::store_eq(s, nxt, 1, k, P, (C)cu, jxb[1], jyb[1]);
-    }
-    const unsigned long long n = s.counter[cslot] + (unsigned long long)step_off;
-    const U dt = (U)P.dt;
-    U ax, ay;
-    if (B.kind == LBM_BC_DIRICHLET) {
-      const double g = load_amp(s, B.load, (double)(n + 1) * P.dt);
-      const U usx = (U)(g * B.val[0]), usy = (U)(g * B.val[1]);
-      ax = U(2.0) / (dt * dt) * (usx - ux0) - U(2.0) / dt * vx0;
-      ay = U(2.0) / (dt * dt) * (usy - uy0) - U(2.0) / dt * vy0;
-    } else {
-      const double g = load_amp(s, B.load, (double)n * P.dt);
-      const U V = (U)B.cell[0], lE = (U)B.cell[1], lN = (U)B.cell[2], lW = (U)B.cell[3],
-              lS = (U)B.cell[4];
-      U sxx, syy, sxy, rxx, ryy, rxy;
-      hooke<U>(P, gs, sxx, syy, sxy);
-      U tEx = 0, tEy = 0, tWx = 0, tWy = 0, tNx = 0, tNy = 0, tSx = 0, tSy = 0;
-      // sigma_kr n_kr l_kr with sigma_kr the mean of the nodal stresses
-      if (T.g[1] >= 0) {
-        hooke<U>(P, grad[T.g[1]], rxx, ryy, rxy);
-        tEx = U(0.5) * (sxx + rxx) * lE;
-        tEy = U(0.5) * (sxy + rxy) * lE;
-      }
-      if (T.g[3] >= 0) {
-        hooke<U>(P, grad[T.g[3]], rxx, ryy, rxy);
-        tWx = -(U(0.5) * (sxx + rxx)) * lW;
-        tWy = -(U(0.5) * (sxy + rxy)) * lW;
-      }
-      if (T.g[2] >= 0) {
-        hooke<U>(P, grad[T.g[2]], rxx, ryy, rxy);
-        tNx = U(0.5) * (sxy + rxy) * lN;
-        tNy = U(0.5) * (syy + ryy) * lN;
-      }
-      if (T.g[4] >= 0) {
-        hooke<U>(P, grad[T.g[4]], rxx, ryy, rxy);
-        tSx = -(U(0.5) * (sxy + rxy)) * lS;
-        tSy = -(U(0.5) * (syy + ryy)) * lS;
-      }
-      const U Fx = (U)(g * B.val[0]), Fy = (U)(g * B.val[1]);
-      const U m = (U)P.rho_m * V;
-      ax = (((tEx + tWx) + (tNx + tSx)) + Fx) / m;
-      ay = (((tEy + tWy) + (tNy + tSy)) + Fy) / m;
-    }
-    const U nux = ux0 + dt * vx0 + dt * dt / U(2.0) * ax;
-    const U nuy = uy0 + dt * vy0 + dt * dt / U(2.0) * ay;
-    stg<U>(s.u[ub][0], k, nux);
-    stg<U>(s.u[ub][1], k, nuy);
-    stg<U>(s.v[ub][0], k, vx0 + dt * ax);
-    stg<U>(s.v[ub][1], k, vy0 + dt * ay);
-    if (!(fabs((double)nux) < 1e30) || !(fabs((double)nuy) < 1e30)) s.flag[0] = 1;
-  }
-
-  // phase 3b: second-row task, one field per thread
-  if (hasS) {
-    const int fl = sfl;
-    C fo[5];
-#pragma unroll
-    for (int al = 0; al < 5; al++) {
-      C f[5], r, fs[5];
-      CD::raw_to_pops(P, fl, raw[al], f);
-      if (Q.g[al] >= 0) {
-        // eq. LBE_mod: average of the populations at t and of the reset
-        // values at t+dt, collided with the equilibrium of their own moments
-        const U *gy = grad[Q.g[al]];
-        const C fld = fl == 0 ? (C)(gy[0] + gy[3]) : (C)(gy[2] - gy[1]);
-        C fnew[5], jx, jy;
-        CD::raw_flux(raw[al], jx, jy);
-        CD::eq_pops(P, fl, fld, jx, jy, fnew);
-#pragma unroll
-        for (int qq = 0; qq < 5; qq++) f[qq] = C(0.5) * (fnew[qq] + f[qq]);
-      }
-      collide_pops<CD>(P, fl, f, r, fs);
-      fo[al] = fs[al];
-    }
-    CD::store(s, nxt, fl, Q.node, P, fo);
   }
 }
 
@@ -911,10 +951,8 @@ __global__ void k_init_pops(DevState s, int plate, const double *__restrict__ e0
     div_curl<U>(s, 0, P, i, j, dv, cu);
     const C phi = e0 ? (C)e0[d] : (C)dv;
     const C psi = w0 ? (C)w0[d] : (C)cu;
-    for (int b = 0; b < 2; b++) {
-      CD::store_eq(s, b, 0, k, P, phi, C(0), C(0));
-      CD::store_eq(s, b, 1, k, P, psi, C(0), C(0));
-    }
+    CD::store_eq(s, 0, 0, k, P, phi, C(0), C(0));
+    CD::store_eq(s, 0, 1, k, P, psi, C(0), C(0));
   }
 }
 
@@ -948,18 +986,20 @@ __global__ void k_fields(DevState s, int plate, int b, double *e, double *w, dou
 
 template <int ST>
 static hipError_t launch_interior_t(const DevState &s, const Tile *tiles, int ntiles, int lanes,
-                                    int cur, hipStream_t st) {
+                                    int b, const Prologue &pro, hipStream_t st) {
   const int q = (ntiles + 7) / 8;
   const dim3 grid(8 * q);
   switch (lanes) {
     case 64:
-      hipLaunchKernelGGL((k_interior<ST, 64>), grid, dim3(64), 0, st, s, tiles, ntiles, q, cur);
+      hipLaunchKernelGGL((k_interior<ST, 64>), grid, dim3(64), 0, st, s, tiles, ntiles, q, b, pro);
       break;
     case 128:
-      hipLaunchKernelGGL((k_interior<ST, 128>), grid, dim3(128), 0, st, s, tiles, ntiles, q, cur);
+      hipLaunchKernelGGL((k_interior<ST, 128>), grid, dim3(128), 0, st, s, tiles, ntiles, q, b,
+                         pro);
       break;
     case 256:
-      hipLaunchKernelGGL((k_interior<ST, 256>), grid, dim3(256), 0, st, s, tiles, ntiles, q, cur);
+      hipLaunchKernelGGL((k_interior<ST, 256>), grid, dim3(256), 0, st, s, tiles, ntiles, q, b,
+                         pro);
       break;
     default:
       return hipErrorInvalidValue;
@@ -968,8 +1008,8 @@ static hipError_t launch_interior_t(const DevState &s, const Tile *tiles, int nt
 }
 
 template <int ST>
-static hipError_t launch_sync_t(const DevState &s, const Tile *tiles, int ntiles, int lanes, int b,
-                                hipStream_t st) {
+static hipError_t launch_sync_t(const DevState &s, const Tile *tiles, int ntiles, int lanes,
+                                int b, hipStream_t st) {
   const int q = (ntiles + 7) / 8;
   const dim3 grid(8 * q);
   switch (lanes) {
@@ -999,21 +1039,18 @@ static hipError_t launch_sync_t(const DevState &s, const Tile *tiles, int ntiles
   }
 
 hipError_t launch_interior(int st, const DevState &s, const Tile *tiles, int ntiles, int lanes,
-                           int cur, hipStream_t stream) {
+                           int b, const Prologue &pro, hipStream_t stream) {
   if (ntiles <= 0) return hipSuccess;
-  LBM_DISPATCH(st, return launch_interior_t<ST>(s, tiles, ntiles, lanes, cur, stream));
+  LBM_DISPATCH(st, return launch_interior_t<ST>(s, tiles, ntiles, lanes, b, pro, stream));
   return hipSuccess;
 }
 
 hipError_t launch_boundary(int st, const DevState &s, const Chunk *chunks, int nchunks,
                            const UNode *un, const GradNode *gn, const BTask *bt, const STask *stk,
-                           int cur, int gb, int ub, int do_reset, int recompute, int cslot,
-                           int step_off, hipStream_t stream) {
+                           int b, int do_reset, hipStream_t stream) {
   if (nchunks <= 0) return hipSuccess;
   LBM_DISPATCH(st, hipLaunchKernelGGL((k_boundary<ST>), dim3(nchunks), dim3(kBoundaryThreads), 0,
-                                      stream, s,
-                                      chunks, un, gn, bt, stk, cur, gb, ub, do_reset, recompute,
-                                      cslot, step_off));
+                                      stream, s, chunks, un, gn, bt, stk, b, do_reset));
   return hipGetLastError();
 }
 

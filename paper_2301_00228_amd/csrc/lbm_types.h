@@ -40,10 +40,12 @@ struct PlateDev {
   float iscale[2];
 };
 
-// Interior-kernel tile: owned columns [x0, x1) and rows [y0, y1) of a plate.
+// Interior-kernel tile: owned columns [x0, x1) and rows [y0, y1) of a plate;
+// chunk: index of its prologue work list (-1 = none).
 struct Tile {
   int32_t plate, x0, x1, y0, y1;
-  int32_t pad[3];
+  int32_t chunk;
+  int32_t pad[2];
 };
 
 // Boundary node record (one per node with a missing neighbour).
@@ -106,11 +108,29 @@ struct Chunk {
 
 // Boundary task: the boundary record of the node and the block-local
 // gradient indices of the node itself and of its E, N, W, S neighbours
-// (-1 where the neighbour is not in the body).
+// (-1 where the neighbour is not in the body).  accel: the task also
+// computes the node's next boundary acceleration (else only its reset).
 struct BTask {
   BndNode b;
   int32_t g[5];
-  int32_t pad[3];
+  int32_t accel;
+  int32_t pad[2];
+};
+
+// Work list of an interior tile's prologue: gradient nodes [g0, g1) (their
+// gradients go to the scratch rows g0..g1-1), boundary tasks [b0, b1),
+// second-row tasks [s0, s1), all of one plate.
+struct TileChunk {
+  int32_t g0, g1, b0, b1, s0, s1;
+  int32_t plate;
+  int32_t pad;
+};
+
+// Gradient node of a tile prologue (stencil read straight from u).
+struct TGradNode {
+  int64_t node;
+  int32_t i, j, code;
+  int32_t pad;
 };
 
 // Second-row task: the node and, per lattice direction alpha, the
@@ -120,7 +140,8 @@ struct STask {
   int64_t node;
   int32_t i, j;
   int32_t g[5];
-  int32_t pad[3];
+  int32_t si;  // second-row index
+  int32_t pad[2];
 };
 
 // Piecewise linear amplitude g(t).
@@ -136,9 +157,16 @@ struct LoadTable {
 // storages slots are (rho, J_x, J_y, N, Q - 4 a rho), where the 16-bit
 // variants pack N and Q - 4 a rho into slot 3 and leave slot 4 unused.
 struct DevState {
-  void *pop[2][2][5];  // [buffer][field][slot]
+  void *pop[2][2][5];  // [buffer][field][slot]; step n keeps t_n in buffer n & 1
   void *u[2][2];       // [buffer][component]
   void *v[2][2];
+  // Pulled populations of the second-row nodes from their non-boundary
+  // upwind nodes, written by the march of step n into side[(n + 1) & 1] (the
+  // collision type, [field][alpha][second-row index]); sidx: second-row
+  // index of a node (-1 elsewhere).
+  void *side[2];
+  const int32_t *sidx;
+  int64_t nsec;
   const uint8_t *cls;
   const PlateDev *plates;
   const LoadTable *loads;
@@ -149,6 +177,18 @@ struct DevState {
   // counter[cur ^ 1].
   unsigned long long *counter;
   int *flag;                    // nonzero once a non-finite / blown-up u is seen
+};
+
+// Prologue work lists of the interior kernel (see k_interior); grad:
+// per-tile gradient scratch (4 values of the displacement type per gradient
+// node).
+struct Prologue {
+  const TileChunk *chunks;
+  const TGradNode *gn;
+  const BTask *bt;
+  const STask *st;
+  void *grad;
+  int enabled;
 };
 
 }  // namespace lbm

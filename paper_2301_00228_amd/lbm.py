@@ -57,7 +57,8 @@ class lbm_info_t(C.Structure):
                 ("steps_done", C.c_int64), ("device_bytes", C.c_int64),
                 ("bytes_per_update", C.c_double), ("n_plates", C.c_int32),
                 ("storage", C.c_int32), ("tile_lanes", C.c_int32), ("tile_rows", C.c_int32),
-                ("tile_order", C.c_int32), ("n_tiles", C.c_int32)]
+                ("tile_order", C.c_int32), ("tile_edge_rows", C.c_int32),
+                ("n_tiles", C.c_int32)]
 
 
 _lib = None
@@ -87,7 +88,7 @@ def library():
     L.lbm_info.restype = C.c_int
     L.lbm_info.argtypes = [vp, C.POINTER(lbm_info_t)]
     L.lbm_set_tiling.restype = C.c_int
-    L.lbm_set_tiling.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32]
+    L.lbm_set_tiling.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
     L.lbm_autotune.restype = C.c_int
     L.lbm_autotune.argtypes = [vp, C.c_int32, dp]
     L.lbm_profile.restype = C.c_int
@@ -257,8 +258,9 @@ class Context:
         self._check(library().lbm_info(self._h, C.byref(i)))
         return {f: getattr(i, f) for f, _ in lbm_info_t._fields_}
 
-    def set_tiling(self, lanes, rows, order=0):
-        self._check(library().lbm_set_tiling(self._h, int(lanes), int(rows), int(order)))
+    def set_tiling(self, lanes, rows, order=0, edge_rows=0):
+        self._check(library().lbm_set_tiling(self._h, int(lanes), int(rows), int(order),
+                                             int(edge_rows)))
 
     def autotune(self, steps=5):
         best = C.c_double(0)

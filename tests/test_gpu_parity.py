@@ -119,21 +119,28 @@ def test_tilings_graphs_and_eager_are_bitwise_identical():
     case = I.plate_with_hole(n=100, radius=14, sigma=3.0, steps=130, sync_every=50)
     base = gpu_run(case, tiling=(128, 32))
     for tiling, graphs in [((64, 1, 0), True), ((256, 7, 1), False), ((128, 64, 2), False),
-                           ((64, 13, 1), True)]:
+                           ((64, 13, 1), True), ((128, 32, 0, 4), True), ((256, 9, 1, 2), False),
+                           ((64, 16, 2, 1), True)]:
         other = gpu_run(case, tiling=tiling, graphs=graphs)
         for k in FIELDS:
             assert np.array_equal(base[k], other[k]), (tiling, graphs, k)
 
 
-def test_autotune_keeps_the_state_and_results():
+@pytest.mark.parametrize("first", [60, 0, 50])
+def test_autotune_keeps_the_trajectory(first):
+    """Tuning mid-run (also at step 0 and at a synchronization step, where the
+    autotuner takes one real step first) leaves the results bitwise equal."""
     case = I.plate_batch(count=5, side_lo=30, side_hi=90, steps=120)
     base = gpu_run(case)
     with lbm.context_for(case) as ctx:
-        ctx.step(60)
+        ctx.step(first)
         ctx.autotune(2)
         info = ctx.info()
         assert info["tile_lanes"] in (64, 128, 256) and info["tile_order"] in (0, 1, 2)
-        ctx.step(60)
+        assert 1 <= info["tile_edge_rows"] <= info["tile_rows"]
+        done = info["steps_done"]
+        assert done == first + (1 if first in (0, 50) else 0), done
+        ctx.step(120 - done)
         tuned = [ctx.fields(p) for p in range(len(case))]
     for a, b in zip(base, tuned):
         for k in FIELDS:
