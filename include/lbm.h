@@ -172,25 +172,39 @@ typedef struct {
   int32_t tile_lanes, tile_rows; /* interior-kernel tile: lanes per workgroup, rows        */
   int32_t tile_order;         /* interior-tile packing order (see lbm_set_tiling)           */
   int32_t tile_edge_rows;     /* rows of the tiles that carry boundary work                 */
+  int32_t tile_align;         /* column-strip alignment in nodes (0: equal-width strips)    */
   int32_t n_tiles;
 } lbm_info_t;
 lbm_status lbm_info(const lbm_ctx *ctx, lbm_info_t *info);
 
-/* Interior-kernel tiling: lanes per workgroup (64, 128 or 256; a tile owns
- * lanes-2 columns), rows per tile (>= 1), packing order of the tile list
- * (0: plate by plate, row band by row band; 1: plate by plate, column strip
- * by column strip; 2: as 0 with the largest plates first) and edge_rows, the
- * rows of the tiles whose area or one-node halo ring holds boundary or
- * second-row nodes (those tiles finish the previous step's boundary work
- * before their march; 0 or >= rows: no shorter tiles).  Any tiling gives
- * bitwise the same results.  May be changed between steps; invalidates
- * captured step graphs.  LBM_E_INVAL on values out of range. */
-lbm_status lbm_set_tiling(lbm_ctx *ctx, int32_t lanes, int32_t rows, int32_t order,
-                          int32_t edge_rows);
+/* Interior-kernel tiling.  A tile is a strip of columns times a band of
+ * rows; one workgroup marches up (or down) its rows.
+ *  lanes      workgroup size, 64, 128 or 256; a tile owns at most lanes-2
+ *             columns (the two others read the halo columns);
+ *  rows       rows per tile (>= 1);
+ *  order      packing order of the tile list (0: plate by plate, row band by
+ *             row band; 1: plate by plate, column strip by column strip; 2:
+ *             as 0 with the largest plates first);
+ *  edge_rows  rows of the tiles whose area or one-node halo ring holds
+ *             boundary or second-row nodes (those tiles finish the previous
+ *             step's boundary work before their march; 0 or >= rows: no
+ *             shorter tiles);
+ *  align      0: column strips of equal width; > 0: strips of the largest
+ *             multiple of align nodes that fits (strip starts aligned to
+ *             align nodes, so that every row segment a tile writes covers
+ *             whole cache lines).
+ * Any tiling gives bitwise the same results.  May be changed between steps;
+ * invalidates captured step graphs.  LBM_E_INVAL on values out of range
+ * (align: 0..4096). */
+typedef struct {
+  int32_t lanes, rows, order, edge_rows, align;
+} lbm_tiling;
+lbm_status lbm_set_tiling(lbm_ctx *ctx, const lbm_tiling *tiling);
 
 /* Autotuner: time one step's interior launch (with the boundary work it
- * carries) for every tiling of a candidate set (lanes x rows x packing order
- * x edge rows) on this context's plates, `steps` launches each, and keep the
+ * carries) for every tiling of a candidate set (lanes x rows x edge rows x
+ * alignment, and packing order when there are several plates) on this
+ * context's plates, `steps` launches each, and keep the
  * fastest.  Repeating that launch leaves the state unchanged, except at step
  * 0 and at a synchronization step, where the autotuner first takes one real
  * step (steps_done grows by one; the trajectory is the same as without the

@@ -76,7 +76,7 @@ size_t slot_bytes(int st) {
 size_t uv_bytes(int st) { return st == LBM_STORE_F32 ? 4 : 8; }
 
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int>, std::tuple<int, int, int, int>> g_tune_cache;
+std::map<std::tuple<int, int, int>, lbm_tiling> g_tune_cache;
 
 }  // namespace
 
@@ -122,7 +122,7 @@ struct lbm_ctx {
   STask *d_stasks = nullptr;
   std::vector<LoadTable> loads;
   std::vector<Tile> tiles;
-  int lanes = 128, rows = 32, order = 0, edge_rows = 0;
+  int lanes = 128, rows = 32, order = 0, edge_rows = 0, align = 0;
 
   std::vector<Buffer> bufs;
   DevState ds{};
@@ -527,10 +527,12 @@ bool in_ring(int v, int lo, int hi, int n, bool per) {
 int band_of(int j, int rows, int nb) { return std::min(j / rows, nb - 1); }
 
 // Interior tiles: per plate, column strips of at most lanes-2 columns (of
-// equal width) times row bands of `rows` rows; a band piece whose area or
+// equal width, or of a multiple of align columns but the last) times row
+// bands of `rows` rows; a band piece whose area or
 // halo ring holds boundary or second-row nodes (a tile with a prologue) is
 // cut into pieces of edge_rows rows, so that its boundary work plus its
-// shorter march ends with the other tiles' marches.  order 0: plate by
+// shorter march ends with the other tiles' marches.  Vertically adjacent
+// tiles march in opposite directions (dir).  order 0: plate by
 // plate, band by band (strips of a band adjacent); 1: plate by plate, strip
 // by strip (bands of a strip adjacent); 2: as 0 with the plates by decreasing
 // size.  Consecutive tiles land on the same XCD (see k_interior), so the
@@ -550,8 +552,13 @@ void build_tiles(lbm_ctx *c) {
   std::vector<std::vector<uint8_t>> work(c->ph.size());
   for (size_t p = 0; p < c->ph.size(); p++) {
     PlateHost &h = c->ph[p];
-    h.ns = (h.nx + own - 1) / own;
-    h.sw = (h.nx + h.ns - 1) / h.ns;
+    if (c->align > 0 && own >= c->align) {
+      h.sw = own / c->align * c->align;
+      h.ns = (h.nx + h.sw - 1) / h.sw;
+    } else {
+      h.ns = (h.nx + own - 1) / own;
+      h.sw = (h.nx + h.ns - 1) / h.ns;
+    }
     const int nb = (h.ny + rows - 1) / rows;
     if (er < rows) work[p].assign((size_t)h.ns * nb, 0);
   }
@@ -589,10 +596,11 @@ void build_tiles(lbm_ctx *c) {
       const int x0 = s * w, x1 = std::min(h.nx, (s + 1) * w);
       const int y0 = b * rows, y1 = std::min(h.ny, (b + 1) * rows);
       const int hgt = (er < rows && work[(size_t)p][(size_t)s * nb + b]) ? er : rows;
-      for (int y = y0; y < y1; y += hgt) {
+      for (int y = y0, piece = 0; y < y1; y += hgt, piece++) {
         Tile t{};
         t.plate = p;
         t.chunk = -1;
+        t.dir = (b + piece) & 1;
         t.x0 = x0;
         t.x1 = x1;
         t.y0 = y;
@@ -1262,18 +1270,17 @@ lbm_status lbm_create(const lbm_plate *plates, int32_t n_plates, lbm_storage sto
                                (int)std::lround(std::log2((double)std::max<int64_t>(1, c->n_body))));
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
-      c->lanes = std::get<0>(it->second);
-      c->rows = std::get<1>(it->second);
-      c->order = std::get<2>(it->second);
-      c->edge_rows = std::get<3>(it->second);
+      c->lanes = it->second.lanes;
+      c->rows = it->second.rows;
+      c->order = it->second.order;
+      c->edge_rows = it->second.edge_rows;
+      c->align = it->second.align;
     } else {
-      c->lanes = 256;
-      c->rows = 64;
-      int64_t maxnx = 0;
-      for (auto &h : c->ph) maxnx = std::max<int64_t>(maxnx, h.nx);
-      if (maxnx <= 512) c->lanes = 128;
-      if (c->n_body < (int64_t)4 << 20) c->rows = 16;
-      c->edge_rows = 4;
+      // what the autotuner picks on 1024^2 (unaligned) and 4096^2 plates
+      c->lanes = 128;
+      c->rows = 8;
+      c->edge_rows = 2;
+      c->align = c->n_body < ((int64_t)4 << 20) ? 0 : 16;
     }
   }
   build_tiles(c);
@@ -1431,22 +1438,26 @@ lbm_status lbm_info(const lbm_ctx *c, lbm_info_t *info) {
   info->tile_rows = c->rows;
   info->tile_order = c->order;
   info->tile_edge_rows = (c->edge_rows > 0 && c->edge_rows < c->rows) ? c->edge_rows : c->rows;
+  info->tile_align = c->align;
   info->n_tiles = (int32_t)c->tiles.size();
   return LBM_OK;
 }
 
-lbm_status lbm_set_tiling(lbm_ctx *c, int32_t lanes, int32_t rows, int32_t order,
-                          int32_t edge_rows) {
-  if (!c) return LBM_E_INVAL;
+lbm_status lbm_set_tiling(lbm_ctx *c, const lbm_tiling *t) {
+  if (!c || !t) return LBM_E_INVAL;
+  const int32_t lanes = t->lanes, rows = t->rows, order = t->order, edge_rows = t->edge_rows,
+                align = t->align;
   if ((lanes != 64 && lanes != 128 && lanes != 256) || rows < 1 || rows > 65536 || order < 0 ||
-      order > 2 || edge_rows < 0)
+      order > 2 || edge_rows < 0 || align < 0 || align > 4096)
     return fail(c, LBM_E_INVAL,
-                "lanes must be 64, 128 or 256, rows >= 1, order 0..2, edge_rows >= 0");
+                "lanes must be 64, 128 or 256, rows >= 1, order 0..2, edge_rows >= 0, "
+                "align 0..4096");
   HIP_TRY(c, hipStreamSynchronize(c->stream), "synchronize");
   c->lanes = lanes;
   c->rows = rows;
   c->order = order;
   c->edge_rows = edge_rows;
+  c->align = align;
   build_tiles(c);
   build_tile_tables(c);
   lbm_status st = upload_tiles(c);
@@ -1514,55 +1525,56 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
   const bool with_prologue = !(c->sync_every > 0 && c->step % c->sync_every == 0);
   HIP_TRY(c, hipStreamSynchronize(c->stream), "synchronize");
   const int lane_set[3] = {64, 128, 256};
-  const int row_set[6] = {4, 8, 16, 32, 64, 128};
+  const int row_set[4] = {8, 16, 32, 64};
   const int edge_set[4] = {0, 8, 4, 2};
-  const int n_orders = c->ph.size() > 1 ? 3 : 2;
+  const int align_set[2] = {0, 16};
+  const int n_orders = c->ph.size() > 1 ? 3 : 1;
   hipEvent_t e0, e1;
   HIP_TRY(c, hipEventCreate(&e0), "event");
   HIP_TRY(c, hipEventCreate(&e1), "event");
   const int64_t n = c->step;
   double best = 1e300;
-  int bl = c->lanes, br = c->rows, bo = c->order, be = c->edge_rows;
+  lbm_tiling bt{c->lanes, c->rows, c->order, c->edge_rows, c->align};
   for (int O = 0; O < n_orders; O++)
     for (int L : lane_set)
       for (int R : row_set)
-        for (int E : edge_set) {
-          if (E != 0 && E >= R) continue;  // same tiling as E = 0
-          c->lanes = L;
-          c->rows = R;
-          c->order = O;
-          c->edge_rows = E;
-          build_tiles(c);
-          build_tile_tables(c);
-          if (upload_tiles(c) != LBM_OK || upload_tile_tables(c) != LBM_OK) continue;
-          const Prologue pro = make_prologue(c, n, with_prologue);
-          auto launch = [&] {
-            return launch_interior(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), L,
-                                   (int)(n & 1), pro, c->stream);
-          };
-          hipError_t e = launch();
-          (void)hipEventRecord(e0, c->stream);
-          for (int k = 0; k < steps && e == hipSuccess; k++) e = launch();
-          (void)hipEventRecord(e1, c->stream);
-          (void)hipEventSynchronize(e1);
-          if (e != hipSuccess) continue;
-          float t = 0;
-          (void)hipEventElapsedTime(&t, e0, e1);
-          const double per = t / steps;
-          if (per < best) {
-            best = per;
-            bl = L;
-            br = R;
-            bo = O;
-            be = E;
+        for (int E : edge_set)
+          for (int A : align_set) {
+            if (E != 0 && E >= R) continue;  // same tiling as E = 0
+            c->lanes = L;
+            c->rows = R;
+            c->order = O;
+            c->edge_rows = E;
+            c->align = A;
+            build_tiles(c);
+            build_tile_tables(c);
+            if (upload_tiles(c) != LBM_OK || upload_tile_tables(c) != LBM_OK) continue;
+            const Prologue pro = make_prologue(c, n, with_prologue);
+            auto launch = [&] {
+              return launch_interior(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), L,
+                                     (int)(n & 1), pro, c->stream);
+            };
+            hipError_t e = launch();
+            (void)hipEventRecord(e0, c->stream);
+            for (int k = 0; k < steps && e == hipSuccess; k++) e = launch();
+            (void)hipEventRecord(e1, c->stream);
+            (void)hipEventSynchronize(e1);
+            if (e != hipSuccess) continue;
+            float t = 0;
+            (void)hipEventElapsedTime(&t, e0, e1);
+            const double per = t / steps;
+            if (per < best) {
+              best = per;
+              bt = lbm_tiling{L, R, O, E, A};
+            }
           }
-        }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  c->lanes = bl;
-  c->rows = br;
-  c->order = bo;
-  c->edge_rows = be;
+  c->lanes = bt.lanes;
+  c->rows = bt.rows;
+  c->order = bt.order;
+  c->edge_rows = bt.edge_rows;
+  c->align = bt.align;
   build_tiles(c);
   build_tile_tables(c);
   st = upload_tiles(c);
@@ -1574,7 +1586,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto key = std::make_tuple(c->storage, c->ph.size() > 1 ? 1 : 0,
                                (int)std::lround(std::log2((double)std::max<int64_t>(1, c->n_body))));
-    g_tune_cache[key] = {bl, br, bo, be};
+    g_tune_cache[key] = bt;
   }
   if (best_ms) *best_ms = best;
   return LBM_OK;

@@ -767,48 +767,60 @@ __global__ void __launch_bounds__(TWL)
     ex[slot][X_F3_1][lane] = fs[1][3];
   };
 
+  // The march visits the rows upwards (d = +1) or downwards (d = -1, tiles
+  // with dir set): vertically adjacent tiles march in opposite directions,
+  // so the halo rows they share are read by both at about the same time and
+  // the second read hits in L2.  "Behind" is row r - d, "ahead" row r + d.
   // Software pipeline over rows: while row r is finalized, the populations
-  // of row r+2, u and du/dt of row r+1 and the class bytes of row r+3 are
-  // in flight.
-  C pr_rho[2], pr_f2[2];                 // row r-1
-  C cu_rho[2], cu_f0[2], cu_f2[2];       // row r
-  uint8_t cu_cl, cl1, cl2, cl3;          // classes of rows r, r+1, r+2, r+3
-  Slot raw1[2][5];                       // populations of row r+1
+  // of row r + 2d, u and du/dt of row r + d and the class bytes of row r + 3d
+  // are in flight.
+  const int d = t.dir ? -1 : 1;
+  const int h = t.y1 - t.y0;
+  const int r0 = t.dir ? t.y1 - 1 : t.y0;
+  // rows of the tile plus its halo rows: y0 - 1 .. y1
+  auto in_reach = [&](int k) { return k <= h; };  // row r0 + k d, k >= -1
+  C be_rho[2], be_f[2];                  // row r - d: rho, population streaming into r
+  C cu_rho[2], cu_f0[2], cu_fb[2];       // row r (cu_fb: streams into r + d)
+  uint8_t cu_cl, cl1, cl2, cl3;          // classes of rows r, r + d, r + 2d, r + 3d
+  Slot raw1[2][5];                       // populations of row r + d
   U uv0[4];                              // u, du/dt of row r
+  // the behind row streams population 2 (d = +1, from the south) or 4 into
+  // row r, the ahead row the other one
+  auto behind_pop = [&](const C fs[5]) { return d > 0 ? fs[2] : fs[4]; };
   {
-    const uint8_t clm = load_cls(t.y0 - 1);
-    cu_cl = load_cls(t.y0);
-    cl1 = load_cls(t.y0 + 1);
-    cl2 = load_cls(t.y0 + 2);
+    const uint8_t clm = load_cls(r0 - d);
+    cu_cl = load_cls(r0);
+    cl1 = load_cls(r0 + d);
+    cl2 = load_cls(r0 + 2 * d);
     Slot raw[2][5];
     C rho[2], fs[2][5];
-    load_raw(t.y0 - 1, clm, raw);
+    load_raw(r0 - d, clm, raw);
     collide_row(clm, raw, rho, fs);
-    pr_rho[0] = rho[0];
-    pr_rho[1] = rho[1];
-    pr_f2[0] = fs[0][2];
-    pr_f2[1] = fs[1][2];
-    load_raw(t.y0, cu_cl, raw);
-    load_raw(t.y0 + 1, cl1, raw1);
-    load_uv(t.y0, cu_cl, uv0);
+    be_rho[0] = rho[0];
+    be_rho[1] = rho[1];
+    be_f[0] = behind_pop(fs[0]);
+    be_f[1] = behind_pop(fs[1]);
+    load_raw(r0, cu_cl, raw);
+    load_raw(r0 + d, cl1, raw1);
+    load_uv(r0, cu_cl, uv0);
     collide_row(cu_cl, raw, rho, fs);
     publish(0, rho, fs);
     cu_rho[0] = rho[0];
     cu_rho[1] = rho[1];
     cu_f0[0] = fs[0][0];
     cu_f0[1] = fs[1][0];
-    cu_f2[0] = fs[0][2];
-    cu_f2[1] = fs[1][2];
+    cu_fb[0] = behind_pop(fs[0]);
+    cu_fb[1] = behind_pop(fs[1]);
   }
   int slot = 0;
-  for (int r = t.y0; r < t.y1; r++) {
+  for (int k = 0; k < h; k++) {
+    const int r = r0 + k * d;
     const int nslot = slot == 2 ? 0 : slot + 1;
     // prefetch
-    const bool more = r + 2 <= t.y1;
-    cl3 = (r + 3 <= t.y1) ? load_cls(r + 3) : (uint8_t)0;
+    cl3 = in_reach(k + 3) ? load_cls(r + 3 * d) : (uint8_t)0;
     Slot raw2[2][5];
-    if (more) {
-      load_raw(r + 2, cl2, raw2);
+    if (in_reach(k + 2)) {
+      load_raw(r + 2 * d, cl2, raw2);
     } else {
 #pragma unroll
       for (int fl = 0; fl < 2; fl++)
@@ -816,57 +828,59 @@ __global__ void __launch_bounds__(TWL)
         for (int qq = 0; qq < 5; qq++) raw2[fl][qq] = Slot(0);
     }
     U uv1[4];
-    load_uv(r + 1, (r + 1 < t.y1) ? cl1 : (uint8_t)0, uv1);
-    // collide row r+1 and hand its values to the x-neighbours
+    load_uv(r + d, (k + 1 < h) ? cl1 : (uint8_t)0, uv1);
+    // collide row r + d and hand its values to the x-neighbours
     C nx_rho[2], nx_fs[2][5];
     collide_row(cl1, raw1, nx_rho, nx_fs);
     publish(nslot, nx_rho, nx_fs);
     __syncthreads();
     const bool fin = owned && (cu_cl & (CL_IN | CL_B)) == CL_IN;
     if (fin) {
-      const int64_t k = node_of(P, x, r);
+      const int64_t kn = node_of(P, x, r);
       const C wr0 = ex[slot][X_RHO0][lane - 1], er0 = ex[slot][X_RHO0][lane + 1];
       const C wr1 = ex[slot][X_RHO1][lane - 1], er1 = ex[slot][X_RHO1][lane + 1];
+      // rho of the north / south neighbours
+      const C n0 = d > 0 ? nx_rho[0] : be_rho[0], s0 = d > 0 ? be_rho[0] : nx_rho[0];
+      const C n1 = d > 0 ? nx_rho[1] : be_rho[1], s1 = d > 0 ? be_rho[1] : nx_rho[1];
       U nux, nuy, nvx, nvy;
-      interior_update<U>(P, (U)er0, (U)wr0, (U)nx_rho[0], (U)pr_rho[0], (U)er1, (U)wr1,
-                         (U)nx_rho[1], (U)pr_rho[1], uv0[0], uv0[1], uv0[2], uv0[3], nux, nuy,
-                         nvx, nvy);
-      stg<U>(s.u[un][0], k, nux);
-      stg<U>(s.u[un][1], k, nuy);
-      stg<U>(s.v[un][0], k, nvx);
-      stg<U>(s.v[un][1], k, nvy);
+      interior_update<U>(P, (U)er0, (U)wr0, (U)n0, (U)s0, (U)er1, (U)wr1, (U)n1, (U)s1, uv0[0],
+                         uv0[1], uv0[2], uv0[3], nux, nuy, nvx, nvy);
+      stg<U>(s.u[un][0], kn, nux);
+      stg<U>(s.u[un][1], kn, nuy);
+      stg<U>(s.v[un][0], kn, nvx);
+      stg<U>(s.v[un][1], kn, nvy);
       // Pull: f_alpha(x, t+dt) = f*_alpha(x - c^alpha dt).  A second-row
       // node keeps it in the side buffer; the next step's boundary work
       // replaces the populations that leave boundary nodes and stores it.
       const bool sec = (cu_cl & CL_S) != 0;
-      const int64_t si = sec ? (int64_t)s.sidx[k] : 0;
+      const int64_t si = sec ? (int64_t)s.sidx[kn] : 0;
       C *side = static_cast<C *>(s.side[pn]);
 #pragma unroll
       for (int fl = 0; fl < 2; fl++) {
         C f[5];
         f[0] = cu_f0[fl];
         f[1] = ex[slot][fl == 0 ? X_F1_0 : X_F1_1][lane - 1];
-        f[2] = pr_f2[fl];
         f[3] = ex[slot][fl == 0 ? X_F3_0 : X_F3_1][lane + 1];
-        f[4] = nx_fs[fl][4];
+        f[2] = d > 0 ? be_f[fl] : nx_fs[fl][2];
+        f[4] = d > 0 ? nx_fs[fl][4] : be_f[fl];
         if (!sec) {
-          CD::store(s, pn, fl, k, P, f);
+          CD::store(s, pn, fl, kn, P, f);
         } else {
 #pragma unroll
           for (int qq = 0; qq < 5; qq++) side[(int64_t)(fl * 5 + qq) * s.nsec + si] = f[qq];
         }
       }
     }
-    pr_rho[0] = cu_rho[0];
-    pr_rho[1] = cu_rho[1];
-    pr_f2[0] = cu_f2[0];
-    pr_f2[1] = cu_f2[1];
+    be_rho[0] = cu_rho[0];
+    be_rho[1] = cu_rho[1];
+    be_f[0] = cu_fb[0];
+    be_f[1] = cu_fb[1];
     cu_rho[0] = nx_rho[0];
     cu_rho[1] = nx_rho[1];
     cu_f0[0] = nx_fs[0][0];
     cu_f0[1] = nx_fs[1][0];
-    cu_f2[0] = nx_fs[0][2];
-    cu_f2[1] = nx_fs[1][2];
+    cu_fb[0] = behind_pop(nx_fs[0]);
+    cu_fb[1] = behind_pop(nx_fs[1]);
     cu_cl = cl1;
     cl1 = cl2;
     cl2 = cl3;

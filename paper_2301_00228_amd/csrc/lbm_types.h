@@ -44,8 +44,9 @@ struct PlateDev {
 // chunk: index of its prologue work list (-1 = none).
 struct Tile {
   int32_t plate, x0, x1, y0, y1;
-  int32_t chunk;
-  int32_t pad[2];
+  int32_t chunk;  // prologue work list (-1: none)
+  int32_t dir;    // 1: the march visits the rows downwards
+  int32_t pad;
 };
 
 // Boundary node record (one per node with a missing neighbour).

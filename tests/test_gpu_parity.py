@@ -120,7 +120,8 @@ def test_tilings_graphs_and_eager_are_bitwise_identical():
     base = gpu_run(case, tiling=(128, 32))
     for tiling, graphs in [((64, 1, 0), True), ((256, 7, 1), False), ((128, 64, 2), False),
                            ((64, 13, 1), True), ((128, 32, 0, 4), True), ((256, 9, 1, 2), False),
-                           ((64, 16, 2, 1), True)]:
+                           ((64, 16, 2, 1), True), ((64, 8, 0, 2, 16), True),
+                           ((128, 5, 1, 3, 32), False), ((256, 16, 0, 0, 48), True)]:
         other = gpu_run(case, tiling=tiling, graphs=graphs)
         for k in FIELDS:
             assert np.array_equal(base[k], other[k]), (tiling, graphs, k)
@@ -138,6 +139,7 @@ def test_autotune_keeps_the_trajectory(first):
         info = ctx.info()
         assert info["tile_lanes"] in (64, 128, 256) and info["tile_order"] in (0, 1, 2)
         assert 1 <= info["tile_edge_rows"] <= info["tile_rows"]
+        assert info["tile_align"] in (0, 16)
         done = info["steps_done"]
         assert done == first + (1 if first in (0, 50) else 0), done
         ctx.step(120 - done)
