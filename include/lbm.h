@@ -213,9 +213,11 @@ lbm_status lbm_set_tiling(lbm_ctx *ctx, const lbm_tiling *tiling);
  * contexts.  best_ms (nullable) receives the fastest time per launch. */
 lbm_status lbm_autotune(lbm_ctx *ctx, int32_t steps, double *best_ms);
 
-/* Run n_steps steps eagerly (no graph), with a HIP event recorded on the
- * context's stream before and after every kernel launch, and return the
- * summed device time per kernel kind in ms: ms[0] interior stream+collide,
+/* Run n_steps steps eagerly (no graph), launches back to back with a HIP
+ * event recorded on the context's stream before the first and after every
+ * kernel launch, and return the summed time between consecutive events per
+ * kernel kind in ms (a launch's device time plus the gap after the previous
+ * one): ms[0] interior stream+collide,
  * ms[1] boundary/second-row, ms[2] synchronization, ms[3] all other; and
  * the number of launches of each kind in launches[0..3] (nullable).
  * Synchronizes the stream. */

@@ -122,12 +122,15 @@ struct lbm_ctx {
   STask *d_stasks = nullptr;
   std::vector<LoadTable> loads;
   std::vector<Tile> tiles;
-  int lanes = 128, rows = 32, order = 0, edge_rows = 0, align = 0;
+  std::vector<Tile> etiles;  // the single-step tiles (second launch of a two-step pair)
+  int lanes = 128, rows = 32, order = 0, edge_rows = 0, align = 0, two = 0;
 
   std::vector<Buffer> bufs;
   DevState ds{};
   PlateDev *d_plates = nullptr;
   Tile *d_tiles = nullptr;
+  Tile *d_etiles = nullptr;
+  size_t etiles_cap = 0;
   BndNode *d_bnd = nullptr;
   SecNode *d_sec = nullptr;
   LoadTable *d_loads = nullptr;
@@ -139,6 +142,8 @@ struct lbm_ctx {
   size_t tiles_cap = 0;
 
   int64_t step = 0;
+  int cur = 0;   // buffer holding the state of t_step
+  int prev = 1;  // buffer holding the boundary populations of t_{step-1}
   bool started = false;
   bool bnd_dirty = true;
 
@@ -146,6 +151,7 @@ struct lbm_ctx {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   int64_t gsteps = 0;
+  int gcur = 0, gprev = 0;  // buffers at the start (and end) of the captured steps
 
   int *h_flag = nullptr;
   hipEvent_t flag_ev = nullptr;
@@ -786,18 +792,28 @@ lbm_status upload_tile_tables(lbm_ctx *c) {
   return LBM_OK;
 }
 
-lbm_status upload_tiles(lbm_ctx *c) {
-  if (c->tiles.size() > c->tiles_cap) {
-    size_t cap = c->tiles.size() * 2;
-    Tile *d = (Tile *)dev_alloc(c, cap * sizeof(Tile));
-    if (!d) return fail(c, LBM_E_NOMEM, "tile list allocation failed");
-    c->d_tiles = d;
-    c->tiles_cap = cap;
+lbm_status upload_tile_list(lbm_ctx *c, const std::vector<Tile> &v, Tile *&d, size_t &cap) {
+  if (v.size() > cap || !d) {
+    const size_t nc = std::max<size_t>(16, v.size() * 2);
+    Tile *p = (Tile *)dev_alloc(c, nc * sizeof(Tile));
+    if (!p) return fail(c, LBM_E_NOMEM, "tile list allocation failed");
+    dev_free(c, d);
+    d = p;
+    cap = nc;
   }
-  HIP_TRY(c, hipMemcpy(c->d_tiles, c->tiles.data(), c->tiles.size() * sizeof(Tile),
-                       hipMemcpyHostToDevice),
-          "tile upload");
+  if (!v.empty())
+    HIP_TRY(c, hipMemcpy(d, v.data(), v.size() * sizeof(Tile), hipMemcpyHostToDevice),
+            "tile upload");
   return LBM_OK;
+}
+
+lbm_status upload_tiles(lbm_ctx *c) {
+  c->etiles.clear();
+  for (const Tile &t : c->tiles)
+    if (!(t.flags & TF_TWO)) c->etiles.push_back(t);
+  lbm_status st = upload_tile_list(c, c->tiles, c->d_tiles, c->tiles_cap);
+  if (st) return st;
+  return upload_tile_list(c, c->etiles, c->d_etiles, c->etiles_cap);
 }
 
 lbm_status upload_boundary(lbm_ctx *c) {
@@ -822,7 +838,7 @@ lbm_status upload_boundary(lbm_ctx *c) {
   return LBM_OK;
 }
 
-Prologue make_prologue(const lbm_ctx *c, int64_t n, bool enabled) {
+Prologue make_prologue(const lbm_ctx *c, bool enabled) {
   Prologue p{};
   p.chunks = c->d_tchunks;
   p.gn = c->d_tgn;
@@ -834,46 +850,89 @@ Prologue make_prologue(const lbm_ctx *c, int64_t n, bool enabled) {
 }
 
 // Steps [s, s + k) from a complete state at t_s (populations of t_s at every
-// body node, u and du/dt of t_s, boundary nodes' u and du/dt of t_{s+1}):
-// k interior launches, the later ones with the prologue that finishes the
-// previous step's boundary work; then one boundary launch finishing step
-// s + k - 1, which leaves the state complete at t_{s+k}; then the
-// synchronization if s + k is a multiple of l.  ev: events around each launch
-// for profiling (kind 0 interior, 1 boundary, 2 synchronization).
-hipError_t enqueue_segment(lbm_ctx *c, int64_t s, int64_t k, hipStream_t st, hipEvent_t *ev,
-                           double *ms, int64_t *cnt) {
+// body node, u and du/dt of t_s in buffer cur, the boundary nodes' u and
+// du/dt of t_{s+1} in the output buffers of the next step): one interior
+// launch per step -- or, with two-step tiles, per pair of steps a launch
+// that takes those tiles two steps and the others one, and a launch that
+// takes the others the second step -- every launch but the first finishing
+// the previous step's boundary work in its prologues; then one boundary
+// launch finishing step s + k - 1, which leaves the state complete at
+// t_{s+k}; then the synchronization if s + k is a multiple of l.  cur and
+// prev (buffers of t_s and of the boundary populations of t_{s-1}) are
+// advanced.  rec (profiling): an event after every launch, with the
+// launch's kind (0 interior, 1 boundary, 2 synchronization).
+struct LaunchRecorder {
+  std::vector<hipEvent_t> ev;  // ev[0] before the first launch, ev[i + 1] after launch i
+  std::vector<int> kind;
+};
+
+hipError_t enqueue_segment(lbm_ctx *c, int64_t s, int64_t k, int &cur, int &prev, hipStream_t st,
+                           LaunchRecorder *rec) {
   auto timed = [&](int kind, auto &&fn) -> hipError_t {
-    if (ev) (void)hipEventRecord(ev[0], st);
+    auto mark = [&]() -> hipError_t {
+      hipEvent_t e;
+      hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return r;
+      rec->ev.push_back(e);
+      return hipEventRecord(e, st);
+    };
+    if (rec && rec->ev.empty()) {
+      hipError_t r = mark();
+      if (r != hipSuccess) return r;
+    }
     hipError_t e = fn();
-    if (ev) {
-      (void)hipEventRecord(ev[1], st);
-      (void)hipEventSynchronize(ev[1]);
-      float t = 0;
-      (void)hipEventElapsedTime(&t, ev[0], ev[1]);
-      ms[kind] += t;
-      cnt[kind] += 1;
+    if (rec && e == hipSuccess) {
+      e = mark();
+      rec->kind.push_back(kind);
     }
     return e;
   };
+  const int T = 2;  // intermediate buffer of a two-step pair
   hipError_t e = hipSuccess;
-  for (int64_t n = s; n < s + k && e == hipSuccess; n++) {
-    const Prologue pro = make_prologue(c, n, n > s);
-    e = timed(0, [&] {
-      return launch_interior(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), c->lanes,
-                             (int)(n & 1), pro, st);
-    });
+  for (int64_t n = s; n < s + k && e == hipSuccess;) {
+    if (c->two && s + k - n >= 2) {
+      const StepBufs b1{cur, T, prev, (int)(n & 1), cur ^ 1};
+      const Prologue p1 = make_prologue(c, n > s);
+      e = timed(0, [&] {
+        return launch_interior(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), c->lanes, b1,
+                               p1, st);
+      });
+      if (e != hipSuccess) break;
+      const StepBufs b2{T, cur ^ 1, cur, (int)((n + 1) & 1), -1};
+      const Prologue p2 = make_prologue(c, true);
+      e = timed(0, [&] {
+        return launch_interior(c->storage, c->ds, c->d_etiles, (int)c->etiles.size(), c->lanes,
+                               b2, p2, st);
+      });
+      prev = T;
+      cur ^= 1;
+      n += 2;
+    } else {
+      const StepBufs b1{cur, cur ^ 1, prev, (int)(n & 1), -1};
+      const Prologue p1 = make_prologue(c, n > s);
+      e = timed(0, [&] {
+        return launch_interior(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), c->lanes, b1,
+                               p1, st);
+      });
+      prev = cur;
+      cur ^= 1;
+      n += 1;
+    }
   }
   if (e != hipSuccess) return e;
-  const int64_t m = s + k - 1;  // the step whose boundary work closes the segment
+  // The boundary work of step s + k - 1; the boundary nodes' u(t_{s+k+1})
+  // goes to both buffers the next step may write.
+  const int c_now = cur, p_now = prev;
   e = timed(1, [&] {
     return launch_boundary(c->storage, c->ds, c->d_chunks, (int)c->chunks.size(), c->d_unodes,
-                           c->d_gnodes, c->d_btasks, c->d_stasks, (int)((m + 1) & 1), 1, st);
+                           c->d_gnodes, c->d_btasks, c->d_stasks, c_now, p_now, c_now ^ 1, T,
+                           (int)((s + k) & 1), 1, st);
   });
   if (e != hipSuccess) return e;
   if (c->sync_every > 0 && (s + k) % c->sync_every == 0) {
     e = timed(2, [&] {
-      return launch_sync(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), c->lanes,
-                         (int)((s + k) & 1), st);
+      return launch_sync(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), c->lanes, c_now,
+                         st);
     });
   }
   return e;
@@ -885,28 +944,52 @@ int64_t segment_limit(const lbm_ctx *c, int64_t s, int64_t n) {
   return std::min<int64_t>(n, c->sync_every - s % c->sync_every);
 }
 
-// Steps per captured graph: even (buffer parity) and a multiple of l.
-int64_t graph_period(const lbm_ctx *c) {
-  int64_t g = 64;
-  if (c->sync_every > 0) {
-    g = c->sync_every % 2 ? 2 * c->sync_every : c->sync_every;
-    while (g < 32) g *= 2;
+// Buffers after the steps [s, s + n) from buffers (cur, prev), as
+// enqueue_segment leaves them.
+void advance_buffers(const lbm_ctx *c, int64_t s, int64_t n, int &cur, int &prev) {
+  while (n > 0) {
+    const int64_t k = segment_limit(c, s, n);
+    for (int64_t m = s; m < s + k;) {
+      if (c->two && s + k - m >= 2) {
+        prev = 2;
+        m += 2;
+      } else {
+        prev = cur;
+        m += 1;
+      }
+      cur ^= 1;
+    }
+    s += k;
+    n -= k;
   }
-  return g;
 }
 
-lbm_status ensure_graph(lbm_ctx *c) {
-  if (c->gexec) return LBM_OK;
-  const int64_t G = graph_period(c);
+// Steps per captured graph: a multiple of l that starts and ends on the same
+// buffers.
+int64_t graph_period(const lbm_ctx *c) {
+  int64_t g = c->sync_every > 0 ? c->sync_every : 64;
+  while (g < 32) g *= 2;
+  for (int r = 0; r < 4; r++, g *= 2) {
+    int cur = c->cur, prev = c->prev;
+    advance_buffers(c, 0, g, cur, prev);
+    if (cur == c->cur && prev == c->prev) return g;
+  }
+  return 0;  // no period found: eager stepping
+}
+
+lbm_status ensure_graph(lbm_ctx *c, int64_t G) {
+  if (c->gexec && c->gsteps == G && c->gcur == c->cur && c->gprev == c->prev) return LBM_OK;
+  drop_graph(c);
   if (!c->cap_stream)
     HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "capture stream");
 
   HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal),
           "begin capture");
   hipError_t e = hipSuccess;
+  int cur = c->cur, prev = c->prev;
   for (int64_t s = 0; s < G && e == hipSuccess;) {
     const int64_t k = segment_limit(c, s, G - s);
-    e = enqueue_segment(c, s, k, c->cap_stream, nullptr, nullptr, nullptr);
+    e = enqueue_segment(c, s, k, cur, prev, c->cap_stream, nullptr);
     s += k;
   }
   hipGraph_t g = nullptr;
@@ -925,6 +1008,8 @@ lbm_status ensure_graph(lbm_ctx *c) {
   c->graph = g;
   c->gexec = ge;
   c->gsteps = G;
+  c->gcur = c->cur;
+  c->gprev = c->prev;
   return LBM_OK;
 }
 
@@ -949,9 +1034,11 @@ lbm_status start(lbm_ctx *c) {
     lbm_status st = upload_boundary(c);
     if (st) return st;
   }
-  // boundary accelerations of step 0: u(t_1) of the boundary nodes
+  // boundary accelerations of step 0: u(t_1) of the boundary nodes, into
+  // both buffers the first step may write
   HIP_TRY(c, launch_boundary(c->storage, c->ds, c->d_chunks, (int)c->chunks.size(), c->d_unodes,
-                             c->d_gnodes, c->d_btasks, c->d_stasks, 0, 0, c->stream),
+                             c->d_gnodes, c->d_btasks, c->d_stasks, c->cur, c->prev, c->cur ^ 1,
+                             2, 0, 0, c->stream),
           "first boundary step");
   c->started = true;
   return LBM_OK;
@@ -1140,7 +1227,7 @@ lbm_status lbm_create(const lbm_plate *plates, int32_t n_plates, lbm_storage sto
   };
   const int64_t N = c->n_alloc;
   const int nsl = slot_count(c->storage);
-  for (int b = 0; b < 2; b++)
+  for (int b = 0; b < 3; b++)
     for (int fl = 0; fl < 2; fl++)
       for (int sl = 0; sl < 5; sl++) {
         if (sl >= nsl) {
@@ -1170,7 +1257,7 @@ lbm_status lbm_create(const lbm_plate *plates, int32_t n_plates, lbm_storage sto
       return bail(LBM_E_DEVICE, "second-row index upload");
     c->ds.sidx = d;
   }
-  for (int b = 0; b < 2; b++)
+  for (int b = 0; b < 3; b++)
     for (int comp = 0; comp < 2; comp++) {
       c->ds.u[b][comp] = dev_alloc(c, (size_t)N * uv_bytes(c->storage));
       c->ds.v[b][comp] = dev_alloc(c, (size_t)N * uv_bytes(c->storage));
@@ -1362,8 +1449,8 @@ lbm_status lbm_step(lbm_ctx *c, int64_t n) {
   while (n > 0) {
     if (c->use_graphs) {
       const int64_t G = graph_period(c);
-      if (n >= G && c->step % G == 0) {
-        st = ensure_graph(c);
+      if (G > 0 && n >= G && c->step % G == 0) {
+        st = ensure_graph(c, G);
         if (st) return st;
         HIP_TRY(c, hipGraphLaunch(c->gexec, c->stream), "graph launch");
         c->step += G;
@@ -1372,7 +1459,7 @@ lbm_status lbm_step(lbm_ctx *c, int64_t n) {
       }
     }
     const int64_t k = segment_limit(c, c->step, n);
-    HIP_TRY(c, enqueue_segment(c, c->step, k, c->stream, nullptr, nullptr, nullptr),
+    HIP_TRY(c, enqueue_segment(c, c->step, k, c->cur, c->prev, c->stream, nullptr),
             "step launch");
     c->step += k;
     n -= k;
@@ -1389,7 +1476,7 @@ lbm_status lbm_fields_device(lbm_ctx *c, int32_t plate, double *e, double *w, do
   if (!c) return LBM_E_INVAL;
   if (plate < 0 || plate >= (int)c->ph.size()) return fail(c, LBM_E_INVAL, "bad plate index");
   const PlateHost &h = c->ph[plate];
-  HIP_TRY(c, launch_fields(c->storage, c->ds, plate, (int64_t)h.nx * h.ny, (int)(c->step & 1), e,
+  HIP_TRY(c, launch_fields(c->storage, c->ds, plate, (int64_t)h.nx * h.ny, c->cur, e,
                            w, u, v, c->stream),
           "field kernel");
   return LBM_OK;
@@ -1480,22 +1567,28 @@ lbm_status lbm_profile(lbm_ctx *c, int64_t n, double *ms, int64_t *launches) {
   if (st) return st;
   st = start(c);
   if (st) return st;
-  hipEvent_t ev[2];
-  HIP_TRY(c, hipEventCreate(&ev[0]), "event");
-  HIP_TRY(c, hipEventCreate(&ev[1]), "event");
+  // Launches go back to back; the time between the events around a launch
+  // is its device time plus the gap to the previous launch's end.
+  LaunchRecorder rec;
   double acc[4] = {0, 0, 0, 0};
   int64_t cnt[4] = {0, 0, 0, 0};
   hipError_t e = hipSuccess;
   while (n > 0 && e == hipSuccess) {
     const int64_t k = segment_limit(c, c->step, n);
-    e = enqueue_segment(c, c->step, k, c->stream, ev, acc, cnt);
+    e = enqueue_segment(c, c->step, k, c->cur, c->prev, c->stream, &rec);
     if (e == hipSuccess) {
       c->step += k;
       n -= k;
     }
   }
-  (void)hipEventDestroy(ev[0]);
-  (void)hipEventDestroy(ev[1]);
+  if (e == hipSuccess && !rec.ev.empty()) e = hipEventSynchronize(rec.ev.back());
+  for (size_t i = 0; e == hipSuccess && i < rec.kind.size(); i++) {
+    float t = 0;
+    (void)hipEventElapsedTime(&t, rec.ev[i], rec.ev[i + 1]);
+    acc[rec.kind[i]] += t;
+    cnt[rec.kind[i]] += 1;
+  }
+  for (hipEvent_t ev : rec.ev) (void)hipEventDestroy(ev);
   if (e != hipSuccess) return hip_fail(c, e, "profiled step");
   for (int k = 0; k < 4; k++) {
     ms[k] = acc[k];
@@ -1519,7 +1612,8 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
   // first.
   const bool syncs_now = c->sync_every > 0 && c->step % c->sync_every == 0;
   if (c->step == 0 || (syncs_now && c->sync_every > 1)) {
-    HIP_TRY(c, enqueue_segment(c, c->step, 1, c->stream, nullptr, nullptr, nullptr), "step launch");
+    HIP_TRY(c, enqueue_segment(c, c->step, 1, c->cur, c->prev, c->stream, nullptr),
+            "step launch");
     c->step += 1;
   }
   const bool with_prologue = !(c->sync_every > 0 && c->step % c->sync_every == 0);
@@ -1549,10 +1643,11 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
             build_tiles(c);
             build_tile_tables(c);
             if (upload_tiles(c) != LBM_OK || upload_tile_tables(c) != LBM_OK) continue;
-            const Prologue pro = make_prologue(c, n, with_prologue);
+            const Prologue pro = make_prologue(c, with_prologue);
+            const StepBufs sb{c->cur, c->cur ^ 1, c->prev, (int)(n & 1), -1};
             auto launch = [&] {
-              return launch_interior(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), L,
-                                     (int)(n & 1), pro, c->stream);
+              return launch_interior(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), L, sb,
+                                     pro, c->stream);
             };
             hipError_t e = launch();
             (void)hipEventRecord(e0, c->stream);

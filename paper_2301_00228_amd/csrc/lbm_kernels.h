@@ -8,16 +8,17 @@
 namespace lbm {
 
 // Interior stream+collide, u and du/dt update of every interior node at
-// step n (b = n & 1): populations, u and du/dt from buffers b into b ^ 1;
-// tiles with a prologue list first finish the previous step's boundary work
-// if pro.enabled.  lanes: 64, 128 or 256.
+// step n (buffers b, see StepBufs); tiles with a prologue list first finish
+// the previous step's boundary work if pro.enabled.  lanes: 64, 128 or 256.
 hipError_t launch_interior(int storage, const DevState &s, const Tile *tiles, int ntiles,
-                           int lanes, int b, const Prologue &pro, hipStream_t stream);
+                           int lanes, const StepBufs &b, const Prologue &pro, hipStream_t stream);
 // Boundary kernel over nchunks chunks (see k_boundary): the boundary work of
-// step n - 1 with b = n & 1 (resets and second-row pulls only if do_reset).
+// step n - 1 on the state of t_n in buffer bc (resets and second-row pulls
+// only if do_reset).
 hipError_t launch_boundary(int storage, const DevState &s, const Chunk *chunks, int nchunks,
                            const UNode *un, const GradNode *gn, const BTask *bt, const STask *stk,
-                           int b, int do_reset, hipStream_t stream);
+                           int bc, int bp, int ub, int ub2, int sr, int do_reset,
+                           hipStream_t stream);
 // Synchronization of the state in buffers b.
 hipError_t launch_sync(int storage, const DevState &s, const Tile *tiles, int ntiles, int lanes,
                        int b, hipStream_t stream);

@@ -25,12 +25,13 @@
 //              precedes every synchronization) so the state is complete.
 //  k_sync      the synchronization of Sec. 3.2 every l steps.
 //
-// Populations, u and du/dt ping-pong through two buffers (step n keeps t_n
-// in buffer n & 1).  The march never writes boundary or second-row nodes:
-// boundary nodes keep their populations of t_{n-1} in buffer b ^ 1, which
-// the prologue reads, and second-row nodes' pulls go to a small side buffer
-// (also two of them) that the next step's boundary work completes.
-// Boundary nodes' u(t_{n+1}) is written one step ahead.
+// Populations, u and du/dt ping-pong through two buffers (a third holds the
+// intermediate time level of two-step launches).  The march never writes
+// boundary or second-row nodes: boundary nodes keep their populations of
+// t_{n-1} in the previous buffer, which the prologue reads, and second-row
+// nodes' pulls go to a small side buffer (two of them, by step parity) that
+// the next step's boundary work completes.  Boundary nodes' u(t_{n+1}) is
+// written one step ahead.
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
@@ -438,11 +439,11 @@ __device__ __forceinline__ void hooke(const PlateDev &P, const U *g, U &sxx, U &
 //    (buffer po), written to buffer pn;
 //  accel (eq. acc_dirichlet or eq. acc_neumann, step n with loads at n dt /
 //    (n+1) dt): u, du/dt at t from buffer ua, Newmark update (eq.
-//    integration) into buffer ub.
+//    integration) into buffer ub (and ub2 if >= 0).
 template <class CD>
 __device__ void boundary_task(const DevState &s, const PlateDev &P, const BTask &T,
                               const typename CD::U *grad, int po, int pn, bool reset, bool accel,
-                              int ua, int ub, unsigned long long n) {
+                              int ua, int ub, int ub2, unsigned long long n) {
   using C = typename CD::C;
   using U = typename CD::U;
   const BndNode &B = T.b;
@@ -502,10 +503,17 @@ __device__ void boundary_task(const DevState &s, const PlateDev &P, const BTask 
   }
   const U nux = ux0 + dt * vx0 + dt * dt / U(2.0) * ax;
   const U nuy = uy0 + dt * vy0 + dt * dt / U(2.0) * ay;
+  const U nvx = vx0 + dt * ax, nvy = vy0 + dt * ay;
   stg<U>(s.u[ub][0], k, nux);
   stg<U>(s.u[ub][1], k, nuy);
-  stg<U>(s.v[ub][0], k, vx0 + dt * ax);
-  stg<U>(s.v[ub][1], k, vy0 + dt * ay);
+  stg<U>(s.v[ub][0], k, nvx);
+  stg<U>(s.v[ub][1], k, nvy);
+  if (ub2 >= 0) {
+    stg<U>(s.u[ub2][0], k, nux);
+    stg<U>(s.u[ub2][1], k, nuy);
+    stg<U>(s.v[ub2][0], k, nvx);
+    stg<U>(s.v[ub2][1], k, nvy);
+  }
   if (!(fabs((double)nux) < 1e30) || !(fabs((double)nuy) < 1e30)) s.flag[0] = 1;
 }
 
@@ -554,22 +562,22 @@ __device__ void second_row_task(const DevState &s, const PlateDev &P, const STas
   CD::store(s, pn, fl, Q.node, P, fo);
 }
 
-// Prologue of an interior tile at step n (parity b = n & 1): the boundary
-// work of step n - 1 for the boundary and second-row nodes of the tile and
-// its halo ring (resets and pulls into buffer b, which the march then
-// reads, from the populations at t_{n-1} in buffer b ^ 1 and the side
-// buffer b) and the next boundary accelerations of the tile's own boundary
-// nodes (u buffer b to b ^ 1).  Gradients of u(t_n) go through a per-tile
-// scratch area.
+// Prologue of an interior tile at step n (buffers sb): the boundary work
+// of step n - 1 for the boundary and second-row nodes of the tile and its
+// halo ring (resets and pulls into buffer sb.in, which the march then reads,
+// from the populations of t_{n-1} in buffer sb.prev and the side buffer
+// sb.sp) and the next boundary accelerations of the tile's own boundary
+// nodes (u buffer sb.in to sb.out).  Gradients of u(t_n) go through a
+// per-tile scratch area.
 template <class CD>
-__device__ void prologue(const DevState &s, const Prologue &pro, int chunk, int b, int tid,
-                         int nthreads) {
+__device__ void prologue(const DevState &s, const Prologue &pro, int chunk, const StepBufs &sb,
+                         int tid, int nthreads) {
   using U = typename CD::U;
   const TileChunk ch = pro.chunks[chunk];
   const PlateDev P = s.plates[ch.plate];
   U *grad = static_cast<U *>(pro.grad) + (int64_t)4 * ch.g0;
-  const U *ux = static_cast<const U *>(s.u[b][0]);
-  const U *uy = static_cast<const U *>(s.u[b][1]);
+  const U *ux = static_cast<const U *>(s.u[sb.in][0]);
+  const U *uy = static_cast<const U *>(s.u[sb.in][1]);
   for (int g = ch.g0 + tid; g < ch.g1; g += nthreads) {
     const TGradNode G = pro.gn[g];
     const int cx = G.code & 7, cy = (G.code >> 3) & 7;
@@ -580,32 +588,33 @@ __device__ void prologue(const DevState &s, const Prologue &pro, int chunk, int 
     d[3] = fd_code<U>(uy, P, G.i, G.j, 1, cy);
   }
   __syncthreads();
-  const unsigned long long n = s.counter[b];
+  const unsigned long long n = s.counter[sb.in];
   for (int t = ch.b0 + tid; t < ch.b1; t += nthreads) {
     const BTask T = pro.bt[t];
-    boundary_task<CD>(s, P, T, grad, b ^ 1, b, true, T.accel != 0, b, b ^ 1, n);
+    boundary_task<CD>(s, P, T, grad, sb.prev, sb.in, true, T.accel != 0, sb.in, sb.out, -1, n);
   }
   const int nst = 2 * (ch.s1 - ch.s0);
   for (int t = tid; t < nst; t += nthreads) {
     const STask Q = pro.st[ch.s0 + (t >> 1)];
-    second_row_task<CD>(s, P, Q, t & 1, grad, b ^ 1, b, b);
+    second_row_task<CD>(s, P, Q, t & 1, grad, sb.prev, sb.in, sb.sp);
   }
   __syncthreads();
 }
 
-// Boundary work of step n - 1 (b = n & 1) for every boundary node, one
-// block per chunk of boundary nodes (all of one plate): the same work as the
-// prologues of step n.  Phase 1 puts u(t_n) (buffer b) of every node the
-// chunk's stencils touch into LDS, phase 2 the finite-difference gradients;
-// phase 3 runs the boundary tasks (reset into population buffer b from the
-// populations at t_{n-1} in buffer b ^ 1 if do_reset; acceleration from u
-// buffer b into b ^ 1) and, if do_reset, the second-row tasks (one field per
-// thread).
+// Boundary work of step n - 1 for every boundary node, one block per chunk
+// of boundary nodes (all of one plate): the same work as the prologues of
+// step n.  The state of t_n is in buffer bc, the boundary populations of
+// t_{n-1} in bp, the second-row pulls in side[sr].  Phase 1 puts u(t_n) of
+// every node the chunk's stencils touch into LDS, phase 2 the
+// finite-difference gradients; phase 3 runs the boundary tasks (reset into
+// buffer bc if do_reset; acceleration into u buffer ub, and ub2 if >= 0) and,
+// if do_reset, the second-row tasks (one field per thread).
 template <int ST>
 __global__ void __launch_bounds__(kBoundaryThreads)
     k_boundary(DevState s, const Chunk *__restrict__ chunks, const UNode *__restrict__ un,
                const GradNode *__restrict__ gn, const BTask *__restrict__ btask,
-               const STask *__restrict__ stask, int b, int do_reset) {
+               const STask *__restrict__ stask, int bc, int bp, int ub, int ub2, int sr,
+               int do_reset) {
   using CD = typename CodecOf<ST>::type;
   using U = typename CD::U;
   __shared__ U uu[kMaxU][2];
@@ -615,8 +624,8 @@ __global__ void __launch_bounds__(kBoundaryThreads)
   const int tid = threadIdx.x;
   for (int g = ch.u0 + tid; g < ch.u1; g += kBoundaryThreads) {
     const int64_t k = un[g].node;
-    uu[g - ch.u0][0] = ldg<U>(s.u[b][0], k);
-    uu[g - ch.u0][1] = ldg<U>(s.u[b][1], k);
+    uu[g - ch.u0][0] = ldg<U>(s.u[bc][0], k);
+    uu[g - ch.u0][1] = ldg<U>(s.u[bc][1], k);
   }
   __syncthreads();
   for (int g = ch.g0 + tid; g < ch.g1; g += kBoundaryThreads) {
@@ -631,15 +640,15 @@ __global__ void __launch_bounds__(kBoundaryThreads)
     }
   }
   __syncthreads();
-  const unsigned long long n = s.counter[b];
+  const unsigned long long n = s.counter[bc];
   const int nb = ch.b1 - ch.b0;
   if (tid < nb) {
     const BTask T = btask[ch.b0 + tid];
-    boundary_task<CD>(s, P, T, &grad[0][0], b ^ 1, b, do_reset != 0, true, b, b ^ 1, n);
+    boundary_task<CD>(s, P, T, &grad[0][0], bp, bc, do_reset != 0, true, bc, ub, ub2, n);
   } else if (do_reset) {
     const int t = tid - nb;
     if (ch.s0 + (t >> 1) < ch.s1)
-      second_row_task<CD>(s, P, stask[ch.s0 + (t >> 1)], t & 1, &grad[0][0], b ^ 1, b, b);
+      second_row_task<CD>(s, P, stask[ch.s0 + (t >> 1)], t & 1, &grad[0][0], bp, bc, sr);
   }
 }
 
@@ -677,7 +686,7 @@ __device__ __forceinline__ int tile_index(int b, int q) { return (b & 7) * q + (
 
 template <int ST, int TWL>
 __global__ void __launch_bounds__(TWL)
-    k_interior(DevState s, const Tile *__restrict__ tiles, int ntiles, int q, int b,
+    k_interior(DevState s, const Tile *__restrict__ tiles, int ntiles, int q, StepBufs sb,
                Prologue pro) {
   using CD = typename CodecOf<ST>::type;
   using C = typename CD::C;
@@ -685,13 +694,13 @@ __global__ void __launch_bounds__(TWL)
   using Slot = typename CD::Slot;
   __shared__ C ex[3][X_N][TWL];
 
-  // populations and u, du/dt of t_n in buffers b, of t_{n+1} in b ^ 1
-  const int pc = b, pn = b ^ 1, uc = b, un = b ^ 1;
+  // populations and u, du/dt of t_n in buffers sb.in, of t_{n+1} in sb.out
+  const int pc = sb.in, pn = sb.out, uc = sb.in, un = sb.out;
   if (blockIdx.x == 0 && threadIdx.x == 0) s.counter[un] = s.counter[uc] + 1ull;
   const int tix = tile_index(blockIdx.x, q);
   if (tix >= ntiles) return;
   const Tile t = tiles[tix];
-  if (pro.enabled && t.chunk >= 0) prologue<CD>(s, pro, t.chunk, b, (int)threadIdx.x, TWL);
+  if (pro.enabled && t.chunk >= 0) prologue<CD>(s, pro, t.chunk, sb, (int)threadIdx.x, TWL);
   const PlateDev P = s.plates[t.plate];
   const int lane = threadIdx.x;
   const int w = t.x1 - t.x0;
@@ -854,7 +863,7 @@ __global__ void __launch_bounds__(TWL)
       // replaces the populations that leave boundary nodes and stores it.
       const bool sec = (cu_cl & CL_S) != 0;
       const int64_t si = sec ? (int64_t)s.sidx[kn] : 0;
-      C *side = static_cast<C *>(s.side[pn]);
+      C *side = static_cast<C *>(s.side[sb.sp ^ 1]);
 #pragma unroll
       for (int fl = 0; fl < 2; fl++) {
         C f[5];
@@ -939,7 +948,7 @@ __global__ void k_init_uv(DevState s, int plate, const double *__restrict__ u0,
     const bool in = (s.cls[k] & CL_IN) != 0;
     const U ux = in && u0 ? (U)u0[d] : U(0), uy = in && u0 ? (U)u0[n + d] : U(0);
     const U vx = in && v0 ? (U)v0[d] : U(0), vy = in && v0 ? (U)v0[n + d] : U(0);
-    for (int b = 0; b < 2; b++) {
+    for (int b = 0; b < 3; b++) {
       stg<U>(s.u[b][0], k, ux);
       stg<U>(s.u[b][1], k, uy);
       stg<U>(s.v[b][0], k, vx);
@@ -1000,7 +1009,7 @@ __global__ void k_fields(DevState s, int plate, int b, double *e, double *w, dou
 
 template <int ST>
 static hipError_t launch_interior_t(const DevState &s, const Tile *tiles, int ntiles, int lanes,
-                                    int b, const Prologue &pro, hipStream_t st) {
+                                    const StepBufs &b, const Prologue &pro, hipStream_t st) {
   const int q = (ntiles + 7) / 8;
   const dim3 grid(8 * q);
   switch (lanes) {
@@ -1053,7 +1062,7 @@ static hipError_t launch_sync_t(const DevState &s, const Tile *tiles, int ntiles
   }
 
 hipError_t launch_interior(int st, const DevState &s, const Tile *tiles, int ntiles, int lanes,
-                           int b, const Prologue &pro, hipStream_t stream) {
+                           const StepBufs &b, const Prologue &pro, hipStream_t stream) {
   if (ntiles <= 0) return hipSuccess;
   LBM_DISPATCH(st, return launch_interior_t<ST>(s, tiles, ntiles, lanes, b, pro, stream));
   return hipSuccess;
@@ -1061,10 +1070,12 @@ hipError_t launch_interior(int st, const DevState &s, const Tile *tiles, int nti
 
 hipError_t launch_boundary(int st, const DevState &s, const Chunk *chunks, int nchunks,
                            const UNode *un, const GradNode *gn, const BTask *bt, const STask *stk,
-                           int b, int do_reset, hipStream_t stream) {
+                           int bc, int bp, int ub, int ub2, int sr, int do_reset,
+                           hipStream_t stream) {
   if (nchunks <= 0) return hipSuccess;
   LBM_DISPATCH(st, hipLaunchKernelGGL((k_boundary<ST>), dim3(nchunks), dim3(kBoundaryThreads), 0,
-                                      stream, s, chunks, un, gn, bt, stk, b, do_reset));
+                                      stream, s, chunks, un, gn, bt, stk, bc, bp, ub, ub2, sr,
+                                      do_reset));
   return hipGetLastError();
 }
 

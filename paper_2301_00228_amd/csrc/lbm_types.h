@@ -46,8 +46,11 @@ struct Tile {
   int32_t plate, x0, x1, y0, y1;
   int32_t chunk;  // prologue work list (-1: none)
   int32_t dir;    // 1: the march visits the rows downwards
-  int32_t pad;
+  // bits 0-3: export the t_{n+1} populations of the first/last owned column
+  // and row (W, E, S, N) of a two-step tile; bit 4: two-step tile
+  int32_t flags;
 };
+enum { TF_EXP_W = 1, TF_EXP_E = 2, TF_EXP_S = 4, TF_EXP_N = 8, TF_TWO = 16 };
 
 // Boundary node record (one per node with a missing neighbour).
 struct BndNode {
@@ -158,9 +161,12 @@ struct LoadTable {
 // storages slots are (rho, J_x, J_y, N, Q - 4 a rho), where the 16-bit
 // variants pack N and Q - 4 a rho into slot 3 and leave slot 4 unused.
 struct DevState {
-  void *pop[2][2][5];  // [buffer][field][slot]; step n keeps t_n in buffer n & 1
-  void *u[2][2];       // [buffer][component]
-  void *v[2][2];
+  // [buffer][field][slot]: buffers 0 and 1 hold the state between launches
+  // (the current one alternates), buffer 2 the intermediate time level of
+  // a two-step launch near boundaries
+  void *pop[3][2][5];
+  void *u[3][2];       // [buffer][component]
+  void *v[3][2];
   // Pulled populations of the second-row nodes from their non-boundary
   // upwind nodes, written by the march of step n into side[(n + 1) & 1] (the
   // collision type, [field][alpha][second-row index]); sidx: second-row
@@ -173,11 +179,19 @@ struct DevState {
   const LoadTable *loads;
   const BndNode *bnd;
   const SecNode *sec;
-  // Step counters, one per buffer parity: during step n (buffer cur = n & 1)
-  // counter[cur] holds n; the interior kernel of step n writes n + 1 into
-  // counter[cur ^ 1].
+  // counter[b]: index of the time step whose state buffer b holds; a
+  // launch writing buffer b sets it.
   unsigned long long *counter;
   int *flag;                    // nonzero once a non-finite / blown-up u is seen
+};
+
+// Buffers of one single-step launch (step n): the state of t_n in buffer
+// `in`, t_{n+1} written to `out`; the boundary nodes' populations of t_{n-1}
+// in `prev` (read by the prologue); sp = n & 1 (the prologue reads side[sp],
+// the march writes side[sp ^ 1]).  A two-step tile (kind 1) writes t_{n+2}
+// to out2 and the t_{n+1} populations of its export bands to `out`.
+struct StepBufs {
+  int in, out, prev, sp, out2;
 };
 
 // Prologue work lists of the interior kernel (see k_interior); grad:
