@@ -87,9 +87,9 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=200)
     ap.add_argument("--storage", default="f64", help="storage of the headline run")
-    ap.add_argument("--tiling", default="", metavar="L,R,O,E,A",
-                    help="fixed interior tiling (lanes, rows, order, edge rows, alignment) "
-                         "instead of the autotuner, e.g. to profile one tiling's launches only")
+    ap.add_argument("--tiling", default="", metavar="L,R,O,E,A,S",
+                    help="fixed interior tiling (lanes, rows, order, edge rows, alignment, "
+                         "steps) instead of the autotuner, e.g. to profile one tiling only")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device copy of this many GiB 5 times (counter "
                          "calibration for rocprofv3 --pmc) and exit")
@@ -192,7 +192,7 @@ def main():
                                "sync every 50, FP64 populations and u",
                    "nodes": nodes, "storage": args.storage,
                    "tile": [info["tile_lanes"], info["tile_rows"], info["tile_order"],
-                            info["tile_edge_rows"], info["tile_align"]],
+                            info["tile_edge_rows"], info["tile_align"], info["tile_steps"]],
                    "graphs": True},
         "roofline": roofline,
         "cpu_baseline": cpu,

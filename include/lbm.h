@@ -173,6 +173,7 @@ typedef struct {
   int32_t tile_order;         /* interior-tile packing order (see lbm_set_tiling)           */
   int32_t tile_edge_rows;     /* rows of the tiles that carry boundary work                 */
   int32_t tile_align;         /* column-strip alignment in nodes (0: equal-width strips)    */
+  int32_t tile_steps;         /* time steps per pass over the tiles away from boundaries    */
   int32_t n_tiles;
 } lbm_info_t;
 lbm_status lbm_info(const lbm_ctx *ctx, lbm_info_t *info);
@@ -192,19 +193,24 @@ lbm_status lbm_info(const lbm_ctx *ctx, lbm_info_t *info);
  *  align      0: column strips of equal width; > 0: strips of the largest
  *             multiple of align nodes that fits (strip starts aligned to
  *             align nodes, so that every row segment a tile writes covers
- *             whole cache lines).
+ *             whole cache lines);
+ *  steps      1 (or 0): one time step per launch; 2: tiles with no boundary
+ *             or second-row node within two nodes of their area take two
+ *             time steps per pass over HBM (the other tiles take the two
+ *             steps in two launches); a tile then owns at most lanes-4
+ *             columns.
  * Any tiling gives bitwise the same results.  May be changed between steps;
  * invalidates captured step graphs.  LBM_E_INVAL on values out of range
  * (align: 0..4096). */
 typedef struct {
-  int32_t lanes, rows, order, edge_rows, align;
+  int32_t lanes, rows, order, edge_rows, align, steps;
 } lbm_tiling;
 lbm_status lbm_set_tiling(lbm_ctx *ctx, const lbm_tiling *tiling);
 
-/* Autotuner: time one step's interior launch (with the boundary work it
- * carries) for every tiling of a candidate set (lanes x rows x edge rows x
- * alignment, and packing order when there are several plates) on this
- * context's plates, `steps` launches each, and keep the
+/* Autotuner: time one step's interior launches (with the boundary work they
+ * carry) for every tiling of a candidate set (lanes x rows x edge rows x
+ * alignment x steps, and packing order when there are several plates) on
+ * this context's plates, `steps` launches each, and keep the
  * fastest.  Repeating that launch leaves the state unchanged, except at step
  * 0 and at a synchronization step, where the autotuner first takes one real
  * step (steps_done grows by one; the trajectory is the same as without the

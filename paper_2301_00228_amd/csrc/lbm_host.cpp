@@ -521,16 +521,112 @@ bool build_boundary_tables(lbm_ctx *c, std::string &why) {
   return true;
 }
 
-// v within [lo - 1, hi] (an owned range of a tile plus its halo ring), with
-// wrap-around on a periodic axis of length n.
-bool in_ring(int v, int lo, int hi, int n, bool per) {
-  if (!per) return v >= lo - 1 && v <= hi;
-  const int d = ((v - (lo - 1)) % n + n) % n;
-  return d <= hi - lo + 1;
-}
-
 // Row bands of height `rows` on a plate of ny rows; the band holding row j.
 int band_of(int j, int rows, int nb) { return std::min(j / rows, nb - 1); }
+
+// v within [lo - r, hi - 1 + r] (an owned range of a tile plus a ring of r
+// nodes), with wrap-around on a periodic axis of length n.
+bool in_ring_r(int v, int lo, int hi, int n, bool per, int r) {
+  if (!per) return v >= lo - r && v <= hi - 1 + r;
+  const int d = ((v - (lo - r)) % n + n) % n;
+  return d <= hi - lo - 1 + 2 * r;
+}
+
+// Calls fn(tile index, owned) for every tile of plate p whose owned area or
+// ring of r nodes holds node (i, j) (plate strips built).
+template <class F>
+void tiles_near(const lbm_ctx *c, int p, int i, int j, int r, F &&fn) {
+  const PlateHost &h = c->ph[(size_t)p];
+  int strips[8], ns = 0;
+  for (int dx = -r; dx <= r; dx++) {
+    int x = i + dx;
+    if (x < 0 || x >= h.nx) {
+      if (!h.px) continue;
+      x = ((x % h.nx) + h.nx) % h.nx;
+    }
+    const int st = std::min(x / h.sw, h.ns - 1);
+    bool dup = false;
+    for (int q = 0; q < ns; q++) dup = dup || strips[q] == st;
+    if (!dup && ns < 8) strips[ns++] = st;
+  }
+  int cand[64], nc = 0;
+  for (int q = 0; q < ns; q++) {
+    const auto &col = h.strips[(size_t)strips[q]];
+    for (int dy = -r; dy <= r; dy++) {
+      int y = j + dy;
+      if (y < 0 || y >= h.ny) {
+        if (!h.py) continue;
+        y = ((y % h.ny) + h.ny) % h.ny;
+      }
+      auto it = std::upper_bound(col.begin(), col.end(), std::make_pair(y, INT32_MAX));
+      const int ti = std::prev(it)->second;
+      bool dup = false;
+      for (int k = 0; k < nc; k++) dup = dup || cand[k] == ti;
+      if (!dup && nc < 64) cand[nc++] = ti;
+    }
+  }
+  for (int q = 0; q < nc; q++) {
+    const Tile &t = c->tiles[(size_t)cand[q]];
+    if (!in_ring_r(i, t.x0, t.x1, h.nx, h.px, r) || !in_ring_r(j, t.y0, t.y1, h.ny, h.py, r))
+      continue;
+    fn(cand[q], i >= t.x0 && i < t.x1 && j >= t.y0 && j < t.y1);
+  }
+}
+
+// The tile of plate p that owns node (i, j).
+int tile_at(const lbm_ctx *c, int p, int i, int j) {
+  const PlateHost &h = c->ph[(size_t)p];
+  const auto &col = h.strips[(size_t)std::min(i / h.sw, h.ns - 1)];
+  auto it = std::upper_bound(col.begin(), col.end(), std::make_pair(j, INT32_MAX));
+  return std::prev(it)->second;
+}
+
+// Two-step tiles (steps = 2): tiles with no boundary or second-row node in
+// their area or two-node ring and some body node, so that two time steps of
+// the plain scheme cover their area; the others take single steps.  A
+// two-step tile exports the t_{n+1} populations of its owned nodes that lie
+// in the one-node ring of a single-step tile.
+void classify_two_step(lbm_ctx *c) {
+  for (Tile &t : c->tiles) t.flags = 0;
+  if (c->two == 0) return;
+  std::vector<uint8_t> near(c->tiles.size(), 0);
+  auto mark = [&](int p, int i, int j) {
+    tiles_near(c, p, i, j, 2, [&](int ti, bool) { near[(size_t)ti] = 1; });
+  };
+  for (const BndNode &B : c->bnd) mark(B.plate, B.i, B.j);
+  for (const SecNode &S : c->sec) mark(S.plate, S.i, S.j);
+  for (size_t ti = 0; ti < c->tiles.size(); ti++) {
+    Tile &t = c->tiles[ti];
+    const PlateHost &h = c->ph[(size_t)t.plate];
+    // (the two-node ring must not wrap more than once around a periodic plate)
+    if (!near[ti] && h.nx >= 4 && h.ny >= 4 && (h.cls[(size_t)t.y0 * h.nx + t.x0] & CL_IN))
+      t.flags |= TF_TWO;
+  }
+  for (const Tile &e : c->tiles) {
+    if (e.flags & TF_TWO) continue;
+    const PlateHost &h = c->ph[(size_t)e.plate];
+    auto exp = [&](int i, int j, int bit) {
+      if (i < 0 || i >= h.nx) {
+        if (!h.px) return;
+        i = (i + h.nx) % h.nx;
+      }
+      if (j < 0 || j >= h.ny) {
+        if (!h.py) return;
+        j = (j + h.ny) % h.ny;
+      }
+      Tile &o = c->tiles[(size_t)tile_at(c, e.plate, i, j)];
+      if (o.flags & TF_TWO) o.flags |= bit;
+    };
+    for (int j = e.y0; j < e.y1; j++) {
+      exp(e.x0 - 1, j, TF_EXP_E);  // west ring column: the east column of its owner
+      exp(e.x1, j, TF_EXP_W);
+    }
+    for (int i = e.x0; i < e.x1; i++) {
+      exp(i, e.y0 - 1, TF_EXP_N);
+      exp(i, e.y1, TF_EXP_S);
+    }
+  }
+}
 
 // Interior tiles: per plate, column strips of at most lanes-2 columns (of
 // equal width, or of a multiple of align columns but the last) times row
@@ -545,7 +641,7 @@ int band_of(int j, int rows, int nb) { return std::min(j / rows, nb - 1); }
 // order decides which halo rows / columns share an L2.
 void build_tiles(lbm_ctx *c) {
   c->tiles.clear();
-  const int own = c->lanes - 2;
+  const int own = c->lanes - (c->two ? 4 : 2);
   const int rows = c->rows;
   const int er = (c->edge_rows > 0 && c->edge_rows < rows) ? c->edge_rows : rows;
   std::vector<int> plates(c->ph.size());
@@ -586,7 +682,7 @@ void build_tiles(lbm_ctx *c) {
           }
           const int x0 = s * h.sw, x1 = std::min(h.nx, (s + 1) * h.sw);
           const int y0 = b * rows, y1 = std::min(h.ny, (b + 1) * rows);
-          if (in_ring(i, x0, x1, h.nx, h.px) && in_ring(j, y0, y1, h.ny, h.py))
+          if (in_ring_r(i, x0, x1, h.nx, h.px, 1) && in_ring_r(j, y0, y1, h.ny, h.py, 1))
             work[(size_t)p][(size_t)s * nb + b] = 1;
         }
     };
@@ -623,6 +719,7 @@ void build_tiles(lbm_ctx *c) {
         for (int s = 0; s < ns; s++) add(s, b);
     }
   }
+  classify_two_step(c);
 }
 
 // Prologue work lists.  A boundary or second-row node belongs to every tile
@@ -643,39 +740,8 @@ void build_tile_tables(lbm_ctx *c) {
   for (Tile &t : c->tiles) t.chunk = -1;
   std::vector<std::vector<std::pair<int64_t, int>>> tb(c->tiles.size());  // (bnd index, owned)
   std::vector<std::vector<int>> ts(c->tiles.size());                       // sec index
-  // visit the tiles whose owned area or halo ring holds node (i, j): those
-  // of the three strips around column i that hold row j - 1, j or j + 1
-  auto visit = [&](int p, int i, int j, auto &&fn) {
-    const PlateHost &h = c->ph[p];
-    const int s0 = std::min(i / h.sw, h.ns - 1);
-    int cand[9], nc = 0;
-    for (int ds = -1; ds <= 1; ds++) {
-      int s = s0 + ds;
-      if (s < 0 || s >= h.ns) {
-        if (!h.px) continue;
-        s = (s + h.ns) % h.ns;
-      }
-      const auto &col = h.strips[(size_t)s];
-      for (int dj = -1; dj <= 1; dj++) {
-        int y = j + dj;
-        if (y < 0 || y >= h.ny) {
-          if (!h.py) continue;
-          y = (y + h.ny) % h.ny;
-        }
-        auto it = std::upper_bound(col.begin(), col.end(), std::make_pair(y, INT32_MAX));
-        const int ti = std::prev(it)->second;
-        bool dup = false;
-        for (int q = 0; q < nc; q++) dup = dup || cand[q] == ti;
-        if (!dup) cand[nc++] = ti;
-      }
-    }
-    for (int q = 0; q < nc; q++) {
-      const Tile &t = c->tiles[cand[q]];
-      if (!in_ring(i, t.x0, t.x1, h.nx, h.px) || !in_ring(j, t.y0, t.y1, h.ny, h.py)) continue;
-      const bool owned = i >= t.x0 && i < t.x1 && j >= t.y0 && j < t.y1;
-      fn(cand[q], owned);
-    }
-  };
+  // the tiles whose owned area or halo ring holds node (i, j)
+  auto visit = [&](int p, int i, int j, auto &&fn) { tiles_near(c, p, i, j, 1, fn); };
   for (size_t b = 0; b < c->bnd.size(); b++) {
     const BndNode &B = c->bnd[b];
     visit(B.plate, B.i, B.j, [&](int ti, bool owned) { tb[ti].push_back({(int64_t)b, owned ? 1 : 0}); });
@@ -1244,11 +1310,11 @@ lbm_status lbm_create(const lbm_plate *plates, int32_t n_plates, lbm_storage sto
     // second-row side buffers and the node -> second-row index map
     const int64_t ns = (int64_t)c->sec.size();
     const size_t cb = c->storage == LBM_STORE_F64 ? sizeof(double) : sizeof(float);
+    c->ds.nsec = ns;
     for (int b = 0; b < 2; b++) {
       c->ds.side[b] = dev_alloc(c, (size_t)std::max<int64_t>(1, ns) * 10 * cb);
       if (!c->ds.side[b]) return bail(LBM_E_NOMEM, "side buffer allocation failed");
     }
-    c->ds.nsec = ns;
     std::vector<int32_t> sidx((size_t)N, -1);
     for (int64_t q = 0; q < ns; q++) sidx[(size_t)c->sec[(size_t)q].node] = (int32_t)q;
     int32_t *d = (int32_t *)dev_alloc(c, (size_t)N * sizeof(int32_t));
@@ -1362,6 +1428,7 @@ lbm_status lbm_create(const lbm_plate *plates, int32_t n_plates, lbm_storage sto
       c->order = it->second.order;
       c->edge_rows = it->second.edge_rows;
       c->align = it->second.align;
+      c->two = it->second.steps == 2 ? 1 : 0;
     } else {
       // what the autotuner picks on 1024^2 (unaligned) and 4096^2 plates
       c->lanes = 128;
@@ -1526,6 +1593,7 @@ lbm_status lbm_info(const lbm_ctx *c, lbm_info_t *info) {
   info->tile_order = c->order;
   info->tile_edge_rows = (c->edge_rows > 0 && c->edge_rows < c->rows) ? c->edge_rows : c->rows;
   info->tile_align = c->align;
+  info->tile_steps = c->two ? 2 : 1;
   info->n_tiles = (int32_t)c->tiles.size();
   return LBM_OK;
 }
@@ -1533,18 +1601,19 @@ lbm_status lbm_info(const lbm_ctx *c, lbm_info_t *info) {
 lbm_status lbm_set_tiling(lbm_ctx *c, const lbm_tiling *t) {
   if (!c || !t) return LBM_E_INVAL;
   const int32_t lanes = t->lanes, rows = t->rows, order = t->order, edge_rows = t->edge_rows,
-                align = t->align;
+                align = t->align, steps = t->steps;
   if ((lanes != 64 && lanes != 128 && lanes != 256) || rows < 1 || rows > 65536 || order < 0 ||
-      order > 2 || edge_rows < 0 || align < 0 || align > 4096)
+      order > 2 || edge_rows < 0 || align < 0 || align > 4096 || steps < 0 || steps > 2)
     return fail(c, LBM_E_INVAL,
                 "lanes must be 64, 128 or 256, rows >= 1, order 0..2, edge_rows >= 0, "
-                "align 0..4096");
+                "align 0..4096, steps 0..2");
   HIP_TRY(c, hipStreamSynchronize(c->stream), "synchronize");
   c->lanes = lanes;
   c->rows = rows;
   c->order = order;
   c->edge_rows = edge_rows;
   c->align = align;
+  c->two = steps == 2 ? 1 : 0;
   build_tiles(c);
   build_tile_tables(c);
   lbm_status st = upload_tiles(c);
@@ -1603,21 +1672,32 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
   if (st) return st;
   st = start(c);
   if (st) return st;
-  // The timed launch is the interior kernel of step n with its prologue
-  // (the boundary work of step n - 1).  From a complete state at t_n it
-  // rewrites the boundary values of t_n and t_{n+1} with the values they
-  // already hold and the t_{n+1} buffers from the t_n ones, so repeating it
-  // leaves the state unchanged -- unless there is no t_{n-1} (n = 0) or the
-  // state of t_n comes from a synchronization: then one real step is taken
-  // first.
+  // The timed launches are those of step n with their prologues (the
+  // boundary work of step n - 1).  From a complete state at t_n the
+  // single-step launch rewrites the boundary values of t_n and t_{n+1} with
+  // the values they already hold and the t_{n+1} buffers from the t_n ones,
+  // so repeating it leaves the state unchanged; so do the two launches of a
+  // two-step pair, repeated, except that the second one overwrites the side
+  // buffer the first one's prologue reads, which is saved and restored
+  // around them.  That needs the boundary populations of t_{n-1} in a
+  // buffer neither launch writes and a state of t_n that does not come from
+  // a synchronization (nor n = 0): otherwise one real step is taken first.
   const bool syncs_now = c->sync_every > 0 && c->step % c->sync_every == 0;
-  if (c->step == 0 || (syncs_now && c->sync_every > 1)) {
+  if (c->step == 0 || (syncs_now && c->sync_every > 1) || c->prev == 2) {
     HIP_TRY(c, enqueue_segment(c, c->step, 1, c->cur, c->prev, c->stream, nullptr),
             "step launch");
     c->step += 1;
   }
   const bool with_prologue = !(c->sync_every > 0 && c->step % c->sync_every == 0);
   HIP_TRY(c, hipStreamSynchronize(c->stream), "synchronize");
+  const int64_t n = c->step;
+  const size_t side_bytes = (size_t)std::max<int64_t>(1, c->ds.nsec) * 10 *
+                            (c->storage == LBM_STORE_F64 ? sizeof(double) : sizeof(float));
+  void *side_save = dev_alloc(c, side_bytes);
+  if (!side_save) return fail(c, LBM_E_NOMEM, "autotuner scratch allocation failed");
+  void *side_n = c->ds.side[n & 1];
+  HIP_TRY(c, hipMemcpyAsync(side_save, side_n, side_bytes, hipMemcpyDeviceToDevice, c->stream),
+          "side save");
   const int lane_set[3] = {64, 128, 256};
   const int row_set[4] = {8, 16, 32, 64};
   const int edge_set[4] = {0, 8, 4, 2};
@@ -1626,43 +1706,73 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
   hipEvent_t e0, e1;
   HIP_TRY(c, hipEventCreate(&e0), "event");
   HIP_TRY(c, hipEventCreate(&e1), "event");
-  const int64_t n = c->step;
   double best = 1e300;
-  lbm_tiling bt{c->lanes, c->rows, c->order, c->edge_rows, c->align};
-  for (int O = 0; O < n_orders; O++)
-    for (int L : lane_set)
-      for (int R : row_set)
-        for (int E : edge_set)
-          for (int A : align_set) {
-            if (E != 0 && E >= R) continue;  // same tiling as E = 0
-            c->lanes = L;
-            c->rows = R;
-            c->order = O;
-            c->edge_rows = E;
-            c->align = A;
-            build_tiles(c);
-            build_tile_tables(c);
-            if (upload_tiles(c) != LBM_OK || upload_tile_tables(c) != LBM_OK) continue;
-            const Prologue pro = make_prologue(c, with_prologue);
-            const StepBufs sb{c->cur, c->cur ^ 1, c->prev, (int)(n & 1), -1};
-            auto launch = [&] {
-              return launch_interior(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), L, sb,
-                                     pro, c->stream);
-            };
-            hipError_t e = launch();
-            (void)hipEventRecord(e0, c->stream);
-            for (int k = 0; k < steps && e == hipSuccess; k++) e = launch();
-            (void)hipEventRecord(e1, c->stream);
-            (void)hipEventSynchronize(e1);
-            if (e != hipSuccess) continue;
-            float t = 0;
-            (void)hipEventElapsedTime(&t, e0, e1);
-            const double per = t / steps;
-            if (per < best) {
-              best = per;
-              bt = lbm_tiling{L, R, O, E, A};
+  lbm_tiling bt{c->lanes, c->rows, c->order, c->edge_rows, c->align, c->two ? 2 : 1};
+  auto time_launches = [&](auto &&launch) -> double {
+    hipError_t e = launch();
+    (void)hipEventRecord(e0, c->stream);
+    for (int k = 0; k < steps && e == hipSuccess; k++) e = launch();
+    (void)hipEventRecord(e1, c->stream);
+    (void)hipEventSynchronize(e1);
+    if (e != hipSuccess) return 1e300;
+    float t = 0;
+    (void)hipEventElapsedTime(&t, e0, e1);
+    return t / steps;
+  };
+  const int cur = c->cur, prev = c->prev;
+  for (int S = 1; S <= 2; S++)
+    for (int O = 0; O < n_orders; O++)
+      for (int L : lane_set)
+        for (int R : row_set)
+          for (int E : edge_set)
+            for (int A : align_set) {
+              if (E != 0 && E >= R) continue;  // same tiling as E = 0
+              c->lanes = L;
+              c->rows = R;
+              c->order = O;
+              c->edge_rows = E;
+              c->align = A;
+              c->two = S == 2 ? 1 : 0;
+              build_tiles(c);
+              build_tile_tables(c);
+              if (upload_tiles(c) != LBM_OK || upload_tile_tables(c) != LBM_OK) continue;
+              const Prologue pro = make_prologue(c, with_prologue);
+              double per;
+              if (S == 1) {
+                const StepBufs sb{cur, cur ^ 1, prev, (int)(n & 1), -1};
+                per = time_launches([&] {
+                  return launch_interior(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), L,
+                                         sb, pro, c->stream);
+                });
+              } else {
+                const StepBufs b1{cur, 2, prev, (int)(n & 1), cur ^ 1};
+                const StepBufs b2{2, cur ^ 1, cur, (int)((n + 1) & 1), -1};
+                const Prologue pro2 = make_prologue(c, true);
+                const double t1 = time_launches([&] {
+                  return launch_interior(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), L,
+                                         b1, pro, c->stream);
+                });
+                const double t2 = time_launches([&] {
+                  return launch_interior(c->storage, c->ds, c->d_etiles, (int)c->etiles.size(), L,
+                                         b2, pro2, c->stream);
+                });
+                (void)hipMemcpyAsync(side_n, side_save, side_bytes, hipMemcpyDeviceToDevice,
+                                     c->stream);
+                per = 0.5 * (t1 + t2);
+              }
+              if (per < best) {
+                best = per;
+                bt = lbm_tiling{L, R, O, E, A, S};
+              }
             }
-          }
+  // The second launch of a pair wrote the boundary nodes' u(t_{n+2}) where
+  // the next step expects u(t_{n+1}): recompute that from u(t_n).
+  HIP_TRY(c, launch_boundary(c->storage, c->ds, c->d_chunks, (int)c->chunks.size(), c->d_unodes,
+                             c->d_gnodes, c->d_btasks, c->d_stasks, cur, prev, cur ^ 1, 2,
+                             (int)(n & 1), 0, c->stream),
+          "boundary accelerations");
+  (void)hipStreamSynchronize(c->stream);
+  dev_free(c, side_save);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   c->lanes = bt.lanes;
@@ -1670,6 +1780,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
   c->order = bt.order;
   c->edge_rows = bt.edge_rows;
   c->align = bt.align;
+  c->two = bt.steps == 2 ? 1 : 0;
   build_tiles(c);
   build_tile_tables(c);
   st = upload_tiles(c);

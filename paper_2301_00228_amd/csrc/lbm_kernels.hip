@@ -130,6 +130,8 @@ struct PopCodec {
     load(s, b, fl, k, P, f);
     return (double)(f[0] + ((f[1] + f[3]) + (f[2] + f[4])));
   }
+  // f as a store and a load would return it (exact for plain storage)
+  __device__ static void roundtrip(const PlateDev &, int, C[5]) {}
 };
 
 // Deviation from the local rest equilibrium in a moment basis:
@@ -257,6 +259,20 @@ struct DevCodec {
   }
   __device__ static double field(const DevState &s, int b, int fl, int64_t k, const PlateDev &) {
     return (double)ldg<float>(s.pop[b][fl][0], k);
+  }
+  // f as store() followed by load() returns it: the same moments and
+  // rounding, without the memory
+  __device__ static void roundtrip(const PlateDev &P, int fl, C f[5]) {
+    const float s13 = f[1] + f[3], s24 = f[2] + f[4];
+    const float q = s13 + s24;
+    float m[5];
+    m[0] = f[0] + q;
+    m[1] = f[1] - f[3];
+    m[2] = f[2] - f[4];
+    m[3] = s13 - s24;
+    m[4] = q - 4.0f * aw(P, fl) * m[0];
+    if (H != 0) unpack(pack(m[3], m[4], P, fl), P, fl, m[3], m[4]);
+    moments_to_pops(P, fl, m, f);
   }
 };
 
@@ -684,7 +700,213 @@ enum { X_RHO0 = 0, X_RHO1, X_F1_0, X_F1_1, X_F3_0, X_F3_1, X_N };
 
 __device__ __forceinline__ int tile_index(int b, int q) { return (b & 7) * q + (b >> 3); }
 
-template <int ST, int TWL>
+// Two steps of a tile whose area and two-node halo ring hold only interior
+// nodes (no boundary or second-row node): step n on the area plus its
+// one-node ring (from t_n on the two-node ring, buffer sb.in), step n + 1 on
+// the area (buffer sb.out2); the t_{n+1} populations of the export bands
+// (owned columns / rows next to single-step tiles) go to buffer sb.out.  Lane
+// l holds column x0 - 2 + l.  Rows are indexed i = 0..h-1 in the march
+// direction (i = -2, -1, h, h+1: halo rows).  The front row a of t_n is
+// collided while row a - 1 takes step n and row a - 2 step n + 1; each
+// stage hands its post-collision values to the x-neighbours through its own
+// triple-buffered LDS slots (exA: t_n, exB: t_{n+1}).
+template <class CD, int TWL>
+__device__ void march2(const DevState &s, const Tile &t, const StepBufs &sb,
+                       typename CD::C (*exA)[X_N][TWL], typename CD::C (*exB)[X_N][TWL]) {
+  using C = typename CD::C;
+  using U = typename CD::U;
+  using Slot = typename CD::Slot;
+  const PlateDev P = s.plates[t.plate];
+  const int lane = threadIdx.x;
+  const int w = t.x1 - t.x0;
+  const bool live = lane <= w + 3;
+  const int x = wrapc(t.x0 - 2 + lane, P.nx);
+  const bool stepA = lane >= 1 && lane <= w + 2;  // step n on columns x0-1 .. x1
+  const bool stepB = lane >= 2 && lane <= w + 1;  // step n+1 on the owned columns
+  const int d = t.dir ? -1 : 1;
+  const int h = t.y1 - t.y0;
+  auto row_y = [&](int i) { return wrapc(d > 0 ? t.y0 + i : t.y1 - 1 - i, P.ny); };
+  auto load_raw = [&](int i, Slot raw[2][5]) {
+#pragma unroll
+    for (int fl = 0; fl < 2; fl++)
+#pragma unroll
+      for (int qq = 0; qq < 5; qq++) raw[fl][qq] = Slot(0);
+    if (live) {
+      const int64_t k = node_of(P, x, row_y(i));
+      CD::load_raw(s, sb.in, 0, k, raw[0]);
+      CD::load_raw(s, sb.in, 1, k, raw[1]);
+    }
+  };
+  auto load_uv = [&](int i, U uv[4]) {
+    uv[0] = uv[1] = uv[2] = uv[3] = U(0);
+    if (stepA) {
+      const int64_t k = node_of(P, x, row_y(i));
+      uv[0] = ldg<U>(s.u[sb.in][0], k);
+      uv[1] = ldg<U>(s.u[sb.in][1], k);
+      uv[2] = ldg<U>(s.v[sb.in][0], k);
+      uv[3] = ldg<U>(s.v[sb.in][1], k);
+    }
+  };
+  auto collide = [&](const C f[2][5], C rho[2], C fs[2][5]) {
+#pragma unroll
+    for (int fl = 0; fl < 2; fl++) collide_pops<CD>(P, fl, f[fl], rho[fl], fs[fl]);
+  };
+  auto publish = [&](C(*ex)[X_N][TWL], int slot, const C rho[2], const C fs[2][5]) {
+    ex[slot][X_RHO0][lane] = rho[0];
+    ex[slot][X_RHO1][lane] = rho[1];
+    ex[slot][X_F1_0][lane] = fs[0][1];
+    ex[slot][X_F1_1][lane] = fs[1][1];
+    ex[slot][X_F3_0][lane] = fs[0][3];
+    ex[slot][X_F3_1][lane] = fs[1][3];
+  };
+  // population a row streams into the row after it (behind) / before it
+  auto behind_pop = [&](const C fs[5]) { return d > 0 ? fs[2] : fs[4]; };
+  auto ahead_pop = [&](const C fs[5]) { return d > 0 ? fs[4] : fs[2]; };
+  auto slot_of = [](int i) { return (i + 3) % 3; };
+  // Pull into row i of one stage: f0 of the row, f1 / f3 from the x
+  // neighbours (slot of row i), the behind row's and the ahead row's pops;
+  // then the u, du/dt update from the neighbours' rho.
+  auto finalize = [&](C(*ex)[X_N][TWL], int i, const C f0[2], const C fbe[2], const C fah[2],
+                      const C rbe[2], const C rah[2], const U uv[4], C f[2][5], U nu[4]) {
+    const int sl = slot_of(i);
+    // (the end lanes read a clamped neighbour; their results are not used)
+    const int lw = lane > 0 ? lane - 1 : 0, le = lane < TWL - 1 ? lane + 1 : TWL - 1;
+#pragma unroll
+    for (int fl = 0; fl < 2; fl++) {
+      f[fl][0] = f0[fl];
+      f[fl][1] = ex[sl][fl == 0 ? X_F1_0 : X_F1_1][lw];
+      f[fl][3] = ex[sl][fl == 0 ? X_F3_0 : X_F3_1][le];
+      f[fl][2] = d > 0 ? fbe[fl] : fah[fl];
+      f[fl][4] = d > 0 ? fah[fl] : fbe[fl];
+    }
+    const C wr0 = ex[sl][X_RHO0][lw], er0 = ex[sl][X_RHO0][le];
+    const C wr1 = ex[sl][X_RHO1][lw], er1 = ex[sl][X_RHO1][le];
+    const C n0 = d > 0 ? rah[0] : rbe[0], s0 = d > 0 ? rbe[0] : rah[0];
+    const C n1 = d > 0 ? rah[1] : rbe[1], s1 = d > 0 ? rbe[1] : rah[1];
+    interior_update<U>(P, (U)er0, (U)wr0, (U)n0, (U)s0, (U)er1, (U)wr1, (U)n1, (U)s1, uv[0], uv[1],
+                       uv[2], uv[3], nu[0], nu[1], nu[2], nu[3]);
+  };
+
+  // t_n stage registers: row a-2 (rho, behind pop), row a-1 (rho, f0, behind pop)
+  C a2_rho[2], a2_fb[2], a1_rho[2], a1_f0[2], a1_fb[2];
+  // t_{n+1} stage registers: row a-3 (rho, behind pop), row a-2 (rho, f0, behind pop)
+  C b3_rho[2], b3_fb[2], b2_rho[2], b2_f0[2], b2_fb[2];
+  U uvA[4];   // u, du/dt of t_n, row a-1
+  U uvB[4];   // u, du/dt of t_{n+1}, row a-2
+  Slot rawn[2][5];  // t_n populations of row a
+  {
+    Slot raw[2][5];
+    C f[2][5], rho[2], fs[2][5];
+    load_raw(-2, raw);
+    load_raw(-1, rawn);
+#pragma unroll
+    for (int fl = 0; fl < 2; fl++) CD::raw_to_pops(P, fl, raw[fl], f[fl]);
+    collide(f, rho, fs);
+    a2_rho[0] = rho[0];
+    a2_rho[1] = rho[1];
+    a2_fb[0] = behind_pop(fs[0]);
+    a2_fb[1] = behind_pop(fs[1]);
+#pragma unroll
+    for (int fl = 0; fl < 2; fl++) CD::raw_to_pops(P, fl, rawn[fl], f[fl]);
+    load_raw(0, rawn);
+    load_uv(-1, uvA);
+    collide(f, rho, fs);
+    publish(exA, slot_of(-1), rho, fs);
+    a1_rho[0] = rho[0];
+    a1_rho[1] = rho[1];
+    a1_f0[0] = fs[0][0];
+    a1_f0[1] = fs[1][0];
+    a1_fb[0] = behind_pop(fs[0]);
+    a1_fb[1] = behind_pop(fs[1]);
+#pragma unroll
+    for (int q = 0; q < 4; q++) uvB[q] = U(0);
+#pragma unroll
+    for (int fl = 0; fl < 2; fl++)
+      b3_rho[fl] = b3_fb[fl] = b2_rho[fl] = b2_f0[fl] = b2_fb[fl] = C(0);
+  }
+  for (int a = 0; a <= h + 1; a++) {
+    // collide t_n row a, prefetch row a+1 and u of row a
+    C f[2][5], rho[2], fs[2][5];
+#pragma unroll
+    for (int fl = 0; fl < 2; fl++) CD::raw_to_pops(P, fl, rawn[fl], f[fl]);
+    if (a + 1 <= h + 1) load_raw(a + 1, rawn);
+    U uvn[4];
+    load_uv(a, uvn);
+    collide(f, rho, fs);
+    publish(exA, slot_of(a), rho, fs);
+    __syncthreads();
+    // step n at row a-1 (columns x0-1 .. x1)
+    const C fa[2] = {ahead_pop(fs[0]), ahead_pop(fs[1])};
+    C g[2][5];
+    U nu[4];
+    finalize(exA, a - 1, a1_f0, a2_fb, fa, a2_rho, rho, uvA, g, nu);
+    const int ya = row_y(a - 1);
+    if (stepA && a - 1 >= 0 && a - 1 < h) {
+      const bool exp = ((t.flags & TF_EXP_W) && lane == 2) ||
+                       ((t.flags & TF_EXP_E) && lane == w + 1) ||
+                       ((t.flags & TF_EXP_S) && ya == t.y0) ||
+                       ((t.flags & TF_EXP_N) && ya == t.y1 - 1);
+      if (exp && stepB) {
+        const int64_t k = node_of(P, x, ya);
+        CD::store(s, sb.out, 0, k, P, g[0]);
+        CD::store(s, sb.out, 1, k, P, g[1]);
+      }
+    }
+    // collide t_{n+1} row a-1 (as a store and a load between two launches
+    // would leave it) and hand it to the x-neighbours
+    C rho1[2], fs1[2][5];
+    CD::roundtrip(P, 0, g[0]);
+    CD::roundtrip(P, 1, g[1]);
+    collide(g, rho1, fs1);
+    if (!stepA) {
+#pragma unroll
+      for (int fl = 0; fl < 2; fl++) {
+        rho1[fl] = C(0);
+#pragma unroll
+        for (int qq = 0; qq < 5; qq++) fs1[fl][qq] = C(0);
+      }
+    }
+    publish(exB, slot_of(a - 1), rho1, fs1);
+    // step n+1 at row a-2 (owned columns); its x-neighbours' values were
+    // published in the previous iteration
+    if (a - 2 >= 0 && a - 2 < h) {
+      const C fa1[2] = {ahead_pop(fs1[0]), ahead_pop(fs1[1])};
+      C g2[2][5];
+      U nu2[4];
+      finalize(exB, a - 2, b2_f0, b3_fb, fa1, b3_rho, rho1, uvB, g2, nu2);
+      if (stepB) {
+        const int64_t k = node_of(P, x, row_y(a - 2));
+        stg<U>(s.u[sb.out2][0], k, nu2[0]);
+        stg<U>(s.u[sb.out2][1], k, nu2[1]);
+        stg<U>(s.v[sb.out2][0], k, nu2[2]);
+        stg<U>(s.v[sb.out2][1], k, nu2[3]);
+        CD::store(s, sb.out2, 0, k, P, g2[0]);
+        CD::store(s, sb.out2, 1, k, P, g2[1]);
+      }
+    }
+    // shift the stages by one row
+#pragma unroll
+    for (int fl = 0; fl < 2; fl++) {
+      a2_rho[fl] = a1_rho[fl];
+      a2_fb[fl] = a1_fb[fl];
+      a1_rho[fl] = rho[fl];
+      a1_f0[fl] = fs[fl][0];
+      a1_fb[fl] = behind_pop(fs[fl]);
+      b3_rho[fl] = b2_rho[fl];
+      b3_fb[fl] = b2_fb[fl];
+      b2_rho[fl] = rho1[fl];
+      b2_f0[fl] = fs1[fl][0];
+      b2_fb[fl] = behind_pop(fs1[fl]);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      uvB[q] = nu[q];
+      uvA[q] = uvn[q];
+    }
+  }
+}
+
+template <int ST, int TWL, bool TWO>
 __global__ void __launch_bounds__(TWL)
     k_interior(DevState s, const Tile *__restrict__ tiles, int ntiles, int q, StepBufs sb,
                Prologue pro) {
@@ -692,7 +914,8 @@ __global__ void __launch_bounds__(TWL)
   using C = typename CD::C;
   using U = typename CD::U;
   using Slot = typename CD::Slot;
-  __shared__ C ex[3][X_N][TWL];
+  __shared__ C exs[TWO ? 6 : 3][X_N][TWL];
+  C(*ex)[X_N][TWL] = exs;
 
   // populations and u, du/dt of t_n in buffers sb.in, of t_{n+1} in sb.out
   const int pc = sb.in, pn = sb.out, uc = sb.in, un = sb.out;
@@ -700,6 +923,10 @@ __global__ void __launch_bounds__(TWL)
   const int tix = tile_index(blockIdx.x, q);
   if (tix >= ntiles) return;
   const Tile t = tiles[tix];
+  if (TWO && sb.out2 >= 0 && (t.flags & TF_TWO)) {
+    march2<CD, TWL>(s, t, sb, exs, exs + 3);
+    return;
+  }
   if (pro.enabled && t.chunk >= 0) prologue<CD>(s, pro, t.chunk, sb, (int)threadIdx.x, TWL);
   const PlateDev P = s.plates[t.plate];
   const int lane = threadIdx.x;
@@ -1007,22 +1234,24 @@ __global__ void k_fields(DevState s, int plate, int b, double *e, double *w, dou
 
 // --------------------------------------------------------------- launchers
 
-template <int ST>
+template <int ST, bool TWO>
 static hipError_t launch_interior_t(const DevState &s, const Tile *tiles, int ntiles, int lanes,
                                     const StepBufs &b, const Prologue &pro, hipStream_t st) {
-  const int q = (ntiles + 7) / 8;
+  // at least one block: block 0 advances the step counter
+  const int q = ntiles > 0 ? (ntiles + 7) / 8 : 1;
   const dim3 grid(8 * q);
   switch (lanes) {
     case 64:
-      hipLaunchKernelGGL((k_interior<ST, 64>), grid, dim3(64), 0, st, s, tiles, ntiles, q, b, pro);
+      hipLaunchKernelGGL((k_interior<ST, 64, TWO>), grid, dim3(64), 0, st, s, tiles, ntiles, q, b,
+                         pro);
       break;
     case 128:
-      hipLaunchKernelGGL((k_interior<ST, 128>), grid, dim3(128), 0, st, s, tiles, ntiles, q, b,
-                         pro);
+      hipLaunchKernelGGL((k_interior<ST, 128, TWO>), grid, dim3(128), 0, st, s, tiles, ntiles, q,
+                         b, pro);
       break;
     case 256:
-      hipLaunchKernelGGL((k_interior<ST, 256>), grid, dim3(256), 0, st, s, tiles, ntiles, q, b,
-                         pro);
+      hipLaunchKernelGGL((k_interior<ST, 256, TWO>), grid, dim3(256), 0, st, s, tiles, ntiles, q,
+                         b, pro);
       break;
     default:
       return hipErrorInvalidValue;
@@ -1063,8 +1292,11 @@ static hipError_t launch_sync_t(const DevState &s, const Tile *tiles, int ntiles
 
 hipError_t launch_interior(int st, const DevState &s, const Tile *tiles, int ntiles, int lanes,
                            const StepBufs &b, const Prologue &pro, hipStream_t stream) {
-  if (ntiles <= 0) return hipSuccess;
-  LBM_DISPATCH(st, return launch_interior_t<ST>(s, tiles, ntiles, lanes, b, pro, stream));
+  if (b.out2 >= 0) {
+    LBM_DISPATCH(st, return (launch_interior_t<ST, true>(s, tiles, ntiles, lanes, b, pro, stream)));
+  } else {
+    LBM_DISPATCH(st, return (launch_interior_t<ST, false>(s, tiles, ntiles, lanes, b, pro, stream)));
+  }
   return hipSuccess;
 }
 

@@ -67,7 +67,7 @@ def timed(cases, storage, steps, warmup, tune=True):
            "interior_frac": achieved / HBM_PEAK_GBS, "boundary_us": b_ms / max(b_n, 1) * 1e3,
            "bytes_per_lup": info["bytes_per_update"], "boundary_nodes": info["boundary_nodes"],
            "tile": [info["tile_lanes"], info["tile_rows"], info["tile_order"],
-                    info["tile_edge_rows"], info["tile_align"]],
+                    info["tile_edge_rows"], info["tile_align"], info["tile_steps"]],
            "device_GB": info["device_bytes"] / 1e9, "setup_s": setup}
     return ctx, res
 

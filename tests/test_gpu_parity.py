@@ -121,7 +121,9 @@ def test_tilings_graphs_and_eager_are_bitwise_identical():
     for tiling, graphs in [((64, 1, 0), True), ((256, 7, 1), False), ((128, 64, 2), False),
                            ((64, 13, 1), True), ((128, 32, 0, 4), True), ((256, 9, 1, 2), False),
                            ((64, 16, 2, 1), True), ((64, 8, 0, 2, 16), True),
-                           ((128, 5, 1, 3, 32), False), ((256, 16, 0, 0, 48), True)]:
+                           ((128, 5, 1, 3, 32), False), ((256, 16, 0, 0, 48), True),
+                           ((64, 8, 0, 2, 0, 2), True), ((128, 16, 1, 4, 16, 2), False),
+                           ((256, 5, 0, 0, 0, 2), True), ((64, 3, 0, 1, 0, 2), False)]:
         other = gpu_run(case, tiling=tiling, graphs=graphs)
         for k in FIELDS:
             assert np.array_equal(base[k], other[k]), (tiling, graphs, k)
@@ -147,6 +149,53 @@ def test_autotune_keeps_the_trajectory(first):
     for a, b in zip(base, tuned):
         for k in FIELDS:
             assert np.array_equal(a[k], b[k]), k
+
+
+TWO_STEP = [(64, 8, 0, 2, 0, 2), (128, 16, 0, 4, 16, 2), (256, 5, 1, 0, 0, 2)]
+
+
+@pytest.mark.parametrize("tiling", TWO_STEP)
+def test_two_step_tiles_match_the_oracle(tiling):
+    """Tiles away from boundaries take two steps per pass; the others take
+    them in two launches; odd step counts end with a single step."""
+    cases = [I.periodic_square(), I.clamped_plate(n=150, ny=97, sigma=6.0, steps=151, sync_every=50),
+             I.plate_with_hole(n=160, radius=24, sigma=4.0, steps=121, sync_every=40)]
+    for case in cases:
+        ref, _ = run_case(case)
+        got = gpu_run(case, tiling=tiling)
+        assert_parity(got, ref, what=f"{case.name} {tiling}")
+
+
+def test_two_step_batch_and_split_stepping_bitwise():
+    cases = I.plate_batch(count=6, side_lo=20, side_hi=200, steps=0)
+    base = [None] * len(cases)
+    with lbm.context_for(cases) as ctx:
+        ctx.step(157)
+        base = [ctx.fields(p) for p in range(len(cases))]
+    with lbm.context_for(cases) as ctx:
+        ctx.set_tiling(64, 8, 0, 2, 0, 2)
+        for n in (1, 2, 64, 50, 7, 33):
+            ctx.step(n)
+        got = [ctx.fields(p) for p in range(len(cases))]
+    for a, b in zip(base, got):
+        for k in FIELDS:
+            assert np.array_equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("storage", ["f32", "f32dev", "f16dev", "bf16dev"])
+def test_reduced_storages_bitwise_across_tilings(storage):
+    """The two-step pass applies the storage rounding to its intermediate
+    level, so every tiling gives the same bits in every storage."""
+    case = I.plate_with_hole(n=140, radius=20, sigma=4.0, steps=0, sync_every=25)
+    outs = []
+    for tiling in [(64, 8, 0, 2, 0, 1), (64, 8, 0, 2, 0, 2), (256, 32, 1, 4, 16, 2)]:
+        with lbm.context_for(case, storage) as ctx:
+            ctx.set_tiling(*tiling)
+            ctx.step(83)
+            outs.append(ctx.fields(0))
+    for o in outs[1:]:
+        for k in FIELDS:
+            assert np.array_equal(outs[0][k], o[k]), (storage, k)
 
 
 def test_repeat_runs_are_deterministic():
