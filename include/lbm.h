@@ -164,6 +164,7 @@ typedef struct {
   int64_t nodes_allocated;    /* nodes stored, including row padding                        */
   int64_t boundary_nodes;     /* nodes with a missing neighbour                             */
   int64_t second_row_nodes;   /* interior nodes with a boundary neighbour                   */
+  int64_t nodes_two_step;     /* body nodes in two-step tiles (tiling steps = 2)            */
   int64_t steps_done;
   int64_t device_bytes;       /* device memory held                                         */
   double bytes_per_update;    /* algorithmic HBM bytes per body node and step (read+write) */
@@ -208,25 +209,28 @@ typedef struct {
 lbm_status lbm_set_tiling(lbm_ctx *ctx, const lbm_tiling *tiling);
 
 /* Autotuner: time one step's interior launches (with the boundary work they
- * carry) for every tiling of a candidate set (lanes x rows x edge rows x
- * alignment x steps, and packing order when there are several plates) on
- * this context's plates, `steps` launches each, and keep the
- * fastest.  Repeating that launch leaves the state unchanged, except at step
- * 0 and at a synchronization step, where the autotuner first takes one real
+ * carry) on this context's plates for the tilings of a two-stage search
+ * (steps x lanes x rows, then edge rows, alignment, rows and -- with several
+ * plates -- packing order one at a time around the best, about 30 tilings),
+ * `steps` launches each, and keep the fastest.  Repeating those launches
+ * leaves the state unchanged, except at step 0, at a synchronization step
+ * and right after a two-step pair, where the autotuner first takes one real
  * step (steps_done grows by one; the trajectory is the same as without the
  * autotuner).  Results are cached per (storage, single/multiple plates,
  * size bucket) for the life of the process and picked up by later
- * contexts.  best_ms (nullable) receives the fastest time per launch. */
+ * contexts.  best_ms (nullable) receives the fastest interior time per step
+ * (for two-step tilings half the time of a pair's two launches). */
 lbm_status lbm_autotune(lbm_ctx *ctx, int32_t steps, double *best_ms);
 
 /* Run n_steps steps eagerly (no graph), launches back to back with a HIP
  * event recorded on the context's stream before the first and after every
  * kernel launch, and return the summed time between consecutive events per
  * kernel kind in ms (a launch's device time plus the gap after the previous
- * one): ms[0] interior stream+collide,
- * ms[1] boundary/second-row, ms[2] synchronization, ms[3] all other; and
- * the number of launches of each kind in launches[0..3] (nullable).
- * Synchronizes the stream. */
+ * one): ms[0] single-step interior launches (stream+collide of one step),
+ * ms[1] boundary/second-row, ms[2] synchronization, ms[3] two-step interior
+ * launches (the first launch of a pair: two steps of the two-step tiles, one
+ * of the others); and the number of launches of each kind in
+ * launches[0..3] (nullable).  Synchronizes the stream. */
 lbm_status lbm_profile(lbm_ctx *ctx, int64_t n_steps, double *ms, int64_t *launches);
 
 /* Use (nonzero) or bypass (0) captured HIP graphs in lbm_step.  Default on. */

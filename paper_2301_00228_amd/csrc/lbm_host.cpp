@@ -92,6 +92,7 @@ struct lbm_ctx {
   std::vector<PlateHost> ph;
   std::vector<PlateDev> pd;
   int64_t n_alloc = 0;
+  int64_t n_two = 0;  // body nodes in two-step tiles
   int64_t n_body = 0;
   int sync_every = 0;
 
@@ -587,6 +588,7 @@ int tile_at(const lbm_ctx *c, int p, int i, int j) {
 // two-step tile exports the t_{n+1} populations of its owned nodes that lie
 // in the one-node ring of a single-step tile.
 void classify_two_step(lbm_ctx *c) {
+  c->n_two = 0;
   for (Tile &t : c->tiles) t.flags = 0;
   if (c->two == 0) return;
   std::vector<uint8_t> near(c->tiles.size(), 0);
@@ -602,6 +604,8 @@ void classify_two_step(lbm_ctx *c) {
     if (!near[ti] && h.nx >= 4 && h.ny >= 4 && (h.cls[(size_t)t.y0 * h.nx + t.x0] & CL_IN))
       t.flags |= TF_TWO;
   }
+  for (const Tile &t : c->tiles)
+    if (t.flags & TF_TWO) c->n_two += (int64_t)(t.x1 - t.x0) * (t.y1 - t.y0);
   for (const Tile &e : c->tiles) {
     if (e.flags & TF_TWO) continue;
     const PlateHost &h = c->ph[(size_t)e.plate];
@@ -904,6 +908,58 @@ lbm_status upload_boundary(lbm_ctx *c) {
   return LBM_OK;
 }
 
+bool have_third(const lbm_ctx *c) { return c->ds.u[2][0] != nullptr; }
+
+// Buffer 2 (the intermediate level of two-step pairs), allocated when a
+// two-step tiling is first used.  Its u, du/dt start as a copy of buffer
+// cur ^ 1, which holds the boundary nodes' u(t_{step+1}) that the first
+// step of a pair reads there too.
+lbm_status ensure_third(lbm_ctx *c) {
+  if (have_third(c)) return LBM_OK;
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "synchronize");
+  const int64_t N = c->n_alloc;
+  const int nsl = slot_count(c->storage);
+  for (int fl = 0; fl < 2; fl++)
+    for (int sl = 0; sl < nsl; sl++) {
+      void *p = dev_alloc(c, (size_t)N * slot_bytes(c->storage));
+      if (!p) return fail(c, LBM_E_NOMEM, "population allocation failed");
+      HIP_TRY(c, hipMemset(p, 0, (size_t)N * slot_bytes(c->storage)), "memset");
+      c->ds.pop[2][fl][sl] = p;
+    }
+  void *uv[4];
+  for (int q = 0; q < 4; q++) {
+    uv[q] = dev_alloc(c, (size_t)N * uv_bytes(c->storage));
+    if (!uv[q]) return fail(c, LBM_E_NOMEM, "u/v allocation failed");
+  }
+  const int src = c->cur ^ 1;
+  for (int comp = 0; comp < 2; comp++) {
+    HIP_TRY(c, hipMemcpy(uv[comp], c->ds.u[src][comp], (size_t)N * uv_bytes(c->storage),
+                         hipMemcpyDeviceToDevice), "u copy");
+    HIP_TRY(c, hipMemcpy(uv[2 + comp], c->ds.v[src][comp], (size_t)N * uv_bytes(c->storage),
+                         hipMemcpyDeviceToDevice), "v copy");
+    c->ds.u[2][comp] = uv[comp];
+    c->ds.v[2][comp] = uv[2 + comp];
+  }
+  drop_graph(c);
+  return LBM_OK;
+}
+
+void release_third(lbm_ctx *c) {
+  if (!have_third(c)) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (int fl = 0; fl < 2; fl++)
+    for (int sl = 0; sl < 5; sl++) {
+      dev_free(c, c->ds.pop[2][fl][sl]);
+      c->ds.pop[2][fl][sl] = nullptr;
+    }
+  for (int comp = 0; comp < 2; comp++) {
+    dev_free(c, c->ds.u[2][comp]);
+    dev_free(c, c->ds.v[2][comp]);
+    c->ds.u[2][comp] = c->ds.v[2][comp] = nullptr;
+  }
+  drop_graph(c);
+}
+
 Prologue make_prologue(const lbm_ctx *c, bool enabled) {
   Prologue p{};
   p.chunks = c->d_tchunks;
@@ -926,7 +982,8 @@ Prologue make_prologue(const lbm_ctx *c, bool enabled) {
 // t_{s+k}; then the synchronization if s + k is a multiple of l.  cur and
 // prev (buffers of t_s and of the boundary populations of t_{s-1}) are
 // advanced.  rec (profiling): an event after every launch, with the
-// launch's kind (0 interior, 1 boundary, 2 synchronization).
+// launch's kind (0 single-step interior, 1 boundary, 2 synchronization,
+// 3 two-step interior).
 struct LaunchRecorder {
   std::vector<hipEvent_t> ev;  // ev[0] before the first launch, ev[i + 1] after launch i
   std::vector<int> kind;
@@ -959,7 +1016,7 @@ hipError_t enqueue_segment(lbm_ctx *c, int64_t s, int64_t k, int &cur, int &prev
     if (c->two && s + k - n >= 2) {
       const StepBufs b1{cur, T, prev, (int)(n & 1), cur ^ 1};
       const Prologue p1 = make_prologue(c, n > s);
-      e = timed(0, [&] {
+      e = timed(3, [&] {
         return launch_interior(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), c->lanes, b1,
                                p1, st);
       });
@@ -991,7 +1048,8 @@ hipError_t enqueue_segment(lbm_ctx *c, int64_t s, int64_t k, int &cur, int &prev
   const int c_now = cur, p_now = prev;
   e = timed(1, [&] {
     return launch_boundary(c->storage, c->ds, c->d_chunks, (int)c->chunks.size(), c->d_unodes,
-                           c->d_gnodes, c->d_btasks, c->d_stasks, c_now, p_now, c_now ^ 1, T,
+                           c->d_gnodes, c->d_btasks, c->d_stasks, c_now, p_now, c_now ^ 1,
+                           have_third(c) ? T : -1,
                            (int)((s + k) & 1), 1, st);
   });
   if (e != hipSuccess) return e;
@@ -1104,7 +1162,7 @@ lbm_status start(lbm_ctx *c) {
   // both buffers the first step may write
   HIP_TRY(c, launch_boundary(c->storage, c->ds, c->d_chunks, (int)c->chunks.size(), c->d_unodes,
                              c->d_gnodes, c->d_btasks, c->d_stasks, c->cur, c->prev, c->cur ^ 1,
-                             2, 0, 0, c->stream),
+                             have_third(c) ? 2 : -1, 0, 0, c->stream),
           "first boundary step");
   c->started = true;
   return LBM_OK;
@@ -1293,7 +1351,8 @@ lbm_status lbm_create(const lbm_plate *plates, int32_t n_plates, lbm_storage sto
   };
   const int64_t N = c->n_alloc;
   const int nsl = slot_count(c->storage);
-  for (int b = 0; b < 3; b++)
+  // buffers 0 and 1; buffer 2 (two-step pairs) is allocated on first use
+  for (int b = 0; b < 2; b++)
     for (int fl = 0; fl < 2; fl++)
       for (int sl = 0; sl < 5; sl++) {
         if (sl >= nsl) {
@@ -1323,7 +1382,7 @@ lbm_status lbm_create(const lbm_plate *plates, int32_t n_plates, lbm_storage sto
       return bail(LBM_E_DEVICE, "second-row index upload");
     c->ds.sidx = d;
   }
-  for (int b = 0; b < 3; b++)
+  for (int b = 0; b < 2; b++)
     for (int comp = 0; comp < 2; comp++) {
       c->ds.u[b][comp] = dev_alloc(c, (size_t)N * uv_bytes(c->storage));
       c->ds.v[b][comp] = dev_alloc(c, (size_t)N * uv_bytes(c->storage));
@@ -1429,6 +1488,7 @@ lbm_status lbm_create(const lbm_plate *plates, int32_t n_plates, lbm_storage sto
       c->edge_rows = it->second.edge_rows;
       c->align = it->second.align;
       c->two = it->second.steps == 2 ? 1 : 0;
+      if (c->two && ensure_third(c) != LBM_OK) c->two = 0;
     } else {
       // what the autotuner picks on 1024^2 (unaligned) and 4096^2 plates
       c->lanes = 128;
@@ -1583,6 +1643,7 @@ lbm_status lbm_info(const lbm_ctx *c, lbm_info_t *info) {
   info->nodes_allocated = c->n_alloc;
   info->boundary_nodes = (int64_t)c->bnd.size();
   info->second_row_nodes = (int64_t)c->sec.size();
+  info->nodes_two_step = c->n_two;
   info->steps_done = c->step;
   info->device_bytes = c->device_bytes;
   info->bytes_per_update = bytes_per_update(c->storage);
@@ -1614,6 +1675,13 @@ lbm_status lbm_set_tiling(lbm_ctx *c, const lbm_tiling *t) {
   c->edge_rows = edge_rows;
   c->align = align;
   c->two = steps == 2 ? 1 : 0;
+  if (c->two) {
+    lbm_status st3 = ensure_third(c);
+    if (st3) {
+      c->two = 0;
+      return st3;
+    }
+  }
   build_tiles(c);
   build_tile_tables(c);
   lbm_status st = upload_tiles(c);
@@ -1698,16 +1766,12 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
   void *side_n = c->ds.side[n & 1];
   HIP_TRY(c, hipMemcpyAsync(side_save, side_n, side_bytes, hipMemcpyDeviceToDevice, c->stream),
           "side save");
-  const int lane_set[3] = {64, 128, 256};
-  const int row_set[4] = {8, 16, 32, 64};
-  const int edge_set[4] = {0, 8, 4, 2};
-  const int align_set[2] = {0, 16};
-  const int n_orders = c->ph.size() > 1 ? 3 : 1;
+  // two-step candidates only if the third state buffer fits in memory
+  const bool had_third = have_third(c);
+  const int max_steps = ensure_third(c) == LBM_OK ? 2 : 1;
   hipEvent_t e0, e1;
   HIP_TRY(c, hipEventCreate(&e0), "event");
   HIP_TRY(c, hipEventCreate(&e1), "event");
-  double best = 1e300;
-  lbm_tiling bt{c->lanes, c->rows, c->order, c->edge_rows, c->align, c->two ? 2 : 1};
   auto time_launches = [&](auto &&launch) -> double {
     hipError_t e = launch();
     (void)hipEventRecord(e0, c->stream);
@@ -1720,55 +1784,80 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
     return t / steps;
   };
   const int cur = c->cur, prev = c->prev;
-  for (int S = 1; S <= 2; S++)
-    for (int O = 0; O < n_orders; O++)
-      for (int L : lane_set)
-        for (int R : row_set)
-          for (int E : edge_set)
-            for (int A : align_set) {
-              if (E != 0 && E >= R) continue;  // same tiling as E = 0
-              c->lanes = L;
-              c->rows = R;
-              c->order = O;
-              c->edge_rows = E;
-              c->align = A;
-              c->two = S == 2 ? 1 : 0;
-              build_tiles(c);
-              build_tile_tables(c);
-              if (upload_tiles(c) != LBM_OK || upload_tile_tables(c) != LBM_OK) continue;
-              const Prologue pro = make_prologue(c, with_prologue);
-              double per;
-              if (S == 1) {
-                const StepBufs sb{cur, cur ^ 1, prev, (int)(n & 1), -1};
-                per = time_launches([&] {
-                  return launch_interior(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), L,
-                                         sb, pro, c->stream);
-                });
-              } else {
-                const StepBufs b1{cur, 2, prev, (int)(n & 1), cur ^ 1};
-                const StepBufs b2{2, cur ^ 1, cur, (int)((n + 1) & 1), -1};
-                const Prologue pro2 = make_prologue(c, true);
-                const double t1 = time_launches([&] {
-                  return launch_interior(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), L,
-                                         b1, pro, c->stream);
-                });
-                const double t2 = time_launches([&] {
-                  return launch_interior(c->storage, c->ds, c->d_etiles, (int)c->etiles.size(), L,
-                                         b2, pro2, c->stream);
-                });
-                (void)hipMemcpyAsync(side_n, side_save, side_bytes, hipMemcpyDeviceToDevice,
-                                     c->stream);
-                per = 0.5 * (t1 + t2);
-              }
-              if (per < best) {
-                best = per;
-                bt = lbm_tiling{L, R, O, E, A, S};
-              }
-            }
+  // interior time per step of one tiling (1e300 if it cannot run)
+  auto eval = [&](const lbm_tiling &T) -> double {
+    c->lanes = T.lanes;
+    c->rows = T.rows;
+    c->order = T.order;
+    c->edge_rows = T.edge_rows;
+    c->align = T.align;
+    c->two = T.steps == 2 ? 1 : 0;
+    build_tiles(c);
+    build_tile_tables(c);
+    if (upload_tiles(c) != LBM_OK || upload_tile_tables(c) != LBM_OK) return 1e300;
+    const Prologue pro = make_prologue(c, with_prologue);
+    if (T.steps == 1) {
+      const StepBufs sb{cur, cur ^ 1, prev, (int)(n & 1), -1};
+      return time_launches([&] {
+        return launch_interior(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), T.lanes, sb,
+                               pro, c->stream);
+      });
+    }
+    const StepBufs b1{cur, 2, prev, (int)(n & 1), cur ^ 1};
+    const StepBufs b2{2, cur ^ 1, cur, (int)((n + 1) & 1), -1};
+    const Prologue pro2 = make_prologue(c, true);
+    const double t1 = time_launches([&] {
+      return launch_interior(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), T.lanes, b1,
+                             pro, c->stream);
+    });
+    const double t2 = time_launches([&] {
+      return launch_interior(c->storage, c->ds, c->d_etiles, (int)c->etiles.size(), T.lanes, b2,
+                             pro2, c->stream);
+    });
+    (void)hipMemcpyAsync(side_n, side_save, side_bytes, hipMemcpyDeviceToDevice, c->stream);
+    return 0.5 * (t1 + t2);
+  };
+  double best = 1e300;
+  lbm_tiling bt{c->lanes, c->rows, c->order, c->edge_rows, c->align, c->two ? 2 : 1};
+  auto consider = [&](lbm_tiling T) {
+    if (T.edge_rows >= T.rows) T.edge_rows = 0;
+    const double per = eval(T);
+    if (per < best) {
+      best = per;
+      bt = T;
+    }
+  };
+  // Stage 1: steps per pass x lanes x rows, short tiles near boundaries,
+  // strips aligned on large plates.
+  const int a0 = c->n_body >= ((int64_t)4 << 20) ? 16 : 0;
+  for (int S = max_steps; S >= 1; S--)
+    for (int L : {64, 128, 256})
+      for (int R : {8, 16, 32}) consider(lbm_tiling{L, R, 0, std::min(4, R / 2), a0, S});
+  // Stage 2: one dimension at a time around the best.
+  {
+    const lbm_tiling b0 = bt;
+    for (int E : {0, 2, 4, 8})
+      if (E != b0.edge_rows) consider(lbm_tiling{b0.lanes, b0.rows, b0.order, E, b0.align, b0.steps});
+  }
+  {
+    const lbm_tiling b0 = bt;
+    consider(lbm_tiling{b0.lanes, b0.rows, b0.order, b0.edge_rows, b0.align ? 0 : 16, b0.steps});
+  }
+  {
+    const lbm_tiling b0 = bt;
+    for (int R : {b0.rows / 2, b0.rows * 2})
+      if (R >= 4 && R <= 64) consider(lbm_tiling{b0.lanes, R, b0.order, b0.edge_rows, b0.align, b0.steps});
+  }
+  if (c->ph.size() > 1) {
+    const lbm_tiling b0 = bt;
+    for (int O : {1, 2})
+      consider(lbm_tiling{b0.lanes, b0.rows, O, b0.edge_rows, b0.align, b0.steps});
+  }
   // The second launch of a pair wrote the boundary nodes' u(t_{n+2}) where
   // the next step expects u(t_{n+1}): recompute that from u(t_n).
   HIP_TRY(c, launch_boundary(c->storage, c->ds, c->d_chunks, (int)c->chunks.size(), c->d_unodes,
-                             c->d_gnodes, c->d_btasks, c->d_stasks, cur, prev, cur ^ 1, 2,
+                             c->d_gnodes, c->d_btasks, c->d_stasks, cur, prev, cur ^ 1,
+                             have_third(c) ? 2 : -1,
                              (int)(n & 1), 0, c->stream),
           "boundary accelerations");
   (void)hipStreamSynchronize(c->stream);
@@ -1781,6 +1870,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
   c->edge_rows = bt.edge_rows;
   c->align = bt.align;
   c->two = bt.steps == 2 ? 1 : 0;
+  if (!c->two && !had_third) release_third(c);
   build_tiles(c);
   build_tile_tables(c);
   st = upload_tiles(c);

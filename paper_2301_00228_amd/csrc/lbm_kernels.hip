@@ -1175,7 +1175,7 @@ __global__ void k_init_uv(DevState s, int plate, const double *__restrict__ u0,
     const bool in = (s.cls[k] & CL_IN) != 0;
     const U ux = in && u0 ? (U)u0[d] : U(0), uy = in && u0 ? (U)u0[n + d] : U(0);
     const U vx = in && v0 ? (U)v0[d] : U(0), vy = in && v0 ? (U)v0[n + d] : U(0);
-    for (int b = 0; b < 3; b++) {
+    for (int b = 0; b < 2; b++) {
       stg<U>(s.u[b][0], k, ux);
       stg<U>(s.u[b][1], k, uy);
       stg<U>(s.v[b][0], k, vx);

@@ -54,6 +54,7 @@ class lbm_alloc(C.Structure):
 class lbm_info_t(C.Structure):
     _fields_ = [("nodes_in_body", C.c_int64), ("nodes_allocated", C.c_int64),
                 ("boundary_nodes", C.c_int64), ("second_row_nodes", C.c_int64),
+                ("nodes_two_step", C.c_int64),
                 ("steps_done", C.c_int64), ("device_bytes", C.c_int64),
                 ("bytes_per_update", C.c_double), ("n_plates", C.c_int32),
                 ("storage", C.c_int32), ("tile_lanes", C.c_int32), ("tile_rows", C.c_int32),
@@ -276,7 +277,7 @@ class Context:
         ms = (C.c_double * 4)()
         cnt = (C.c_int64 * 4)()
         self._check(library().lbm_profile(self._h, int(n), ms, cnt))
-        names = ("interior", "boundary", "sync", "other")
+        names = ("interior", "boundary", "sync", "two_step")
         return {k: (ms[i], cnt[i]) for i, k in enumerate(names)}
 
     def use_graphs(self, on=True):

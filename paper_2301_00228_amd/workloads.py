@@ -45,9 +45,18 @@ def timed(cases, storage, steps, warmup, tune=True):
     print(f"context {storage}: {setup:.1f} s", file=sys.stderr, flush=True)
     ctx.step(2)
     if tune:
-        ctx.autotune(3)
-        print("tuned", ctx.info()["tile_lanes"], ctx.info()["tile_rows"], file=sys.stderr,
-              flush=True)
+        t1 = time.perf_counter()
+        t_set = time.perf_counter()
+        ctx.set_tiling(128, 16, 0, 4, 16, 2)
+        t_set = time.perf_counter() - t_set
+        print(f"one tiling set up in {t_set:.2f} s", file=sys.stderr, flush=True)
+        # the autotuner sets up about 30 tilings
+        if t_set < 4.0:
+            ctx.autotune(3)
+        i = ctx.info()
+        print("tuned", [i["tile_lanes"], i["tile_rows"], i["tile_order"], i["tile_edge_rows"],
+                        i["tile_align"], i["tile_steps"]],
+              f"in {time.perf_counter() - t1:.1f} s", file=sys.stderr, flush=True)
     ctx.step(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -55,16 +64,22 @@ def timed(cases, storage, steps, warmup, tune=True):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     info = ctx.info()
-    prof = ctx.profile(3)
-    i_ms, i_n = prof["interior"]
+    prof = ctx.profile(4)
+    # the launch that reads and writes every body node once: the first of a
+    # two-step pair, else the single-step launch
+    kind = "two_step" if prof["two_step"][1] > 0 else "interior"
+    i_ms, i_n = prof[kind]
     b_ms, b_n = prof["boundary"]
     per = i_ms / i_n / 1e3
     nodes = info["nodes_in_body"]
     achieved = nodes * info["bytes_per_update"] / per / 1e9
     res = {"storage": storage, "plates": info["n_plates"], "nodes": nodes, "steps": steps,
            "glups": nodes * steps / dt / 1e9, "ms_per_step": dt / steps * 1e3,
-           "interior_us": per * 1e6, "interior_GBs": achieved,
+           "interior_kind": kind, "interior_us": per * 1e6, "interior_GBs": achieved,
            "interior_frac": achieved / HBM_PEAK_GBS, "boundary_us": b_ms / max(b_n, 1) * 1e3,
+           "second_launch_us": (prof["interior"][0] / max(prof["interior"][1], 1) * 1e3
+                                if kind == "two_step" else None),
+           "two_step_nodes": info["nodes_two_step"],
            "bytes_per_lup": info["bytes_per_update"], "boundary_nodes": info["boundary_nodes"],
            "tile": [info["tile_lanes"], info["tile_rows"], info["tile_order"],
                     info["tile_edge_rows"], info["tile_align"], info["tile_steps"]],
