@@ -726,30 +726,37 @@ __device__ void march2(const DevState &s, const Tile &t, const StepBufs &sb,
   const int d = t.dir ? -1 : 1;
   const int h = t.y1 - t.y0;
   auto row_y = [&](int i) { return wrapc(d > 0 ? t.y0 + i : t.y1 - 1 - i, P.ny); };
+  // Every lane loads (lanes past the tile from column x0, their values are
+  // not used): a load under a branch, or a default written over the
+  // registers of a load in flight, makes the compiler wait for all
+  // outstanding memory operations right there.
+  const int xl = live ? x : t.x0;
   auto load_raw = [&](int i, Slot raw[2][5]) {
-#pragma unroll
-    for (int fl = 0; fl < 2; fl++)
-#pragma unroll
-      for (int qq = 0; qq < 5; qq++) raw[fl][qq] = Slot(0);
-    if (live) {
-      const int64_t k = node_of(P, x, row_y(i));
-      CD::load_raw(s, sb.in, 0, k, raw[0]);
-      CD::load_raw(s, sb.in, 1, k, raw[1]);
-    }
+    const int64_t k = node_of(P, xl, row_y(i));
+    CD::load_raw(s, sb.in, 0, k, raw[0]);
+    CD::load_raw(s, sb.in, 1, k, raw[1]);
   };
   auto load_uv = [&](int i, U uv[4]) {
-    uv[0] = uv[1] = uv[2] = uv[3] = U(0);
-    if (stepA) {
-      const int64_t k = node_of(P, x, row_y(i));
-      uv[0] = ldg<U>(s.u[sb.in][0], k);
-      uv[1] = ldg<U>(s.u[sb.in][1], k);
-      uv[2] = ldg<U>(s.v[sb.in][0], k);
-      uv[3] = ldg<U>(s.v[sb.in][1], k);
-    }
+    const int64_t k = node_of(P, xl, row_y(i));
+    uv[0] = ldg<U>(s.u[sb.in][0], k);
+    uv[1] = ldg<U>(s.u[sb.in][1], k);
+    uv[2] = ldg<U>(s.v[sb.in][0], k);
+    uv[3] = ldg<U>(s.v[sb.in][1], k);
   };
   auto collide = [&](const C f[2][5], C rho[2], C fs[2][5]) {
 #pragma unroll
     for (int fl = 0; fl < 2; fl++) collide_pops<CD>(P, fl, f[fl], rho[fl], fs[fl]);
+  };
+  // t_n values of lanes past the tile (their loads read column x0)
+  auto clear_dead = [&](C rho[2], C fs[2][5]) {
+    if (!live) {
+#pragma unroll
+      for (int fl = 0; fl < 2; fl++) {
+        rho[fl] = C(0);
+#pragma unroll
+        for (int qq = 0; qq < 5; qq++) fs[fl][qq] = C(0);
+      }
+    }
   };
   auto publish = [&](C(*ex)[X_N][TWL], int slot, const C rho[2], const C fs[2][5]) {
     ex[slot][X_RHO0][lane] = rho[0];
@@ -791,7 +798,7 @@ __device__ void march2(const DevState &s, const Tile &t, const StepBufs &sb,
   C a2_rho[2], a2_fb[2], a1_rho[2], a1_f0[2], a1_fb[2];
   // t_{n+1} stage registers: row a-3 (rho, behind pop), row a-2 (rho, f0, behind pop)
   C b3_rho[2], b3_fb[2], b2_rho[2], b2_f0[2], b2_fb[2];
-  U uvA[4];   // u, du/dt of t_n, row a-1
+  U uvA[4];   // u, du/dt of t_n, row a-1 (row a once step n of row a-1 is done)
   U uvB[4];   // u, du/dt of t_{n+1}, row a-2
   Slot rawn[2][5];  // t_n populations of row a
   {
@@ -802,6 +809,7 @@ __device__ void march2(const DevState &s, const Tile &t, const StepBufs &sb,
 #pragma unroll
     for (int fl = 0; fl < 2; fl++) CD::raw_to_pops(P, fl, raw[fl], f[fl]);
     collide(f, rho, fs);
+    clear_dead(rho, fs);
     a2_rho[0] = rho[0];
     a2_rho[1] = rho[1];
     a2_fb[0] = behind_pop(fs[0]);
@@ -811,6 +819,7 @@ __device__ void march2(const DevState &s, const Tile &t, const StepBufs &sb,
     load_raw(0, rawn);
     load_uv(-1, uvA);
     collide(f, rho, fs);
+    clear_dead(rho, fs);
     publish(exA, slot_of(-1), rho, fs);
     a1_rho[0] = rho[0];
     a1_rho[1] = rho[1];
@@ -825,14 +834,14 @@ __device__ void march2(const DevState &s, const Tile &t, const StepBufs &sb,
       b3_rho[fl] = b3_fb[fl] = b2_rho[fl] = b2_f0[fl] = b2_fb[fl] = C(0);
   }
   for (int a = 0; a <= h + 1; a++) {
-    // collide t_n row a, prefetch row a+1 and u of row a
+    // collide t_n row a and prefetch row a+1 into the registers it used
+    // (the last iteration reloads row h+1)
     C f[2][5], rho[2], fs[2][5];
 #pragma unroll
     for (int fl = 0; fl < 2; fl++) CD::raw_to_pops(P, fl, rawn[fl], f[fl]);
-    if (a + 1 <= h + 1) load_raw(a + 1, rawn);
-    U uvn[4];
-    load_uv(a, uvn);
+    load_raw(a + 1 <= h + 1 ? a + 1 : h + 1, rawn);
     collide(f, rho, fs);
+    clear_dead(rho, fs);
     publish(exA, slot_of(a), rho, fs);
     __syncthreads();
     // step n at row a-1 (columns x0-1 .. x1)
@@ -840,6 +849,8 @@ __device__ void march2(const DevState &s, const Tile &t, const StepBufs &sb,
     C g[2][5];
     U nu[4];
     finalize(exA, a - 1, a1_f0, a2_fb, fa, a2_rho, rho, uvA, g, nu);
+    // u of row a (for the next row's step n) into the registers just used
+    load_uv(a <= h ? a : h, uvA);
     const int ya = row_y(a - 1);
     if (stepA && a - 1 >= 0 && a - 1 < h) {
       const bool exp = ((t.flags & TF_EXP_W) && lane == 2) ||
@@ -899,10 +910,7 @@ __device__ void march2(const DevState &s, const Tile &t, const StepBufs &sb,
       b2_fb[fl] = behind_pop(fs1[fl]);
     }
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
-      uvB[q] = nu[q];
-      uvA[q] = uvn[q];
-    }
+    for (int q = 0; q < 4; q++) uvB[q] = nu[q];
   }
 }
 
