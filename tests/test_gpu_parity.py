@@ -200,6 +200,28 @@ def test_reduced_storages_bitwise_across_tilings(storage):
             assert np.array_equal(outs[0][k], o[k]), (storage, k)
 
 
+def test_switching_steps_per_pass_mid_run():
+    """Switching to two-step tiles mid-run allocates the third buffer from
+    the current state; switching back and forth keeps the trajectory."""
+    case = I.plate_with_hole(n=130, radius=18, sigma=4.0, steps=0, sync_every=40)
+    with lbm.context_for(case) as ctx:
+        ctx.set_tiling(64, 8, 0, 2, 0, 1)
+        ctx.step(97)
+        base = ctx.fields(0)
+    with lbm.context_for(case) as ctx:
+        ctx.set_tiling(64, 8, 0, 2, 0, 1)
+        ctx.step(31)
+        ctx.set_tiling(128, 16, 0, 4, 16, 2)
+        ctx.step(23)
+        ctx.set_tiling(64, 8, 1, 2, 0, 1)
+        ctx.step(20)
+        ctx.set_tiling(256, 8, 0, 0, 0, 2)
+        ctx.step(23)
+        got = ctx.fields(0)
+    for k in FIELDS:
+        assert np.array_equal(base[k], got[k]), k
+
+
 def test_repeat_runs_are_deterministic():
     case = I.clamped_plate(n=70, sigma=4.0, steps=90, sync_every=50)
     a, b = gpu_run(case), gpu_run(case)
