@@ -152,33 +152,39 @@ def main():
     f64_fields = ctx.fields(0)
     tile = [info["tile_lanes"], info["tile_rows"], info["tile_order"], info["tile_edge_rows"],
             info["tile_align"], info["tile_steps"]]
-    # Dominant kernel: the interior launch that moves the most bytes -- the
-    # two-step launch of a pair (two steps of the two-step tiles, one of the
-    # others: every body node read and written once) or the single-step
-    # launch.  Device time per launch from HIP events on the library's
-    # stream, eager back-to-back launches.
+    # Dominant kernel: the interior launch with the most device time -- the
+    # first launch of a two-step pair (two steps of the two-step tiles, one
+    # of the others) or the single-step launch.  Device time per launch from
+    # HIP events on the library's stream, eager back-to-back launches.
+    # achieved = algorithmic bytes per lattice update x the lattice updates
+    # the launch performs / its time; the launch streams each body node's
+    # state once, so with two steps per pass this exceeds the rate at which
+    # it actually streams (min_bytes / time) and the measured traffic.
     prof = ctx.profile(args.profile_steps)
     bnd_ms, bnd_n = prof["boundary"]
     bpu = info["bytes_per_update"]
     kind = "two_step" if prof["two_step"][1] > 0 else "interior"
     k_ms, k_n = prof[kind]
     per_launch_s = k_ms / k_n / 1e3
-    achieved = nodes * bpu / per_launch_s / 1e9
+    n_two = info["nodes_two_step"] if kind == "two_step" else 0
+    lups = nodes + n_two
+    achieved = lups * bpu / per_launch_s / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(args.storage, kind, tile),
                 "kernel": f"k_interior<{args.storage}, {info['tile_lanes']} lanes, "
                           f"{'two-step' if kind == 'two_step' else 'single-step'}>",
-                "bytes_per_lup": bpu, "lups_per_launch": nodes,
-                "bytes_per_launch": nodes * bpu,
+                "bytes_per_lup": bpu, "lups_per_launch": lups,
                 "avg_launch_us": round(per_launch_s * 1e6, 2),
+                "min_bytes_per_launch": nodes * bpu,
+                "min_bytes_GBs": round(nodes * bpu / per_launch_s / 1e9, 1),
                 "boundary_kernel_avg_us": round(bnd_ms / max(bnd_n, 1) * 1e3, 2)}
     if kind == "two_step":
         s_ms, s_n = prof["interior"]
-        roofline["two_step_nodes"] = info["nodes_two_step"]
+        roofline["two_step_nodes"] = n_two
         roofline["second_launch_avg_us"] = round(s_ms / max(s_n, 1) * 1e3, 2)
-    # what a scheme with one step per pass over HBM would have to stream at
-    # the measured step rate (can exceed the peak when steps are fused)
+    # what one step per pass over HBM would have to stream at the measured
+    # step rate
     roofline["effective_GBs"] = round(nodes * bpu / (dt / K) / 1e9, 1)
     ctx.close()
 
@@ -189,9 +195,11 @@ def main():
             c2, d2 = timed_run(st)
             fl = c2.fields(0)
             pr = c2.profile(min(args.profile_steps, 100))
-            i_ms, i_n = pr["two_step"] if pr["two_step"][1] > 0 else pr["interior"]
+            two = pr["two_step"][1] > 0
+            i_ms, i_n = pr["two_step"] if two else pr["interior"]
             bpu2 = c2.info()["bytes_per_update"]
-            ach2 = nodes * bpu2 / (i_ms / i_n / 1e3) / 1e9
+            lups2 = nodes + (c2.info()["nodes_two_step"] if two else 0)
+            ach2 = lups2 * bpu2 / (i_ms / i_n / 1e3) / 1e9
             c2.close()
             variants[st] = {
                 "glups": round(nodes * K / d2 / 1e9, 3),
