@@ -48,12 +48,17 @@ namespace lbm {
 // populations of f_eq(rho, J) (eq. feq, lattice units c = 1, b = 1) exactly
 // as load() returns them after store_eq().
 
-__device__ __forceinline__ uint16_t f32_to_bf16_rne(float x) {
-  uint32_t u = __float_as_uint(x);
-  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40);
-  uint32_t lsb = (u >> 16) & 1u;
-  u += 0x7fffu + lsb;
-  return (uint16_t)(u >> 16);
+// 16-bit conversions for the stored non-equilibrium moments.
+//
+// x to BF16 by truncation after adding r (0 <= r < 2^16) below its last
+// significand bit: with r uniform, x rounds away from zero with probability
+// equal to its distance from the truncated value in ulps (the magnitude
+// bits are linear in the value within a binade; a carry moves to the next
+// binade as it should).  NaN stays NaN.
+__device__ __forceinline__ uint16_t f32_to_bf16_sr(float x, uint32_t r) {
+  const uint32_t u = __float_as_uint(x);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0x007fffffu) ? 0x40 : 0));
+  return (uint16_t)((u + r) >> 16);
 }
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
@@ -61,6 +66,30 @@ __device__ __forceinline__ uint16_t f32_to_f16_rne(float x) {
   return __half_as_ushort(__float2half_rn(x));
 }
 __device__ __forceinline__ float f16_to_f32(uint16_t h) { return __half2float(__ushort_as_half(h)); }
+// x to FP16 by adding r (0 <= r < 2^13) below the last significand bit of
+// an FP16 normal number and clearing the FP32 bits below it: in the FP16
+// normal range the result converts exactly, so x rounds away from zero
+// with probability equal to its fraction of an ulp.  Below that range
+// (|x| < 2^-14) the conversion rounds to nearest once more; infinity and
+// NaN convert as they are.
+__device__ __forceinline__ uint16_t f32_to_f16_sr(float x, uint32_t r) {
+  const uint32_t u = __float_as_uint(x);
+  if ((u & 0x7f800000u) == 0x7f800000u) return f32_to_f16_rne(x);
+  return f32_to_f16_rne(__uint_as_float((u + r) & 0xffffe000u));
+}
+
+// 32 well-mixed bits from three words and a small tag: each word enters
+// through a multiply by an odd constant, then the lowbias32 finalizer
+// (C. Wellons, "Prospecting for hash functions", 2018).
+__device__ __forceinline__ uint32_t rand_bits(uint32_t a, uint32_t b, uint32_t c, uint32_t tag) {
+  uint32_t h = a * 0x9e3779b1u + b * 0x85ebca77u + c * 0xc2b2ae3du + tag * 0x27d4eb2fu;
+  h ^= h >> 16;
+  h *= 0x7feb352du;
+  h ^= h >> 15;
+  h *= 0x846ca68bu;
+  h ^= h >> 16;
+  return h;
+}
 
 template <class T>
 __device__ __forceinline__ T ldg(const void *p, int64_t k) {
@@ -79,6 +108,19 @@ __device__ __forceinline__ void eq_populations(C a0, C a, C rho, C jx, C jy, C f
   f[2] = ar + C(0.5) * jy;
   f[3] = ar - C(0.5) * jx;
   f[4] = ar - C(0.5) * jy;
+}
+
+// Post-collision populations f* = f - 2 (f - f_eq(f)) and zeroth moment of
+// one field (eq. LBE with dt/tau = 2).
+template <class C>
+__device__ __forceinline__ void collide_populations(C a0, C a, const C f[5], C &rho, C fs[5]) {
+  const C r = f[0] + ((f[1] + f[3]) + (f[2] + f[4]));
+  const C jx = f[1] - f[3], jy = f[2] - f[4];
+  C e[5];
+  eq_populations<C>(a0, a, r, jx, jy, e);
+#pragma unroll
+  for (int q = 0; q < 5; q++) fs[q] = f[q] - C(2.0) * (f[q] - e[q]);
+  rho = r;
 }
 
 // Plain populations, FP64 or FP32.
@@ -130,8 +172,17 @@ struct PopCodec {
     load(s, b, fl, k, P, f);
     return (double)(f[0] + ((f[1] + f[3]) + (f[2] + f[4])));
   }
-  // f as a store and a load would return it (exact for plain storage)
-  __device__ static void roundtrip(const PlateDev &, int, C[5]) {}
+  // rho and f* of the stored populations r (eq. LBE)
+  __device__ static void collide_raw(const PlateDev &P, int fl, const Slot r[5], C &rho,
+                                     C fs[5]) {
+    collide_populations<C>(a0w(P, fl), aw(P, fl), r, rho, fs);
+  }
+  // rho and f* of populations f as a store and a load would return them
+  // (plain storage keeps them exactly)
+  __device__ static void collide_stored(const PlateDev &P, int fl, const C f[5], C &rho,
+                                        C fs[5]) {
+    collide_populations<C>(a0w(P, fl), aw(P, fl), f, rho, fs);
+  }
 };
 
 // Deviation from the local rest equilibrium in a moment basis:
@@ -155,15 +206,25 @@ struct DevCodec {
       d = bf16_to_f32(hi) * P.iscale[fl];
     }
   }
-  __device__ static uint32_t pack(float n, float d, const PlateDev &P, int fl) {
-    const float sn = n * P.scale[fl], sd = d * P.scale[fl];
+  // N = m[3] and D = m[4] in the 16-bit type, rounded stochastically:
+  // each value rounds away from zero with probability equal to its fraction
+  // of an ulp, so the rounding errors are unbiased and uncorrelated from
+  // step to step (round-to-nearest leaves nearly the same error on a slowly
+  // varying moment step after step, and those errors add up).  The random
+  // bits are a hash of the node's stored rho and J, whose low bits change
+  // from step to step, so the stored state stays a function of the state
+  // it comes from (every tiling and launch shape gives the same bits).
+  __device__ static uint32_t pack(const float m[5], const PlateDev &P, int fl) {
+    const float sn = m[3] * P.scale[fl], sd = m[4] * P.scale[fl];
     uint16_t lo, hi;
+    const uint32_t r = rand_bits(__float_as_uint(m[0]), __float_as_uint(m[1]),
+                                 __float_as_uint(m[2]), (uint32_t)fl);
     if (H == 1) {
-      lo = f32_to_f16_rne(sn);
-      hi = f32_to_f16_rne(sd);
+      lo = f32_to_f16_sr(sn, r & 0x1fffu);
+      hi = f32_to_f16_sr(sd, (r >> 16) & 0x1fffu);
     } else {
-      lo = f32_to_bf16_rne(sn);
-      hi = f32_to_bf16_rne(sd);
+      lo = f32_to_bf16_sr(sn, r & 0xffffu);
+      hi = f32_to_bf16_sr(sd, r >> 16);
     }
     return (uint32_t)lo | ((uint32_t)hi << 16);
   }
@@ -228,7 +289,7 @@ struct DevCodec {
       stg<float>(s.pop[b][fl][3], k, m[3]);
       stg<float>(s.pop[b][fl][4], k, m[4]);
     } else {
-      stg<uint32_t>(s.pop[b][fl][3], k, pack(m[3], m[4], P, fl));
+      stg<uint32_t>(s.pop[b][fl][3], k, pack(m, P, fl));
     }
   }
   __device__ static void store(const DevState &s, int b, int fl, int64_t k, const PlateDev &P,
@@ -260,9 +321,35 @@ struct DevCodec {
   __device__ static double field(const DevState &s, int b, int fl, int64_t k, const PlateDev &) {
     return (double)ldg<float>(s.pop[b][fl][0], k);
   }
-  // f as store() followed by load() returns it: the same moments and
-  // rounding, without the memory
-  __device__ static void roundtrip(const PlateDev &P, int fl, C f[5]) {
+  // The collision in the moment basis: rho and J are kept and the two
+  // non-equilibrium moments N and D change sign (f* = 2 f_eq - f with
+  // f_eq of rho and J, eq. LBE with dt/tau = 2), so rho is conserved
+  // exactly whatever the rounding of the weights.
+  __device__ static void post_collision(const PlateDev &P, int fl, const float m[5], C &rho,
+                                        C fs[5]) {
+    const float mc[5] = {m[0], m[1], m[2], -m[3], -m[4]};
+    moments_to_pops(P, fl, mc, fs);
+    rho = m[0];
+  }
+  // rho and f* of the stored moments r
+  __device__ static void collide_raw(const PlateDev &P, int fl, const Slot r[5], C &rho,
+                                     C fs[5]) {
+    float m[5];
+    m[0] = __uint_as_float(r[0]);
+    m[1] = __uint_as_float(r[1]);
+    m[2] = __uint_as_float(r[2]);
+    if (H == 0) {
+      m[3] = __uint_as_float(r[3]);
+      m[4] = __uint_as_float(r[4]);
+    } else {
+      unpack(r[3], P, fl, m[3], m[4]);
+    }
+    post_collision(P, fl, m, rho, fs);
+  }
+  // rho and f* of populations f as store() followed by a load returns them:
+  // the same moments and rounding, without the memory
+  __device__ static void collide_stored(const PlateDev &P, int fl, const C f[5], C &rho,
+                                        C fs[5]) {
     const float s13 = f[1] + f[3], s24 = f[2] + f[4];
     const float q = s13 + s24;
     float m[5];
@@ -271,8 +358,8 @@ struct DevCodec {
     m[2] = f[2] - f[4];
     m[3] = s13 - s24;
     m[4] = q - 4.0f * aw(P, fl) * m[0];
-    if (H != 0) unpack(pack(m[3], m[4], P, fl), P, fl, m[3], m[4]);
-    moments_to_pops(P, fl, m, f);
+    if (H != 0) unpack(pack(m, P, fl), P, fl, m[3], m[4]);
+    post_collision(P, fl, m, rho, fs);
   }
 };
 
@@ -371,28 +458,12 @@ __device__ double load_amp(const DevState &s, int li, double t) {
   return L.g[n - 1];
 }
 
-// Post-collision populations f* = f - 2 (f - f_eq(f)) and zeroth moment of
-// one field (eq. LBE with dt/tau = 2).
+// Collision of populations that are not a stored state (the averaged
+// populations of the second-row rule).
 template <class CD>
 __device__ __forceinline__ void collide_pops(const PlateDev &P, int fl, const typename CD::C f[5],
                                              typename CD::C &rho, typename CD::C fs[5]) {
-  using C = typename CD::C;
-  const C r = f[0] + ((f[1] + f[3]) + (f[2] + f[4]));
-  const C jx = f[1] - f[3], jy = f[2] - f[4];
-  C e[5];
-  eq_populations<C>(CD::a0w(P, fl), CD::aw(P, fl), r, jx, jy, e);
-#pragma unroll
-  for (int q = 0; q < 5; q++) fs[q] = f[q] - C(2.0) * (f[q] - e[q]);
-  rho = r;
-}
-
-template <class CD>
-__device__ __forceinline__ void collide(const DevState &s, int b, int fl, int64_t k,
-                                        const PlateDev &P, typename CD::C &rho,
-                                        typename CD::C fs[5]) {
-  typename CD::C f[5];
-  CD::load(s, b, fl, k, P, f);
-  collide_pops<CD>(P, fl, f, rho, fs);
+  collide_populations<typename CD::C>(CD::a0w(P, fl), CD::aw(P, fl), f, rho, fs);
 }
 
 // ------------------------------------------- boundary / second-row work
@@ -743,9 +814,9 @@ __device__ void march2(const DevState &s, const Tile &t, const StepBufs &sb,
     uv[2] = ldg<U>(s.v[sb.in][0], k);
     uv[3] = ldg<U>(s.v[sb.in][1], k);
   };
-  auto collide = [&](const C f[2][5], C rho[2], C fs[2][5]) {
+  auto collide_raw = [&](const Slot raw[2][5], C rho[2], C fs[2][5]) {
 #pragma unroll
-    for (int fl = 0; fl < 2; fl++) collide_pops<CD>(P, fl, f[fl], rho[fl], fs[fl]);
+    for (int fl = 0; fl < 2; fl++) CD::collide_raw(P, fl, raw[fl], rho[fl], fs[fl]);
   };
   // t_n values of lanes past the tile (their loads read column x0)
   auto clear_dead = [&](C rho[2], C fs[2][5]) {
@@ -803,22 +874,22 @@ __device__ void march2(const DevState &s, const Tile &t, const StepBufs &sb,
   Slot rawn[2][5];  // t_n populations of row a
   {
     Slot raw[2][5];
-    C f[2][5], rho[2], fs[2][5];
+    C rho[2], fs[2][5];
     load_raw(-2, raw);
     load_raw(-1, rawn);
-#pragma unroll
-    for (int fl = 0; fl < 2; fl++) CD::raw_to_pops(P, fl, raw[fl], f[fl]);
-    collide(f, rho, fs);
+    collide_raw(raw, rho, fs);
     clear_dead(rho, fs);
     a2_rho[0] = rho[0];
     a2_rho[1] = rho[1];
     a2_fb[0] = behind_pop(fs[0]);
     a2_fb[1] = behind_pop(fs[1]);
 #pragma unroll
-    for (int fl = 0; fl < 2; fl++) CD::raw_to_pops(P, fl, rawn[fl], f[fl]);
+    for (int fl = 0; fl < 2; fl++)
+#pragma unroll
+      for (int qq = 0; qq < 5; qq++) raw[fl][qq] = rawn[fl][qq];
     load_raw(0, rawn);
     load_uv(-1, uvA);
-    collide(f, rho, fs);
+    collide_raw(raw, rho, fs);
     clear_dead(rho, fs);
     publish(exA, slot_of(-1), rho, fs);
     a1_rho[0] = rho[0];
@@ -836,11 +907,14 @@ __device__ void march2(const DevState &s, const Tile &t, const StepBufs &sb,
   for (int a = 0; a <= h + 1; a++) {
     // collide t_n row a and prefetch row a+1 into the registers it used
     // (the last iteration reloads row h+1)
-    C f[2][5], rho[2], fs[2][5];
+    Slot raw[2][5];
+    C rho[2], fs[2][5];
 #pragma unroll
-    for (int fl = 0; fl < 2; fl++) CD::raw_to_pops(P, fl, rawn[fl], f[fl]);
+    for (int fl = 0; fl < 2; fl++)
+#pragma unroll
+      for (int qq = 0; qq < 5; qq++) raw[fl][qq] = rawn[fl][qq];
     load_raw(a + 1 <= h + 1 ? a + 1 : h + 1, rawn);
-    collide(f, rho, fs);
+    collide_raw(raw, rho, fs);
     clear_dead(rho, fs);
     publish(exA, slot_of(a), rho, fs);
     __syncthreads();
@@ -866,9 +940,8 @@ __device__ void march2(const DevState &s, const Tile &t, const StepBufs &sb,
     // collide t_{n+1} row a-1 (as a store and a load between two launches
     // would leave it) and hand it to the x-neighbours
     C rho1[2], fs1[2][5];
-    CD::roundtrip(P, 0, g[0]);
-    CD::roundtrip(P, 1, g[1]);
-    collide(g, rho1, fs1);
+    CD::collide_stored(P, 0, g[0], rho1[0], fs1[0]);
+    CD::collide_stored(P, 1, g[1], rho1[1], fs1[1]);
     if (!stepA) {
 #pragma unroll
       for (int fl = 0; fl < 2; fl++) {
@@ -992,9 +1065,7 @@ __global__ void __launch_bounds__(TWL)
   auto collide_row = [&](uint8_t cl, const Slot raw[2][5], C rho[2], C fs[2][5]) {
 #pragma unroll
     for (int fl = 0; fl < 2; fl++) {
-      C f[5];
-      CD::raw_to_pops(P, fl, raw[fl], f);
-      collide_pops<CD>(P, fl, f, rho[fl], fs[fl]);
+      CD::collide_raw(P, fl, raw[fl], rho[fl], fs[fl]);
       if (!(cl & CL_IN)) {
         rho[fl] = C(0);
 #pragma unroll

@@ -11,8 +11,12 @@ from paper_2301_00228_amd import lbm
 
 pytestmark = pytest.mark.gpu
 
-# Bound per storage on max(rel L2 of e, omega, u) after 2000 steps.
-BOUND = {"f32": 1e-3, "f32dev": 1e-3, "f16dev": 1e-3, "bf16dev": 1e-2}
+# Bound per storage on max(rel L2 of e, omega, u) after 2000 steps.  The
+# sigma = 8 pulse on this small plate has steeper gradients, hence larger
+# non-equilibrium moments relative to the fields, than the 1024^2 and 8192^2
+# workloads; BF16 (8 significand bits) stays within 1e-3 there
+# (test_sixteen_bit_storages_on_the_clamped_plate) but not here.
+BOUND = {"f32": 1e-3, "f32dev": 1e-5, "f16dev": 1e-3, "bf16dev": 2e-3}
 
 
 def rel_l2(a, b):
@@ -38,3 +42,22 @@ def test_reduced_storage_error(reference, storage):
     print(storage, {k: f"{v:.3e}" for k, v in errs.items()}, flush=True)
     bound = 1e-12 if storage == "f64" else BOUND[storage]
     assert max(errs.values()) <= bound, (storage, errs)
+
+
+@pytest.mark.parametrize("storage", ["f16dev", "bf16dev"])
+def test_sixteen_bit_storages_on_the_clamped_plate(storage):
+    """The 1024^2 clamped plate (sigma 16 pulse, a0_phi = 0.9999, synchronization
+    every 50 steps): after 2000 steps within 1e-3 relative L2 of the FP64 path
+    (itself held to the oracle by the parity tests)."""
+    import torch
+    torch.cuda.set_device(0)
+    case = I.clamped_plate(n=1024, steps=2000)
+    with lbm.context_for(case, "f64") as ctx:
+        ctx.step(case.steps)
+        ref = ctx.fields(0)
+    with lbm.context_for(case, storage) as ctx:
+        ctx.step(case.steps)
+        got = ctx.fields(0)
+    errs = {k: rel_l2(got[k], ref[k]) for k in ("e", "omega", "u")}
+    print(storage, "1024^2", {k: f"{v:.3e}" for k, v in errs.items()}, flush=True)
+    assert max(errs.values()) <= 1e-3, (storage, errs)
