@@ -769,6 +769,14 @@ __device__ __forceinline__ void interior_update(const PlateDev &P, U e0, U w0, U
 // Exchange slots in LDS per lane and row.
 enum { X_RHO0 = 0, X_RHO1, X_F1_0, X_F1_1, X_F3_0, X_F3_1, X_N };
 
+// LDS rows of the x-exchange per march stage.  Each row is published one
+// iteration before it is read, with one barrier per iteration.  Several
+// waves need three rows (a wave one barrier ahead may publish the next row
+// while another still reads the previous one); a single wave executes its
+// LDS accesses in order, so two rows suffice, which leaves LDS room for
+// more waves per CU.
+__host__ __device__ constexpr int ex_rows(int lanes) { return lanes == 64 ? 2 : 3; }
+
 __device__ __forceinline__ int tile_index(int b, int q) { return (b & 7) * q + (b >> 3); }
 
 // Two steps of a tile whose area and two-node halo ring hold only interior
@@ -840,7 +848,8 @@ __device__ void march2(const DevState &s, const Tile &t, const StepBufs &sb,
   // population a row streams into the row after it (behind) / before it
   auto behind_pop = [&](const C fs[5]) { return d > 0 ? fs[2] : fs[4]; };
   auto ahead_pop = [&](const C fs[5]) { return d > 0 ? fs[4] : fs[2]; };
-  auto slot_of = [](int i) { return (i + 3) % 3; };
+  constexpr int NS = ex_rows(TWL);
+  auto slot_of = [](int i) { return (i + 3 * NS) % NS; };  // i >= -3
   // Pull into row i of one stage: f0 of the row, f1 / f3 from the x
   // neighbours (slot of row i), the behind row's and the ahead row's pops;
   // then the u, du/dt update from the neighbours' rho.
@@ -987,15 +996,19 @@ __device__ void march2(const DevState &s, const Tile &t, const StepBufs &sb,
   }
 }
 
+// (FP64 with two-step tiles of one wave: at most 168 VGPRs, so that three
+// waves fit per SIMD; with more lanes per tile LDS allows only two.)
 template <int ST, int TWL, bool TWO>
 __global__ void __launch_bounds__(TWL)
+    __attribute__((amdgpu_waves_per_eu((TWO && ST == LBM_STORE_F64 && TWL == 64) ? 3 : 1)))
     k_interior(DevState s, const Tile *__restrict__ tiles, int ntiles, int q, StepBufs sb,
                Prologue pro) {
   using CD = typename CodecOf<ST>::type;
   using C = typename CD::C;
   using U = typename CD::U;
   using Slot = typename CD::Slot;
-  __shared__ C exs[TWO ? 6 : 3][X_N][TWL];
+  constexpr int NS = ex_rows(TWL);
+  __shared__ C exs[TWO ? 2 * NS : NS][X_N][TWL];
   C(*ex)[X_N][TWL] = exs;
 
   // populations and u, du/dt of t_n in buffers sb.in, of t_{n+1} in sb.out
@@ -1005,7 +1018,7 @@ __global__ void __launch_bounds__(TWL)
   if (tix >= ntiles) return;
   const Tile t = tiles[tix];
   if (TWO && sb.out2 >= 0 && (t.flags & TF_TWO)) {
-    march2<CD, TWL>(s, t, sb, exs, exs + 3);
+    march2<CD, TWL>(s, t, sb, exs, exs + NS);
     return;
   }
   if (pro.enabled && t.chunk >= 0) prologue<CD>(s, pro, t.chunk, sb, (int)threadIdx.x, TWL);
@@ -1130,7 +1143,7 @@ __global__ void __launch_bounds__(TWL)
   int slot = 0;
   for (int k = 0; k < h; k++) {
     const int r = r0 + k * d;
-    const int nslot = slot == 2 ? 0 : slot + 1;
+    const int nslot = slot + 1 == NS ? 0 : slot + 1;
     // prefetch
     cl3 = in_reach(k + 3) ? load_cls(r + 3 * d) : (uint8_t)0;
     Slot raw2[2][5];
