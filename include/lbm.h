@@ -126,7 +126,10 @@ lbm_status lbm_create(const lbm_plate *plates, int32_t n_plates, lbm_storage sto
  *        (eq. acc_neumann), per unit thickness.
  * cell : NULL, or 5n values (V_C, l_E, l_N, l_W, l_S) replacing the mask-rule
  *        cell volume and the lengths of the internal sides towards the E, N,
- *        W, S neighbours (for boundaries that do not follow the lattice).
+ *        W, S neighbours (for boundaries that do not follow the lattice, e.g.
+ *        from lbm_exact_cells).  A side towards a neighbour outside the body
+ *        may have a nonzero length: its stress is the node's own.  The
+ *        mask rule gives such sides length 0.
  * knots: n_knots (t, g) pairs of a piecewise linear amplitude g(t) (clamped
  *        outside the knot range, times strictly increasing) multiplying val;
  *        NULL (n_knots = 0) means g = 1.  Neumann loads are taken at t = n dt,
@@ -137,6 +140,45 @@ lbm_status lbm_create(const lbm_plate *plates, int32_t n_plates, lbm_storage sto
 lbm_status lbm_set_bc(lbm_ctx *ctx, int32_t plate, int32_t n, const int32_t *xy,
                       const uint8_t *kind, const double *val, const double *cell,
                       int32_t n_knots, const double *knots);
+
+/* Shapes bounding a body for lbm_exact_cells: an ellipse with centre (cx,
+ * cy), semi-axes a and b and the angle (radians) of its a axis to the x axis,
+ * in lattice units (node (i, j) sits at (i, j)).  LBM_SHAPE_HOLE removes its
+ * open interior from the body, LBM_SHAPE_BOUND its open exterior. */
+enum { LBM_SHAPE_HOLE = 0, LBM_SHAPE_BOUND = 1 };
+typedef struct {
+  double cx, cy, a, b, angle;
+  int32_t kind;
+  int32_t pad;
+} lbm_shape;
+
+/* Exact-geometry boundary cells (Sec. 3.1: the preprocessing computes cell
+ * volumes and surface measures at boundary lattice points by cutting the
+ * square cell of side dh around each point to the body's boundary; used by
+ * eq. acc_neumann).  Host computation only; needs no context or GPU.
+ * The body is the lattice rectangle [0, nx-1] x [0, ny-1] (an axis with
+ * periodic_* nonzero is not bounded) minus the shapes' removed sets, which
+ * must be pairwise disjoint; shapes are not wrapped across periodic axes.
+ * A node belongs to the body iff its position does (points on an ellipse
+ * belong to the body): build the plate's mask the same way.
+ * For each of the n nodes xy[2m], xy[2m+1] (any node of the lattice):
+ *   cell[5m..5m+4]  = V_C, l_E, l_N, l_W, l_S: area of the node's square
+ *                     inside the body (dh^2 units) and the length inside the
+ *                     body of each of its four sides (dh units); the layout
+ *                     of lbm_set_bc's cell table.  A side whose neighbour is
+ *                     not in the body can still have a length (the boundary
+ *                     passes beyond the square): the Neumann acceleration
+ *                     then takes that side's stress from the node itself.
+ *   ext_normal[2m..2m+1] (ext_normal may be NULL) = the integral of the
+ *                     outward unit normal over the body boundary inside the
+ *                     square, -(l_E - l_W, l_N - l_S) by closure; times -p it
+ *                     is the external force of a uniform pressure p.
+ * Outputs are caller-owned host arrays.  A node whose square lies outside
+ * the body gets V_C = 0.  Errors: LBM_E_INVAL for sizes, a node outside the
+ * lattice, a non-positive or non-finite semi-axis, an unknown kind. */
+lbm_status lbm_exact_cells(int32_t nx, int32_t ny, uint8_t periodic_x, uint8_t periodic_y,
+                           double dh, int32_t n_shapes, const lbm_shape *shapes, int32_t n,
+                           const int32_t *xy, double *cell, double *ext_normal);
 
 /* Advance every plate by n_steps time steps (Fig. 4: accelerations,
  * Newmark update, boundary reset, LBE with the second-row rule, and the

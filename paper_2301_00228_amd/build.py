@@ -7,7 +7,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = [os.path.join(CSRC, "lbm_kernels.hip"), os.path.join(CSRC, "lbm_host.cpp")]
+SOURCES = [os.path.join(CSRC, "lbm_kernels.hip"), os.path.join(CSRC, "lbm_host.cpp"),
+           os.path.join(CSRC, "lbm_geom.cpp")]
 HEADERS = [os.path.join(CSRC, "lbm_types.h"), os.path.join(CSRC, "lbm_kernels.h"),
            os.path.join(ROOT, "include", "lbm.h")]
 

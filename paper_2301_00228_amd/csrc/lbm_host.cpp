@@ -1534,7 +1534,12 @@ lbm_status lbm_set_bc(lbm_ctx *c, int32_t plate, int32_t n, const int32_t *xy, c
     if (kind[m] > 1) return fail(c, LBM_E_INVAL, "bad boundary kind");
     if (!std::isfinite(val[2 * m]) || !std::isfinite(val[2 * m + 1]))
       return fail(c, LBM_E_INVAL, "non-finite boundary value");
-    if (cell && !(cell[5 * m] > 0)) return fail(c, LBM_E_INVAL, "cell volume must be positive");
+    if (cell && !(cell[5 * m] > 0 && std::isfinite(cell[5 * m])))
+      return fail(c, LBM_E_INVAL, "cell volume must be positive");
+    if (cell)
+      for (int q = 1; q < 5; q++)
+        if (!(cell[5 * m + q] >= 0 && std::isfinite(cell[5 * m + q])))
+          return fail(c, LBM_E_INVAL, "cell side lengths must be finite and >= 0");
     const int64_t node = h.off + (int64_t)j * h.pitch + i;
     auto first = c->bnd.begin() + h.b0, last = c->bnd.begin() + h.b1;
     auto it = std::lower_bound(first, last, node,

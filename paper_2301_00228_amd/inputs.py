@@ -57,6 +57,10 @@ class Case:
     steps: int = 0
     nu: float = 0.3
     a0_phi: float = 0.0
+    # ellipses that carved the mask: (cx, cy, a, b, angle, kind), kind 0 =
+    # hole (interior removed), 1 = bound (exterior removed); a node is in the
+    # body iff its position is (points on an ellipse are)
+    shapes: list = field(default_factory=list)
 
     def in_body_nodes(self) -> int:
         return int(self.nx * self.ny if self.mask is None else int(np.count_nonzero(self.mask)))
@@ -152,6 +156,64 @@ def clamped_plate(n=1024, nu=0.3, a0_phi=0.9999, steps=5000, sync_every=50, sigm
                 steps=steps, nu=nu, a0_phi=a0_phi)
 
 
+SHAPE_HOLE, SHAPE_BOUND = 0, 1
+
+
+def shape_mask(nx, ny, shapes):
+    """Mask of the lattice nodes inside the body bounded by the shapes."""
+    y, x = np.mgrid[0:ny, 0:nx].astype(np.float64)
+    mask = np.ones((ny, nx), np.uint8)
+    for cx, cy, a, b, ang, kind in shapes:
+        ca, sa = np.cos(ang), np.sin(ang)
+        xr = ca * (x - cx) + sa * (y - cy)
+        yr = -sa * (x - cx) + ca * (y - cy)
+        r2 = (xr / a) ** 2 + (yr / b) ** 2
+        mask[(r2 < 1.0) if kind == SHAPE_HOLE else (r2 > 1.0)] = 0
+    return mask
+
+
+def boundary_nodes(mask, periodic=(False, False)):
+    """(n, 2) coordinates of the body nodes with a missing D2Q5 neighbour
+    (the lattice edge of a non-periodic axis counts as missing)."""
+    m = mask.astype(bool)
+    ny, nx = m.shape
+    miss = np.zeros_like(m)
+    for ax, per in ((1, periodic[0]), (0, periodic[1])):
+        for sh in (1, -1):
+            nb = np.roll(m, sh, axis=ax)
+            if not per:
+                idx = [slice(None)] * 2
+                idx[ax] = 0 if sh == 1 else -1
+                nb[tuple(idx)] = False
+            miss |= ~nb
+    j, i = np.nonzero(m & miss)
+    return np.stack([i, j], 1).astype(np.int32)
+
+
+def plate_with_ellipse_hole(nx=96, ny=80, hole=(47.3, 38.6, 15.0, 9.5, 0.5), nu=0.3, a0_phi=0.5,
+                            steps=300, sync_every=50, sigma=4.0, amp=1e-3, seed_index=5,
+                            clamped=(LEFT,)):
+    """Rectangular plate with one elliptic hole (cx, cy, a, b, angle), the
+    listed outer edges Dirichlet u* = 0, every other boundary node traction
+    free; one seeded pulse between the hole and the plate edges."""
+    rng = rng_for(seed_index)
+    shapes = [tuple(hole) + (SHAPE_HOLE,)]
+    mask = shape_mask(nx, ny, shapes)
+    for _ in range(1000):
+        cx, cy = rng.uniform(3 * sigma, nx - 1 - 3 * sigma), rng.uniform(3 * sigma, ny - 1 - 3 * sigma)
+        if mask[int(round(cy)), int(round(cx))]:
+            break
+    theta = rng.uniform(0, 2 * np.pi)
+    u0 = gaussian_pulse(nx, ny, cx, cy, sigma, amp, theta) * mask[None]
+    bc = dirichlet_edges_bc(nx, ny, list(clamped))
+    bcs = [bc] if bc is not None else []
+    _clear_dirichlet(u0, bcs)
+    return Case(name=f"ellipse_hole{nx}x{ny}", nx=nx, ny=ny, mask=mask, periodic=(False, False),
+                lam=lame_lambda(nu), mu=1.0, rho=1.0, dh=1.0, dt=time_step(nu, a0_phi),
+                sync_every=sync_every, u0=u0, v0=np.zeros_like(u0), e0=None, w0=None, bcs=bcs,
+                steps=steps, nu=nu, a0_phi=a0_phi, shapes=shapes)
+
+
 def hole_mask(n, radius, cx=None, cy=None):
     cx = (n - 1) / 2.0 if cx is None else cx
     cy = (n - 1) / 2.0 if cy is None else cy
@@ -178,7 +240,8 @@ def plate_with_hole(n=8192, radius=1024, nu=0.3, a0_phi=0.9999, steps=2000, sync
     return Case(name=f"hole{n}r{radius}", nx=n, ny=n, mask=mask, periodic=(False, False),
                 lam=lame_lambda(nu), mu=1.0, rho=1.0, dh=1.0, dt=time_step(nu, a0_phi),
                 sync_every=sync_every, u0=u0, v0=np.zeros_like(u0), e0=None, w0=None, bcs=bcs,
-                steps=steps, nu=nu, a0_phi=a0_phi)
+                steps=steps, nu=nu, a0_phi=a0_phi,
+                shapes=[(c, c, float(radius), float(radius), 0.0, SHAPE_HOLE)])
 
 
 def plate_batch(count=256, side_lo=64, side_hi=1024, nu_lo=0.1, nu_hi=0.45, a0_phi=0.9999,
@@ -214,8 +277,10 @@ def ellipse_holes_mask(nx, ny, area_frac, rng, a_lo=8.0, a_hi=64.0, clearance=4.
     """Random non-overlapping elliptic holes until their area reaches
     area_frac of the plate.  Semi-axes a ~ U[a_lo, a_hi], b ~ U[a/4, a],
     angle ~ U[0, pi); holes keep `clearance` nodes from each other and from
-    the plate edges (tested on bounding circles)."""
+    the plate edges (tested on bounding circles).  Returns the mask and the
+    holes as shapes (cx, cy, a, b, angle, SHAPE_HOLE)."""
     mask = np.ones((ny, nx), np.uint8)
+    shapes = []
     target = area_frac * nx * ny
     area = 0.0
     placed = []  # (cx, cy, R)
@@ -242,7 +307,8 @@ def ellipse_holes_mask(nx, ny, area_frac, rng, a_lo=8.0, a_hi=64.0, clearance=4.
         inside = (xr / a) ** 2 + (yr / b) ** 2 < 1.0
         mask[y0:y1, x0:x1][inside] = 0
         area += np.pi * a * b
-    return mask
+        shapes.append((cx, cy, a, b, ang, SHAPE_HOLE))
+    return mask, shapes
 
 
 def strip_with_holes(nx=65536, ny=2048, area_frac=0.05, nu=0.3, a0_phi=0.9999, steps=2000,
@@ -252,7 +318,7 @@ def strip_with_holes(nx=65536, ny=2048, area_frac=0.05, nu=0.3, a0_phi=0.9999, s
     plate), outer edges Dirichlet u* = 0 or free with probability 1/2,
     several seeded pulses."""
     rng = rng_for(seed_index, 1)
-    mask = ellipse_holes_mask(nx, ny, area_frac, rng, a_lo=a_lo, a_hi=a_hi)
+    mask, shapes = ellipse_holes_mask(nx, ny, area_frac, rng, a_lo=a_lo, a_hi=a_hi)
     edges = [e for e in (LEFT, RIGHT, BOTTOM, TOP) if rng.random() < 0.5]
     u0 = np.zeros((2, ny, nx))
     lo = 6 * sigma
@@ -270,7 +336,7 @@ def strip_with_holes(nx=65536, ny=2048, area_frac=0.05, nu=0.3, a0_phi=0.9999, s
     return Case(name=f"strip{nx}x{ny}", nx=nx, ny=ny, mask=mask, periodic=(False, False),
                 lam=lame_lambda(nu), mu=1.0, rho=1.0, dh=1.0, dt=time_step(nu, a0_phi),
                 sync_every=sync_every, u0=u0, v0=np.zeros_like(u0), e0=None, w0=None, bcs=bcs,
-                steps=steps, nu=nu, a0_phi=a0_phi)
+                steps=steps, nu=nu, a0_phi=a0_phi, shapes=shapes)
 
 
 def mixed_plate(nx, ny, rng, nu=0.3, a0_phi=0.9999, steps=2000, sync_every=50, sigma=32.0,

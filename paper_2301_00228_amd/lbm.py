@@ -25,7 +25,8 @@ BC_NEUMANN, BC_DIRICHLET = 0, 1
 # Every entry point declared in include/lbm.h.
 EXPORTS = ["lbm_create", "lbm_set_bc", "lbm_step", "lbm_fields", "lbm_fields_device", "lbm_info",
            "lbm_set_tiling", "lbm_autotune", "lbm_profile", "lbm_use_graphs", "lbm_destroy",
-           "lbm_last_error", "lbm_version"]
+           "lbm_last_error", "lbm_version", "lbm_exact_cells"]
+SHAPE_HOLE, SHAPE_BOUND = 0, 1
 
 
 class LbmError(RuntimeError):
@@ -65,6 +66,11 @@ class lbm_info_t(C.Structure):
 class lbm_tiling(C.Structure):
     _fields_ = [("lanes", C.c_int32), ("rows", C.c_int32), ("order", C.c_int32),
                 ("edge_rows", C.c_int32), ("align", C.c_int32), ("steps", C.c_int32)]
+
+
+class lbm_shape(C.Structure):
+    _fields_ = [("cx", C.c_double), ("cy", C.c_double), ("a", C.c_double), ("b", C.c_double),
+                ("angle", C.c_double), ("kind", C.c_int32), ("pad", C.c_int32)]
 
 
 _lib = None
@@ -107,6 +113,9 @@ def library():
     L.lbm_last_error.argtypes = [vp]
     L.lbm_version.restype = C.c_char_p
     L.lbm_version.argtypes = []
+    L.lbm_exact_cells.restype = C.c_int
+    L.lbm_exact_cells.argtypes = [C.c_int32, C.c_int32, C.c_uint8, C.c_uint8, C.c_double, C.c_int32,
+                                  C.POINTER(lbm_shape), C.c_int32, ip, dp, dp]
     _lib = L
     return L
 
@@ -122,6 +131,25 @@ def _f64(a, shape, what):
     if a.size != int(np.prod(shape)):
         raise LbmError(E_INVAL, f"{what}: expected {shape}, got {a.shape}")
     return a.reshape(shape)
+
+
+def exact_cells(nx, ny, shapes, xy, dh=1.0, periodic=(False, False)):
+    """lbm_exact_cells: cell table (n, 5) = V_C, l_E, l_N, l_W, l_S and the
+    external normal integrals (n, 2) of nodes xy (n, 2) of an nx x ny lattice
+    bounded by ellipses; shapes = [(cx, cy, a, b, angle, kind), ...]."""
+    L = library()
+    xy = np.ascontiguousarray(xy, dtype=np.int32).reshape(-1, 2)
+    n = xy.shape[0]
+    arr = (lbm_shape * max(len(shapes), 1))()
+    for q, (cx, cy, a, b, ang, kind) in enumerate(shapes):
+        arr[q] = lbm_shape(cx, cy, a, b, ang, kind, 0)
+    cell = np.zeros((n, 5), dtype=np.float64)
+    ext = np.zeros((n, 2), dtype=np.float64)
+    st = L.lbm_exact_cells(nx, ny, int(periodic[0]), int(periodic[1]), float(dh), len(shapes), arr, n,
+                           xy.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(cell), _dptr(ext))
+    if st != OK:
+        raise LbmError(st, "lbm_exact_cells rejected its arguments")
+    return cell, ext
 
 
 def default_stream():

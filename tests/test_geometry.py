@@ -1,0 +1,189 @@
+"""Exact-geometry boundary cells (Sec. 3.1: the square cell of side dh around
+a boundary lattice point, cut to the body's boundary; eq. acc_neumann uses
+its volume and side lengths).
+
+The oracle's quadrature is pinned to closed forms and to the exact area of
+the body; the library's ``lbm_exact_cells`` (host code, no GPU) is then held
+to the oracle."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import geometry as G
+from paper_2301_00228_amd import inputs as I
+from paper_2301_00228_amd import lbm
+
+HOLE, BOUND = G.HOLE, G.BOUND
+
+
+def all_nodes(nx, ny):
+    return np.array([(i, j) for j in range(ny) for i in range(nx)], dtype=np.int32)
+
+
+# ------------------------------------------------------------ oracle pins
+
+def test_quarter_disc_at_a_square_corner():
+    # a circle of radius r centred on the north-east corner of node (10, 10)'s
+    # square removes a quarter disc from it and r from its E and N sides
+    for r in (0.1, 0.3, 0.5):
+        sh = [(10.5, 10.5, r, r, 0.0, HOLE)]
+        V, lE, lN, lW, lS = G.cell_of(10, 10, 32, 32, sh)
+        assert V == pytest.approx(1 - math.pi * r * r / 4, abs=1e-13)
+        assert (lE, lN, lW, lS) == pytest.approx((1 - r, 1 - r, 1, 1), abs=1e-14)
+        # and the same quarter from the square of node (11, 11) (S, W sides)
+        V, lE, lN, lW, lS = G.cell_of(11, 11, 32, 32, sh)
+        assert V == pytest.approx(1 - math.pi * r * r / 4, abs=1e-13)
+        assert (lE, lN, lW, lS) == pytest.approx((1, 1, 1 - r, 1 - r), abs=1e-14)
+
+
+def test_small_ellipse_inside_one_square():
+    sh = [(7.1, 5.05, 0.3, 0.12, 0.7, HOLE)]
+    V, lE, lN, lW, lS = G.cell_of(7, 5, 20, 20, sh)
+    assert V == pytest.approx(1 - math.pi * 0.3 * 0.12, abs=1e-13)
+    assert (lE, lN, lW, lS) == (1, 1, 1, 1)
+
+
+def test_large_circle_is_locally_a_straight_cut():
+    # a circle of radius 1e4 whose rim passes x = i + 0.2 at the node's row:
+    # within the square the rim departs from that line by at most
+    # 0.5^2 / (2 R) = 1.25e-5
+    R = 1e4
+    sh = [(10.2 + R, 12.0, R, R, 0.0, HOLE)]
+    V, lE, lN, lW, lS = G.cell_of(10, 12, 30, 30, sh)
+    assert V == pytest.approx(0.7, abs=1.3e-5)
+    assert (lE, lN, lW, lS) == pytest.approx((0.0, 0.7, 1.0, 0.7), abs=1.3e-5)
+
+
+def test_straight_edges_give_the_mask_rule():
+    # without shapes the cells of edge and corner nodes are the mask rule's
+    # half and quarter cells
+    nx, ny = 9, 7
+    assert G.cell_of(0, 3, nx, ny, []) == (0.5, 1.0, 0.5, 0.0, 0.5)
+    assert G.cell_of(8, 0, nx, ny, []) == (0.25, 0.0, 0.5, 0.5, 0.0)
+    assert G.cell_of(4, 3, nx, ny, []) == (1.0, 1.0, 1.0, 1.0, 1.0)
+    # periodic x: no cut on that axis
+    assert G.cell_of(0, 3, nx, ny, [], periodic=(True, False)) == (1.0, 1.0, 1.0, 1.0, 1.0)
+
+
+@pytest.mark.parametrize("shape", [(17.3, 14.1, 7.2, 4.1, 0.6, HOLE), (12.0, 10.4, 3.3, 3.3, 0.0, HOLE),
+                                   (20.2, 14.6, 12.3, 9.1, 2.2, BOUND)])
+def test_cells_tile_the_body(shape):
+    # the squares of all nodes tile the plane, so their parts in the body add
+    # up to the body's area: the rectangle [0, nx-1] x [0, ny-1] minus the
+    # ellipse (hole), or the ellipse itself (bound)
+    nx, ny = 40, 30
+    cx, cy, a, b, ang, kind = shape
+    c = G.cells(nx, ny, [shape], all_nodes(nx, ny))
+    exact = (nx - 1) * (ny - 1) - math.pi * a * b if kind == HOLE else math.pi * a * b
+    assert c[:, 0].sum() == pytest.approx(exact, abs=1e-9)
+
+
+def test_side_lengths_agree_between_neighbours():
+    # the E side of node (i, j) is the W side of node (i+1, j): the two
+    # cells measure the same segment
+    nx, ny = 30, 26
+    sh = [(14.4, 12.9, 8.3, 5.2, 1.1, HOLE)]
+    c = G.cells(nx, ny, sh, all_nodes(nx, ny)).reshape(ny, nx, 5)
+    assert np.allclose(c[:, :-1, 1], c[:, 1:, 3], atol=1e-14)
+    assert np.allclose(c[:-1, :, 2], c[1:, :, 4], atol=1e-14)
+
+
+def test_in_body_matches_the_input_masks():
+    nx, ny = 40, 30
+    sh = [(17.3, 14.1, 7.2, 4.1, 0.6, HOLE)]
+    m = I.shape_mask(nx, ny, sh)
+    ref = np.array([[G.in_body(i, j, nx, ny, sh) for i in range(nx)] for j in range(ny)])
+    assert np.array_equal(m.astype(bool), ref)
+
+
+# -------------------------------------------- the library against the oracle
+
+def _lib_or_skip():
+    try:
+        lbm.library()
+    except lbm.LbmError as e:
+        pytest.skip(str(e))
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_library_cells_match_the_oracle(seed):
+    _lib_or_skip()
+    rng = np.random.default_rng(seed)
+    nx, ny = 64, 52
+    shapes = [(rng.uniform(22, 42), rng.uniform(20, 32), rng.uniform(2.5, 14), rng.uniform(2.5, 14),
+               rng.uniform(0, math.pi), HOLE)]
+    if seed == 2:
+        shapes = [(31.7, 25.2, 24.0, 20.5, 0.4, BOUND), (30.1, 26.3, 6.0, 3.0, 1.0, HOLE)]
+    xy = all_nodes(nx, ny)
+    got, ext = lbm.exact_cells(nx, ny, shapes, xy, dh=0.5)
+    ref = G.cells(nx, ny, shapes, xy, dh=0.5)
+    assert np.abs(got - ref).max() <= 1e-12
+    # external normal integral: minus the square sides' (closure)
+    assert np.allclose(ext[:, 0], -(got[:, 1] - got[:, 3]), atol=0)
+    assert np.allclose(ext[:, 1], -(got[:, 2] - got[:, 4]), atol=0)
+
+
+def test_library_cells_reject_bad_arguments():
+    _lib_or_skip()
+    with pytest.raises(lbm.LbmError):
+        lbm.exact_cells(20, 20, [(5.0, 5.0, 0.0, 1.0, 0.0, HOLE)], [(1, 1)])
+    with pytest.raises(lbm.LbmError):
+        lbm.exact_cells(20, 20, [(5.0, 5.0, 1.0, 1.0, 0.0, 7)], [(1, 1)])
+    with pytest.raises(lbm.LbmError):
+        lbm.exact_cells(20, 20, [], [(20, 1)])
+
+
+# ------------------------------------ the oracle with exact cells (eq. acc_neumann)
+
+def uniform_stress_case(nx=48, ny=40, hole=(23.3, 19.6, 9.0, 6.0, 0.5), drop_outer_sides=False):
+    """A plate with an elliptic hole in a uniform strain state (linear u, at
+    rest) whose boundary nodes carry the traction of that stress state,
+    sigma n integrated over each exact cell's external boundary.  The state
+    is an equilibrium: it must not move."""
+    from paper_2301_00228_amd import inputs as I
+    case = I.plate_with_ellipse_hole(nx=nx, ny=ny, hole=hole, a0_phi=0.9999, clamped=(), steps=400,
+                                     sync_every=50)
+    grad = np.array([[1.0e-3, 3.0e-4], [-2.0e-4, -4.0e-4]])  # d u_a / d x_b
+    eps = 0.5 * (grad + grad.T)
+    sig = case.lam * np.trace(eps) * np.eye(2) + 2 * case.mu * eps
+    y, x = np.mgrid[0:ny, 0:nx].astype(np.float64)
+    u0 = np.stack([grad[0, 0] * x + grad[0, 1] * y, grad[1, 0] * x + grad[1, 1] * y])
+    case.u0 = u0 * case.mask[None]
+    case.v0 = np.zeros_like(case.u0)
+    xy = I.boundary_nodes(case.mask)
+    cell = G.cells(nx, ny, case.shapes, xy)
+    n_ext = np.stack([-(cell[:, 1] - cell[:, 3]), -(cell[:, 2] - cell[:, 4])], 1)
+    val = n_ext @ sig.T  # sigma n per node (sigma symmetric)
+    if drop_outer_sides:
+        # the plausible mistake: no flux through sides that face a missing
+        # neighbour
+        m = case.mask
+        for k, (i, j) in enumerate(xy):
+            for q, (di, dj) in zip((1, 2, 3, 4), ((1, 0), (0, 1), (-1, 0), (0, -1))):
+                ii, jj = i + di, j + dj
+                if not (0 <= ii < nx and 0 <= jj < ny and m[jj, ii]):
+                    cell[k, q] = 0.0
+    case.bcs = [I.BoundaryData(xy, np.zeros(len(xy), np.uint8), val, cell=cell)]
+    return case
+
+
+def test_oracle_keeps_a_uniform_stress_state_with_exact_cells():
+    from oracle.oracle import run_case
+    case = uniform_stress_case()
+    # the exact cells do have sides of nonzero length towards missing
+    # neighbours here (the ellipse passes beyond the squares)
+    cell = case.bcs[0].cell
+    xy = case.bcs[0].xy
+    m = case.mask
+    dangling = sum(1 for k, (i, j) in enumerate(xy) for q, (di, dj) in
+                   zip((1, 2, 3, 4), ((1, 0), (0, 1), (-1, 0), (0, -1)))
+                   if cell[k, q] > 0 and not (0 <= i + di < case.nx and 0 <= j + dj < case.ny
+                                               and m[j + dj, i + di]))
+    assert dangling > 10
+    f, p = run_case(case)
+    assert np.abs(f["u"] - case.u0).max() <= 1e-13
+    assert np.abs(f["v"]).max() <= 1e-13
+    # and without their flux the state does move
+    f2, _ = run_case(uniform_stress_case(drop_outer_sides=True))
+    assert np.abs(f2["u"] - case.u0).max() > 1e-6

@@ -108,6 +108,42 @@ def test_time_dependent_loads_and_cell_table():
     assert_parity(gpu_run(case), ref, what="loads")
 
 
+def exact_cell_case(steps=600):
+    """Plate with an elliptic hole, left edge clamped, exact-geometry cells on
+    every Neumann node (the oracle's cells) and a ramped uniform pressure
+    on the hole's rim (force -p times the rim normal integral of each cell)."""
+    from oracle import geometry as G
+    case = I.plate_with_ellipse_hole(nx=96, ny=80, hole=(47.3, 38.6, 15.0, 9.5, 0.5),
+                                     a0_phi=0.9999, steps=steps, sync_every=50, sigma=4.0)
+    xy = I.boundary_nodes(case.mask)
+    xy = xy[xy[:, 0] != 0]  # the clamped left edge keeps its Dirichlet data
+    cell = G.cells(case.nx, case.ny, case.shapes, xy)
+    n_ext = np.stack([-(cell[:, 1] - cell[:, 3]), -(cell[:, 2] - cell[:, 4])], 1)
+    rim = (xy[:, 0] > 0) & (xy[:, 0] < case.nx - 1) & (xy[:, 1] > 0) & (xy[:, 1] < case.ny - 1)
+    p = 2e-3
+    val = np.where(rim[:, None], -p * n_ext, 0.0)
+    case.bcs.append(I.BoundaryData(xy, np.zeros(len(xy), np.uint8), val, cell=cell,
+                                   knots=np.array([[0.0, 0.0], [300 * case.dt, 1.0]])))
+    return case
+
+
+def test_exact_geometry_cells_match_the_oracle():
+    case = exact_cell_case()
+    print("case", case.name, "exact cells", flush=True)
+    ref, _ = run_case(case)
+    assert_parity(gpu_run(case), ref, what="exact cells")
+    assert_parity(gpu_run(case, tiling=(64, 8, 0, 2, 0, 2)), ref, what="exact cells two-step")
+
+
+def test_uniform_stress_state_stays_at_rest_with_exact_cells():
+    import test_geometry as TG
+    case = TG.uniform_stress_case()
+    print("case uniform stress, exact cells", flush=True)
+    got = gpu_run(case)
+    assert np.abs(got["u"] - case.u0).max() <= 1e-13
+    assert np.abs(got["v"]).max() <= 1e-13
+
+
 def test_clamped_1024_short_run_full_size():
     case = I.clamped_plate(n=1024, steps=60)
     print("case", case.name, case.steps, flush=True)
