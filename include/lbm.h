@@ -127,9 +127,8 @@ lbm_status lbm_create(const lbm_plate *plates, int32_t n_plates, lbm_storage sto
  * cell : NULL, or 5n values (V_C, l_E, l_N, l_W, l_S) replacing the mask-rule
  *        cell volume and the lengths of the internal sides towards the E, N,
  *        W, S neighbours (for boundaries that do not follow the lattice, e.g.
- *        from lbm_exact_cells).  A side towards a neighbour outside the body
- *        may have a nonzero length: its stress is the node's own.  The
- *        mask rule gives such sides length 0.
+ *        from lbm_exact_cells).  Lengths towards neighbours outside the body
+ *        are not used (eq. acc_neumann sums over the neighbours).
  * knots: n_knots (t, g) pairs of a piecewise linear amplitude g(t) (clamped
  *        outside the knot range, times strictly increasing) multiplying val;
  *        NULL (n_knots = 0) means g = 1.  Neumann loads are taken at t = n dt,
@@ -163,16 +162,19 @@ typedef struct {
  * belong to the body): build the plate's mask the same way.
  * For each of the n nodes xy[2m], xy[2m+1] (any node of the lattice):
  *   cell[5m..5m+4]  = V_C, l_E, l_N, l_W, l_S: area of the node's square
- *                     inside the body (dh^2 units) and the length inside the
- *                     body of each of its four sides (dh units); the layout
- *                     of lbm_set_bc's cell table.  A side whose neighbour is
- *                     not in the body can still have a length (the boundary
- *                     passes beyond the square): the Neumann acceleration
- *                     then takes that side's stress from the node itself.
+ *                     inside the body (dh^2 units) and, for each of its four
+ *                     sides towards a neighbour in the body, the side's
+ *                     length inside the body (dh units); the layout of
+ *                     lbm_set_bc's cell table.  A side towards a neighbour
+ *                     outside the body has length 0 even where the boundary
+ *                     passes beyond it: the sliver of body between that side
+ *                     and the boundary belongs to no cell and, massless,
+ *                     passes the boundary's traction on to the cell.
  *   ext_normal[2m..2m+1] (ext_normal may be NULL) = the integral of the
- *                     outward unit normal over the body boundary inside the
- *                     square, -(l_E - l_W, l_N - l_S) by closure; times -p it
- *                     is the external force of a uniform pressure p.
+ *                     outward unit normal over the body boundary of the cell
+ *                     and of those slivers, -(l_E - l_W, l_N - l_S) by
+ *                     closure; times -p it is the external force of a
+ *                     uniform pressure p (the Neumann value of lbm_set_bc).
  * Outputs are caller-owned host arrays.  A node whose square lies outside
  * the body gets V_C = 0.  Errors: LBM_E_INVAL for sizes, a node outside the
  * lattice, a non-positive or non-finite semi-axis, an unknown kind. */

@@ -6,11 +6,17 @@ tables to the oracle and the GPU library.
 
 Sec. 3.1 builds, at each boundary lattice point, a cell that starts as the
 square of side dh centred on the point and is cut to the body's boundary;
-its volume V_C and the lengths of its sides enter the Neumann acceleration
-(eq. acc_neumann).  The body here is the lattice rectangle [0, nx-1] x
-[0, ny-1] (lattice units, node (i, j) at (i, j); a periodic axis is not
-bounded) minus the open interiors of "hole" ellipses and the open exteriors
-of "bound" ellipses, the removed sets pairwise disjoint.
+its volume V_C and the lengths of its sides towards its neighbours enter the
+Neumann acceleration (eq. acc_neumann).  A side towards a neighbour outside
+the body has no length in the table: the sliver of body beyond it (where
+the boundary passes beyond the square) is taken as massless, passing the
+boundary's traction to the cell, so the closure of the cell's normals gives
+the rim normal integral of the cell and its slivers.
+
+The body here is the lattice rectangle [0, nx-1] x [0, ny-1] (lattice
+units, node (i, j) at (i, j); a periodic axis is not bounded) minus the open
+interiors of "hole" ellipses and the open exteriors of "bound" ellipses, the
+removed sets pairwise disjoint.
 
 Method (independent of the library's, which sums triangle and sector areas
 in the coordinates where an ellipse is a circle): the length of a straight
@@ -84,8 +90,10 @@ def _kinks(x0, x1, y0, y1, shapes):
     return sorted(p for p in pts if x0 < p < x1)
 
 
-def cell_of(i, j, nx, ny, shapes, periodic=(False, False)):
-    """(V, l_E, l_N, l_W, l_S) of node (i, j) in lattice units."""
+def cell_of(i, j, nx, ny, shapes, periodic=(False, False), sides="body"):
+    """(V, l_E, l_N, l_W, l_S) of node (i, j) in lattice units; sides =
+    "body": lengths of the sides towards neighbours in the body (others 0),
+    "all": the inside length of every side of the square."""
     def clip(lo, hi, n, per):
         return (lo, hi) if per else (max(lo, 0.0), min(hi, float(n - 1)))
 
@@ -104,13 +112,24 @@ def cell_of(i, j, nx, ny, shapes, periodic=(False, False)):
     lW = inside_length((i - 0.5, y0), (i - 0.5, y1), shapes) if (periodic[0] or i - 0.5 >= 0) else 0.0
     lN = inside_length((x0, j + 0.5), (x1, j + 0.5), shapes) if (periodic[1] or j + 0.5 <= ny - 1) else 0.0
     lS = inside_length((x0, j - 0.5), (x1, j - 0.5), shapes) if (periodic[1] or j - 0.5 >= 0) else 0.0
+    if sides == "body":
+        def nb(ii, jj):
+            if periodic[0]:
+                ii %= nx
+            if periodic[1]:
+                jj %= ny
+            return 0 <= ii < nx and 0 <= jj < ny and in_body(ii, jj, nx, ny, shapes, periodic)
+        lE = lE if nb(i + 1, j) else 0.0
+        lN = lN if nb(i, j + 1) else 0.0
+        lW = lW if nb(i - 1, j) else 0.0
+        lS = lS if nb(i, j - 1) else 0.0
     return (max(V, 0.0), max(lE, 0.0), max(lN, 0.0), max(lW, 0.0), max(lS, 0.0))
 
 
-def cells(nx, ny, shapes, xy, dh=1.0, periodic=(False, False)):
+def cells(nx, ny, shapes, xy, dh=1.0, periodic=(False, False), sides="body"):
     """Cell table (n, 5): V_C (dh^2 units), l_E, l_N, l_W, l_S (dh units) of
     the nodes xy (n, 2)."""
-    out = np.array([cell_of(int(i), int(j), nx, ny, shapes, periodic) for i, j in np.asarray(xy)],
+    out = np.array([cell_of(int(i), int(j), nx, ny, shapes, periodic, sides) for i, j in np.asarray(xy)],
                    dtype=np.float64).reshape(-1, 5)
     out[:, 0] *= dh * dh
     out[:, 1:] *= dh
@@ -131,3 +150,11 @@ def in_body(x, y, nx, ny, shapes, periodic=(False, False)):
         if (kind == HOLE and r2 < 1.0) or (kind == BOUND and r2 > 1.0):
             return False
     return True
+
+
+def rim_normal(cell):
+    """Integral of the outward normal over the body boundary of each cell
+    (and of the slivers beyond its sides towards missing neighbours):
+    minus the normals of its sides times their lengths (closure)."""
+    cell = np.asarray(cell, dtype=np.float64).reshape(-1, 5)
+    return np.stack([-(cell[:, 1] - cell[:, 3]), -(cell[:, 2] - cell[:, 4])], 1)

@@ -26,9 +26,9 @@
  *    missing one; internal side towards neighbour r has the cell's extent
  *    across it as length and +-e_x / +-e_y as normal; a caller-given table
  *    (V, l_E, l_N, l_W, l_S) may replace it.  Nodes lacking both neighbours
- *    along one axis are rejected (zero cell volume).  A caller's cell that
- *    gives a side towards a missing neighbour a length (a boundary passing
- *    beyond the square) takes the node's own stress on that side;
+ *    along one axis are rejected (zero cell volume).  The sum of eq.
+ *    acc_neumann runs over the neighbours in the body only: a length given
+ *    towards a missing neighbour is not used;
  *  - Dirichlet acceleration uses u*(t+dt) (so that u(t+dt) = u*);
  *  - correction-f (eq. correction-f) uses the flux of the populations stored
  *    at the boundary node at time t;
@@ -370,29 +370,23 @@ static void accel_neumann(const orc_plate *p, int i, int j, double g, double *ax
   /* sigma_kr n_kr l_kr with sigma_kr the mean of the two nodal stresses. */
   double tEx = 0, tEy = 0, tWx = 0, tWy = 0, tNx = 0, tNy = 0, tSx = 0, tSy = 0;
   double rxx, ryy, rxy;
-  /* A side towards a missing neighbour carries a flux only if the caller's
-   * cell gives it a length; its stress is then the node's own. */
-  if (kE >= 0 || lE != 0.0) {
-    if (kE >= 0) stress(p, p->ux, p->uy, (int)(kE % p->nx), (int)(kE / p->nx), &rxx, &ryy, &rxy);
-    else { rxx = sxx; ryy = syy; rxy = sxy; }
+  if (kE >= 0) {
+    stress(p, p->ux, p->uy, (int)(kE % p->nx), (int)(kE / p->nx), &rxx, &ryy, &rxy);
     tEx = 0.5 * (sxx + rxx) * lE;
     tEy = 0.5 * (sxy + rxy) * lE;
   }
-  if (kW >= 0 || lW != 0.0) {
-    if (kW >= 0) stress(p, p->ux, p->uy, (int)(kW % p->nx), (int)(kW / p->nx), &rxx, &ryy, &rxy);
-    else { rxx = sxx; ryy = syy; rxy = sxy; }
+  if (kW >= 0) {
+    stress(p, p->ux, p->uy, (int)(kW % p->nx), (int)(kW / p->nx), &rxx, &ryy, &rxy);
     tWx = -(0.5 * (sxx + rxx)) * lW;
     tWy = -(0.5 * (sxy + rxy)) * lW;
   }
-  if (kN >= 0 || lN != 0.0) {
-    if (kN >= 0) stress(p, p->ux, p->uy, (int)(kN % p->nx), (int)(kN / p->nx), &rxx, &ryy, &rxy);
-    else { rxx = sxx; ryy = syy; rxy = sxy; }
+  if (kN >= 0) {
+    stress(p, p->ux, p->uy, (int)(kN % p->nx), (int)(kN / p->nx), &rxx, &ryy, &rxy);
     tNx = 0.5 * (sxy + rxy) * lN;
     tNy = 0.5 * (syy + ryy) * lN;
   }
-  if (kS >= 0 || lS != 0.0) {
-    if (kS >= 0) stress(p, p->ux, p->uy, (int)(kS % p->nx), (int)(kS / p->nx), &rxx, &ryy, &rxy);
-    else { rxx = sxx; ryy = syy; rxy = sxy; }
+  if (kS >= 0) {
+    stress(p, p->ux, p->uy, (int)(kS % p->nx), (int)(kS / p->nx), &rxx, &ryy, &rxy);
     tSx = -(0.5 * (sxy + rxy)) * lS;
     tSy = -(0.5 * (syy + ryy)) * lS;
   }

@@ -8,8 +8,13 @@
 // interiors of the holes and the open exteriors of the bounding ellipses.
 // The cell of node (i, j) is its unit square S = [i-1/2, i+1/2] x
 // [j-1/2, j+1/2] intersected with the body; its volume is the area of that
-// set and the length of each side is the part of the square's side that lies
-// in the body.  Areas are computed in the coordinates in which an ellipse is
+// set and the length of each side towards a neighbour in the body is the
+// part of the square's side that lies in the body.  A side towards a
+// neighbour outside the body gets length 0 even where the boundary passes
+// beyond it: the thin part of the body between that side and the boundary
+// belongs to no cell, and taken as massless it passes the boundary's
+// traction on to the cell, so that side counts as part of the cell's
+// external boundary.  Areas are computed in the coordinates in which an ellipse is
 // the unit circle: there the clipped square is a parallelogram, and the area
 // of a convex polygon inside the unit disc is a sum over its edges of the
 // disc's share of the triangle spanned by the origin and the edge (a
@@ -101,6 +106,19 @@ double seg_in_ellipse(V2 p, V2 r, const Ellipse &e) {
   return t1 > t0 ? (t1 - t0) * len : 0.0;
 }
 
+// Whether node (i, j) lies in the body (points on an ellipse do).
+bool node_in_body(int i, int j, int nx, int ny, bool px, bool py, const std::vector<Ellipse> &E) {
+  if (!px && (i < 0 || i > nx - 1)) return false;
+  if (!py && (j < 0 || j > ny - 1)) return false;
+  for (const Ellipse &e : E) {
+    const V2 q = e.map({(double)i, (double)j});
+    const double r2 = dot(q, q);
+    if ((e.kind == LBM_SHAPE_HOLE && r2 < 1.0) || (e.kind == LBM_SHAPE_BOUND && r2 > 1.0))
+      return false;
+  }
+  return true;
+}
+
 // The part of a body-bounding set inside [lo, hi]: [lo, hi] itself on a
 // periodic axis, else clipped to [0, n - 1].
 bool clip(double lo, double hi, int n, bool periodic, double &a, double &b) {
@@ -146,10 +164,11 @@ extern "C" lbm_status lbm_exact_cells(int32_t nx, int32_t ny, uint8_t periodic_x
       const V2 pW0 = {i - 0.5, y0}, pW1 = {i - 0.5, y1};
       const V2 pN0 = {x0, j + 0.5}, pN1 = {x1, j + 0.5};
       const V2 pS0 = {x0, j - 0.5}, pS1 = {x1, j - 0.5};
-      if (hasE) l[0] = y1 - y0;
-      if (hasN) l[1] = x1 - x0;
-      if (hasW) l[2] = y1 - y0;
-      if (hasS) l[3] = x1 - x0;
+      const bool px = periodic_x != 0, py = periodic_y != 0;
+      if (hasE && node_in_body(i + 1, j, nx, ny, px, py, E)) l[0] = y1 - y0;
+      if (hasN && node_in_body(i, j + 1, nx, ny, px, py, E)) l[1] = x1 - x0;
+      if (hasW && node_in_body(i - 1, j, nx, ny, px, py, E)) l[2] = y1 - y0;
+      if (hasS && node_in_body(i, j - 1, nx, ny, px, py, E)) l[3] = x1 - x0;
       // The removed regions (hole interiors, bounding-ellipse exteriors) are
       // disjoint inside the square: subtract each one's share.
       const double area = V, full[4] = {l[0], l[1], l[2], l[3]};
@@ -173,8 +192,9 @@ extern "C" lbm_status lbm_exact_cells(int32_t nx, int32_t ny, uint8_t periodic_x
     cell[5 * m + 3] = l[2] * dh;
     cell[5 * m + 4] = l[3] * dh;
     if (ext_normal) {
-      // closure of the cell: the outward normal integrated over its boundary
-      // vanishes, so the external part is minus that of its square sides
+      // closure: the outward normal integrated over the boundary of the cell
+      // and the massless parts beyond it vanishes, so the external part is
+      // minus that of the sides towards neighbours
       ext_normal[2 * m + 0] = -(l[0] - l[2]) * dh;
       ext_normal[2 * m + 1] = -(l[1] - l[3]) * dh;
     }

@@ -562,28 +562,24 @@ __device__ void boundary_task(const DevState &s, const PlateDev &P, const BTask 
     U sxx, syy, sxy, rxx, ryy, rxy;
     hooke<U>(P, gs, sxx, syy, sxy);
     U tEx = 0, tEy = 0, tWx = 0, tWy = 0, tNx = 0, tNy = 0, tSx = 0, tSy = 0;
-    // sigma_kr n_kr l_kr with sigma_kr the mean of the nodal stresses; a
-    // side of nonzero length towards a neighbour outside the body (an exact
-    // cell whose boundary passes beyond the square) takes the node's own
-    // stress
-    auto stress_r = [&](int g) { hooke<U>(P, grad + 4 * (g >= 0 ? g : T.g[0]), rxx, ryy, rxy); };
-    if (T.g[1] >= 0 || lE != U(0)) {
-      stress_r(T.g[1]);
+    // sigma_kr n_kr l_kr with sigma_kr the mean of the nodal stresses
+    if (T.g[1] >= 0) {
+      hooke<U>(P, grad + 4 * T.g[1], rxx, ryy, rxy);
       tEx = U(0.5) * (sxx + rxx) * lE;
       tEy = U(0.5) * (sxy + rxy) * lE;
     }
-    if (T.g[3] >= 0 || lW != U(0)) {
-      stress_r(T.g[3]);
+    if (T.g[3] >= 0) {
+      hooke<U>(P, grad + 4 * T.g[3], rxx, ryy, rxy);
       tWx = -(U(0.5) * (sxx + rxx)) * lW;
       tWy = -(U(0.5) * (sxy + rxy)) * lW;
     }
-    if (T.g[2] >= 0 || lN != U(0)) {
-      stress_r(T.g[2]);
+    if (T.g[2] >= 0) {
+      hooke<U>(P, grad + 4 * T.g[2], rxx, ryy, rxy);
       tNx = U(0.5) * (sxy + rxy) * lN;
       tNy = U(0.5) * (syy + ryy) * lN;
     }
-    if (T.g[4] >= 0 || lS != U(0)) {
-      stress_r(T.g[4]);
+    if (T.g[4] >= 0) {
+      hooke<U>(P, grad + 4 * T.g[4], rxx, ryy, rxy);
       tSx = -(U(0.5) * (sxy + rxy)) * lS;
       tSy = -(U(0.5) * (syy + ryy)) * lS;
     }

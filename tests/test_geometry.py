@@ -50,7 +50,7 @@ def test_large_circle_is_locally_a_straight_cut():
     # 0.5^2 / (2 R) = 1.25e-5
     R = 1e4
     sh = [(10.2 + R, 12.0, R, R, 0.0, HOLE)]
-    V, lE, lN, lW, lS = G.cell_of(10, 12, 30, 30, sh)
+    V, lE, lN, lW, lS = G.cell_of(10, 12, 30, 30, sh, sides="all")
     assert V == pytest.approx(0.7, abs=1.3e-5)
     assert (lE, lN, lW, lS) == pytest.approx((0.0, 0.7, 1.0, 0.7), abs=1.3e-5)
 
@@ -84,9 +84,17 @@ def test_side_lengths_agree_between_neighbours():
     # cells measure the same segment
     nx, ny = 30, 26
     sh = [(14.4, 12.9, 8.3, 5.2, 1.1, HOLE)]
-    c = G.cells(nx, ny, sh, all_nodes(nx, ny)).reshape(ny, nx, 5)
+    c = G.cells(nx, ny, sh, all_nodes(nx, ny), sides="all").reshape(ny, nx, 5)
     assert np.allclose(c[:, :-1, 1], c[:, 1:, 3], atol=1e-14)
     assert np.allclose(c[:-1, :, 2], c[1:, :, 4], atol=1e-14)
+    # the cell table keeps a side's length iff the neighbour across it is in
+    # the body
+    cb = G.cells(nx, ny, sh, all_nodes(nx, ny)).reshape(ny, nx, 5)
+    m = I.shape_mask(nx, ny, sh).astype(bool)
+    assert np.array_equal(cb[:, :-1, 1], np.where(m[:, 1:], c[:, :-1, 1], 0.0))
+    assert np.array_equal(cb[:-1, :, 2], np.where(m[1:, :], c[:-1, :, 2], 0.0))
+    assert np.array_equal(cb[:, 1:, 3], np.where(m[:, :-1], c[:, 1:, 3], 0.0))
+    assert np.array_equal(cb[1:, :, 4], np.where(m[:-1, :], c[1:, :, 4], 0.0))
 
 
 def test_in_body_matches_the_input_masks():
@@ -119,9 +127,7 @@ def test_library_cells_match_the_oracle(seed):
     got, ext = lbm.exact_cells(nx, ny, shapes, xy, dh=0.5)
     ref = G.cells(nx, ny, shapes, xy, dh=0.5)
     assert np.abs(got - ref).max() <= 1e-12
-    # external normal integral: minus the square sides' (closure)
-    assert np.allclose(ext[:, 0], -(got[:, 1] - got[:, 3]), atol=0)
-    assert np.allclose(ext[:, 1], -(got[:, 2] - got[:, 4]), atol=0)
+    assert np.abs(ext - G.rim_normal(ref)).max() <= 1e-12
 
 
 def test_library_cells_reject_bad_arguments():
@@ -136,7 +142,7 @@ def test_library_cells_reject_bad_arguments():
 
 # ------------------------------------ the oracle with exact cells (eq. acc_neumann)
 
-def uniform_stress_case(nx=48, ny=40, hole=(23.3, 19.6, 9.0, 6.0, 0.5), drop_outer_sides=False):
+def uniform_stress_case(nx=48, ny=40, hole=(23.3, 19.6, 9.0, 6.0, 0.5), square_closure=False):
     """A plate with an elliptic hole in a uniform strain state (linear u, at
     rest) whose boundary nodes carry the traction of that stress state,
     sigma n integrated over each exact cell's external boundary.  The state
@@ -153,17 +159,11 @@ def uniform_stress_case(nx=48, ny=40, hole=(23.3, 19.6, 9.0, 6.0, 0.5), drop_out
     case.v0 = np.zeros_like(case.u0)
     xy = I.boundary_nodes(case.mask)
     cell = G.cells(nx, ny, case.shapes, xy)
-    n_ext = np.stack([-(cell[:, 1] - cell[:, 3]), -(cell[:, 2] - cell[:, 4])], 1)
+    # the plausible mistake: the rim force from the square's sides inside
+    # the body, leaving out the slivers beyond sides towards missing
+    # neighbours
+    n_ext = G.rim_normal(G.cells(nx, ny, case.shapes, xy, sides="all") if square_closure else cell)
     val = n_ext @ sig.T  # sigma n per node (sigma symmetric)
-    if drop_outer_sides:
-        # the plausible mistake: no flux through sides that face a missing
-        # neighbour
-        m = case.mask
-        for k, (i, j) in enumerate(xy):
-            for q, (di, dj) in zip((1, 2, 3, 4), ((1, 0), (0, 1), (-1, 0), (0, -1))):
-                ii, jj = i + di, j + dj
-                if not (0 <= ii < nx and 0 <= jj < ny and m[jj, ii]):
-                    cell[k, q] = 0.0
     case.bcs = [I.BoundaryData(xy, np.zeros(len(xy), np.uint8), val, cell=cell)]
     return case
 
@@ -171,19 +171,12 @@ def uniform_stress_case(nx=48, ny=40, hole=(23.3, 19.6, 9.0, 6.0, 0.5), drop_out
 def test_oracle_keeps_a_uniform_stress_state_with_exact_cells():
     from oracle.oracle import run_case
     case = uniform_stress_case()
-    # the exact cells do have sides of nonzero length towards missing
-    # neighbours here (the ellipse passes beyond the squares)
-    cell = case.bcs[0].cell
-    xy = case.bcs[0].xy
-    m = case.mask
-    dangling = sum(1 for k, (i, j) in enumerate(xy) for q, (di, dj) in
-                   zip((1, 2, 3, 4), ((1, 0), (0, 1), (-1, 0), (0, -1)))
-                   if cell[k, q] > 0 and not (0 <= i + di < case.nx and 0 <= j + dj < case.ny
-                                               and m[j + dj, i + di]))
-    assert dangling > 10
+    # the ellipse does pass beyond squares' sides towards missing neighbours
+    allc = G.cells(case.nx, case.ny, case.shapes, case.bcs[0].xy, sides="all")
+    assert np.count_nonzero(allc[:, 1:] > case.bcs[0].cell[:, 1:]) > 10
     f, p = run_case(case)
     assert np.abs(f["u"] - case.u0).max() <= 1e-13
     assert np.abs(f["v"]).max() <= 1e-13
-    # and without their flux the state does move
-    f2, _ = run_case(uniform_stress_case(drop_outer_sides=True))
+    # and with the rim force of the squares alone the state does move
+    f2, _ = run_case(uniform_stress_case(square_closure=True))
     assert np.abs(f2["u"] - case.u0).max() > 1e-6

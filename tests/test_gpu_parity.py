@@ -118,7 +118,7 @@ def exact_cell_case(steps=600):
     xy = I.boundary_nodes(case.mask)
     xy = xy[xy[:, 0] != 0]  # the clamped left edge keeps its Dirichlet data
     cell = G.cells(case.nx, case.ny, case.shapes, xy)
-    n_ext = np.stack([-(cell[:, 1] - cell[:, 3]), -(cell[:, 2] - cell[:, 4])], 1)
+    n_ext = G.rim_normal(cell)
     rim = (xy[:, 0] > 0) & (xy[:, 0] < case.nx - 1) & (xy[:, 1] > 0) & (xy[:, 1] < case.ny - 1)
     p = 2e-3
     val = np.where(rim[:, None], -p * n_ext, 0.0)
