@@ -202,6 +202,16 @@ lbm_status lbm_fields(lbm_ctx *ctx, int32_t plate, double *e, double *omega, dou
 lbm_status lbm_fields_device(lbm_ctx *ctx, int32_t plate, double *e, double *omega, double *u,
                              double *v);
 
+/* Consistency error of Sec. 4 (tension example, the error measure e(x, t)):
+ * for each body node of one plate the 2-norm of (omega - (curl u).e_z,
+ * e - div u), where omega and e are the sums of the rotation and dilatation
+ * populations and the derivatives of u are the finite differences the method
+ * uses at that node (the ones of the synchronization, Sec. 3.2); 0 outside
+ * the body.  err: caller-owned host array of nx*ny doubles, x fastest.
+ * Synchronizes the stream.  Errors: LBM_E_INVAL (bad plate, NULL err),
+ * LBM_E_NOMEM, LBM_E_DEVICE, LBM_E_NONFINITE as for lbm_fields. */
+lbm_status lbm_consistency_error(lbm_ctx *ctx, int32_t plate, double *err);
+
 /* Summary of a context.  Filled by lbm_info. */
 typedef struct {
   int64_t nodes_in_body;      /* body nodes over all plates (lattice updates per step)       */

@@ -1623,6 +1623,8 @@ lbm_status lbm_fields(lbm_ctx *c, int32_t plate, double *e, double *w, double *u
   if (need > c->scratch_bytes) {
     double *p = (double *)dev_alloc(c, need);
     if (!p) return fail(c, LBM_E_NOMEM, "field scratch allocation failed");
+    // (every earlier use of the old scratch ended with a stream synchronize)
+    if (c->d_scratch) dev_free(c, c->d_scratch);
     c->d_scratch = p;
     c->scratch_bytes = need;
   }
@@ -1638,6 +1640,27 @@ lbm_status lbm_fields(lbm_ctx *c, int32_t plate, double *e, double *w, double *u
   int flag = 0;
   HIP_TRY(c, hipMemcpy(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost), "copy flag");
   if (flag) c->nonfinite = true;
+  return check_flag(c, true);
+}
+
+lbm_status lbm_consistency_error(lbm_ctx *c, int32_t plate, double *err) {
+  if (!c || !err) return LBM_E_INVAL;
+  if (plate < 0 || plate >= (int)c->ph.size()) return fail(c, LBM_E_INVAL, "bad plate index");
+  const PlateHost &h = c->ph[plate];
+  const size_t n = (size_t)h.nx * h.ny;
+  const size_t need = n * sizeof(double);
+  if (need > c->scratch_bytes) {
+    double *p = (double *)dev_alloc(c, need);
+    if (!p) return fail(c, LBM_E_NOMEM, "field scratch allocation failed");
+    // (every earlier use of the old scratch ended with a stream synchronize)
+    if (c->d_scratch) dev_free(c, c->d_scratch);
+    c->d_scratch = p;
+    c->scratch_bytes = need;
+  }
+  HIP_TRY(c, launch_cons_err(c->storage, c->ds, plate, (int64_t)n, c->cur, c->d_scratch, c->stream),
+          "consistency error kernel");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "synchronize");
+  HIP_TRY(c, hipMemcpy(err, c->d_scratch, need, hipMemcpyDeviceToHost), "copy error");
   return check_flag(c, true);
 }
 

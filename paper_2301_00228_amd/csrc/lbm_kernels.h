@@ -28,5 +28,7 @@ hipError_t launch_init(int storage, const DevState &s, int plate, int64_t nodes,
 // Dense FP64 fields of one plate from buffers b (any output may be null).
 hipError_t launch_fields(int storage, const DevState &s, int plate, int64_t nodes, int b,
                          double *e, double *w, double *u, double *v, hipStream_t stream);
+hipError_t launch_cons_err(int storage, const DevState &s, int plate, int64_t nodes, int b,
+                           double *err, hipStream_t stream);
 
 }  // namespace lbm

@@ -1324,6 +1324,32 @@ __global__ void k_fields(DevState s, int plate, int b, double *e, double *w, dou
   }
 }
 
+// Consistency error of Sec. 4 (tension example): per body node the 2-norm
+// of (omega - (curl u).e_z, e - div u), the fields being the sums of the
+// populations and the derivatives of u the finite differences the method
+// uses at that node; 0 outside the body.
+template <int ST>
+__global__ void k_cons_err(DevState s, int plate, int b, double *err) {
+  using CD = typename CodecOf<ST>::type;
+  using U = typename CD::U;
+  const PlateDev P = s.plates[plate];
+  const int64_t n = (int64_t)P.nx * P.ny;
+  for (int64_t d = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; d < n;
+       d += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(d % P.nx), j = (int)(d / P.nx);
+    const int64_t k = node_of(P, i, j);
+    if (!(s.cls[k] & CL_IN)) {
+      err[d] = 0.0;
+      continue;
+    }
+    U dv, cu;
+    div_curl<U>(s, b, P, i, j, dv, cu);
+    const double d1 = CD::field(s, b, 1, k, P) - (double)cu;
+    const double d0 = CD::field(s, b, 0, k, P) - (double)dv;
+    err[d] = sqrt(d1 * d1 + d0 * d0);
+  }
+}
+
 // --------------------------------------------------------------- launchers
 
 template <int ST, bool TWO>
@@ -1431,6 +1457,16 @@ hipError_t launch_fields(int st, const DevState &s, int plate, int64_t nodes, in
   if (blocks < 1) blocks = 1;
   LBM_DISPATCH(st, hipLaunchKernelGGL((k_fields<ST>), dim3((unsigned)blocks), dim3(256), 0,
                                       stream, s, plate, b, e, w, u, v));
+  return hipGetLastError();
+}
+
+hipError_t launch_cons_err(int st, const DevState &s, int plate, int64_t nodes, int b, double *err,
+                           hipStream_t stream) {
+  int64_t blocks = (nodes + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  LBM_DISPATCH(st, hipLaunchKernelGGL((k_cons_err<ST>), dim3((unsigned)blocks), dim3(256), 0,
+                                      stream, s, plate, b, err));
   return hipGetLastError();
 }
 

@@ -25,7 +25,7 @@ BC_NEUMANN, BC_DIRICHLET = 0, 1
 # Every entry point declared in include/lbm.h.
 EXPORTS = ["lbm_create", "lbm_set_bc", "lbm_step", "lbm_fields", "lbm_fields_device", "lbm_info",
            "lbm_set_tiling", "lbm_autotune", "lbm_profile", "lbm_use_graphs", "lbm_destroy",
-           "lbm_last_error", "lbm_version", "lbm_exact_cells"]
+           "lbm_last_error", "lbm_version", "lbm_exact_cells", "lbm_consistency_error"]
 SHAPE_HOLE, SHAPE_BOUND = 0, 1
 
 
@@ -113,6 +113,8 @@ def library():
     L.lbm_last_error.argtypes = [vp]
     L.lbm_version.restype = C.c_char_p
     L.lbm_version.argtypes = []
+    L.lbm_consistency_error.restype = C.c_int
+    L.lbm_consistency_error.argtypes = [vp, C.c_int32, dp]
     L.lbm_exact_cells.restype = C.c_int
     L.lbm_exact_cells.argtypes = [C.c_int32, C.c_int32, C.c_uint8, C.c_uint8, C.c_double, C.c_int32,
                                   C.POINTER(lbm_shape), C.c_int32, ip, dp, dp]
@@ -277,6 +279,13 @@ class Context:
                                          _dptr(v)))
         out = {"e": e, "omega": w, "u": u, "v": v}
         return {k: out[k] for k in want}
+
+    def consistency_error(self, plate=0):
+        """lbm_consistency_error: (ny, nx) array of the consistency error."""
+        nx, ny = self.shapes[plate]
+        err = np.zeros((ny, nx))
+        self._check(library().lbm_consistency_error(self._h, int(plate), _dptr(err)))
+        return err
 
     def fields_device(self, plate, e=None, omega=None, u=None, v=None):
         """Write fields into caller device buffers (torch float64 tensors or raw ints)."""

@@ -144,6 +144,45 @@ def test_uniform_stress_state_stays_at_rest_with_exact_cells():
     assert np.abs(got["v"]).max() <= 1e-13
 
 
+def test_consistency_error_matches_the_oracle():
+    """The consistency error map (Sec. 4) on a plate with a hole, between
+    synchronizations and right after one."""
+    case = I.plate_with_hole(n=96, radius=14, sigma=4.0, steps=0, sync_every=50)
+    p = OraclePlate(case.nx, case.ny, mask=case.mask, periodic=case.periodic, lam=case.lam,
+                    mu=case.mu, rho=case.rho, dh=case.dh, dt=case.dt, sync_every=case.sync_every,
+                    u0=case.u0, v0=case.v0)
+    for bc in case.bcs:
+        p.set_bc(bc.xy, bc.kind, bc.val, cell=bc.cell, knots=bc.knots)
+    with lbm.context_for(case, "f64") as ctx:
+        for n in (37, 13):  # steps 37 and 50 (a synchronization)
+            p.step(n)
+            ctx.step(n)
+            ref, got = p.cons_err(), ctx.consistency_error(0)
+            scale = np.abs(p.fields()["e"]).max()
+            print("cons_err", n, f"max {ref.max():.3e}", f"diff {np.abs(got - ref).max():.3e}",
+                  flush=True)
+            assert np.abs(got - ref).max() <= 1e-12 * scale
+    assert ref.max() <= 1e-12 * scale  # right after a synchronization
+
+
+@pytest.mark.parametrize("kind,sync", [("tension", 0), ("shear", 50), ("hole", 50)])
+def test_paper_example_setups_match_the_oracle(kind, sync):
+    """The Sec. 4 examples (ramped tension, growing shear with a clamped
+    edge, tension with a hole and exact cells on its rim) at L = 24."""
+    from oracle import geometry as G
+    from paper_2301_00228_amd import experiments as E
+    case = E.paper_case(kind, 24, sync, cells="exact" if kind == "hole" else "mask", t_end=0.3,
+                        cell_fn=lambda nx, ny, shapes, xy: G.cells(nx, ny, shapes, xy))
+    print("case", case.name, case.steps, flush=True)
+    ref, p = run_case(case)
+    with lbm.context_for(case, "f64") as ctx:
+        ctx.step(case.steps)
+        got = ctx.fields(0)
+        err = ctx.consistency_error(0)
+    assert_parity(got, ref, what=case.name)
+    assert np.abs(err - p.cons_err()).max() <= 1e-12 * np.abs(ref["e"]).max()
+
+
 def test_clamped_1024_short_run_full_size():
     case = I.clamped_plate(n=1024, steps=60)
     print("case", case.name, case.steps, flush=True)
