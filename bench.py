@@ -25,12 +25,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Interior tilings (lanes, rows, order, edge rows, alignment, steps per pass)
-# that the library's autotuner picks for this workload on MI355X, pinned so
-# that runs and the committed rocprofv3 summaries use the same launches
-# (--autotune tunes again instead).
-TUNED = {"f64": (64, 8, 0, 4, 16, 2), "f32": (128, 8, 0, 2, 0, 2), "f32dev": (128, 8, 0, 2, 0, 2),
-         "f16dev": (128, 8, 0, 2, 0, 2), "bf16dev": (128, 8, 0, 2, 0, 2)}
+# Interior tilings (lanes, rows, order, edge rows, alignment, steps per pass,
+# edge columns) that the library's autotuner picks for this workload on
+# MI355X, pinned so that runs and the committed rocprofv3 summaries use the
+# same launches (--autotune tunes again instead).
+TUNED = {"f64": (64, 8, 0, 4, 16, 2, 0), "f32": (128, 8, 0, 2, 0, 2, 0),
+         "f32dev": (128, 8, 0, 2, 0, 2, 0), "f16dev": (128, 8, 0, 2, 0, 2, 0),
+         "bf16dev": (128, 8, 0, 2, 0, 2, 0)}
 METRIC = "GLUPS + % HBM roofline, FP64 vs FP16/FP32-storage at ≤1e-3 rel L2"
 
 
@@ -94,9 +95,9 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=200)
     ap.add_argument("--storage", default="f64", help="storage of the headline run")
-    ap.add_argument("--tiling", default="", metavar="L,R,O,E,A,S",
+    ap.add_argument("--tiling", default="", metavar="L,R,O,E,A,S[,W]",
                     help="interior tiling of the headline storage (lanes, rows, order, edge "
-                         "rows, alignment, steps) instead of the pinned one")
+                         "rows, alignment, steps, edge columns) instead of the pinned one")
     ap.add_argument("--autotune", action="store_true",
                     help="run the library's autotuner instead of the pinned tilings")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
@@ -151,7 +152,7 @@ def main():
     info = ctx.info()
     f64_fields = ctx.fields(0)
     tile = [info["tile_lanes"], info["tile_rows"], info["tile_order"], info["tile_edge_rows"],
-            info["tile_align"], info["tile_steps"]]
+            info["tile_align"], info["tile_steps"], info["tile_edge_cols"]]
     # Dominant kernel: the interior launch with the most device time -- the
     # first launch of a two-step pair (two steps of the two-step tiles, one
     # of the others) or the single-step launch.  Device time per launch from

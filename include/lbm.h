@@ -230,6 +230,7 @@ typedef struct {
   int32_t tile_align;         /* column-strip alignment in nodes (0: equal-width strips)    */
   int32_t tile_steps;         /* time steps per pass over the tiles away from boundaries    */
   int32_t n_tiles;
+  int32_t tile_edge_cols;     /* width of the first and last column strip (0: no such strip) */
 } lbm_info_t;
 lbm_status lbm_info(const lbm_ctx *ctx, lbm_info_t *info);
 
@@ -253,19 +254,27 @@ lbm_status lbm_info(const lbm_ctx *ctx, lbm_info_t *info);
  *             or second-row node within two nodes of their area take two
  *             time steps per pass over HBM (the other tiles take the two
  *             steps in two launches); a tile then owns at most lanes-4
- *             columns.
+ *             columns;
+ *  edge_cols  0: the column strips of a plate are as `align` says; > 0: on
+ *             plates whose x axis is not periodic and that are wider than
+ *             2 edge_cols + 2, the first and the last strip are edge_cols
+ *             columns wide (the others as `align` says, between them), so
+ *             that with steps = 2 the strips next to a boundary column are
+ *             narrow and the rest of the plate takes two steps per pass.
  * Any tiling gives bitwise the same results.  May be changed between steps;
  * invalidates captured step graphs.  LBM_E_INVAL on values out of range
- * (align: 0..4096). */
+ * (align: 0..4096, edge_cols: 0..lanes-4). */
 typedef struct {
   int32_t lanes, rows, order, edge_rows, align, steps;
+  int32_t edge_cols;
 } lbm_tiling;
 lbm_status lbm_set_tiling(lbm_ctx *ctx, const lbm_tiling *tiling);
 
 /* Autotuner: time one step's interior launches (with the boundary work they
  * carry) on this context's plates for the tilings of a two-stage search
- * (steps x lanes x rows, then edge rows, alignment, rows and -- with several
- * plates -- packing order one at a time around the best, about 30 tilings),
+ * (steps x lanes x rows, then edge rows, edge columns, alignment, rows and --
+ * with several plates -- packing order one at a time around the best, about
+ * 30 tilings),
  * `steps` launches each, and keep the fastest.  Repeating those launches
  * leaves the state unchanged, except at step 0, at a synchronization step
  * and right after a two-step pair, where the autotuner first takes one real

@@ -37,7 +37,8 @@ struct PlateHost {
   int64_t b0 = 0, b1 = 0;    // range in the boundary list
   int nloads = 0;
   int64_t body = 0;
-  int ns = 0, sw = 1;  // interior tiles: column strips and their width
+  int ns = 0;          // interior tiles: column strips
+  std::vector<int> sx;  // first column of each strip, then nx (ns + 1 entries)
   // per strip: (first row, tile index) of its tiles, by increasing row
   std::vector<std::vector<std::pair<int, int>>> strips;
 };
@@ -124,7 +125,7 @@ struct lbm_ctx {
   std::vector<LoadTable> loads;
   std::vector<Tile> tiles;
   std::vector<Tile> etiles;  // the single-step tiles (second launch of a two-step pair)
-  int lanes = 128, rows = 32, order = 0, edge_rows = 0, align = 0, two = 0;
+  int lanes = 128, rows = 32, order = 0, edge_rows = 0, align = 0, two = 0, edge_cols = 0;
 
   std::vector<Buffer> bufs;
   DevState ds{};
@@ -525,6 +526,12 @@ bool build_boundary_tables(lbm_ctx *c, std::string &why) {
 // Row bands of height `rows` on a plate of ny rows; the band holding row j.
 int band_of(int j, int rows, int nb) { return std::min(j / rows, nb - 1); }
 
+// The column strip of plate h holding column x (0 <= x < nx).
+int strip_of(const PlateHost &h, int x) {
+  const int s = (int)(std::upper_bound(h.sx.begin(), h.sx.end(), x) - h.sx.begin()) - 1;
+  return std::min(std::max(s, 0), h.ns - 1);
+}
+
 // v within [lo - r, hi - 1 + r] (an owned range of a tile plus a ring of r
 // nodes), with wrap-around on a periodic axis of length n.
 bool in_ring_r(int v, int lo, int hi, int n, bool per, int r) {
@@ -545,7 +552,7 @@ void tiles_near(const lbm_ctx *c, int p, int i, int j, int r, F &&fn) {
       if (!h.px) continue;
       x = ((x % h.nx) + h.nx) % h.nx;
     }
-    const int st = std::min(x / h.sw, h.ns - 1);
+    const int st = strip_of(h, x);
     bool dup = false;
     for (int q = 0; q < ns; q++) dup = dup || strips[q] == st;
     if (!dup && ns < 8) strips[ns++] = st;
@@ -577,7 +584,7 @@ void tiles_near(const lbm_ctx *c, int p, int i, int j, int r, F &&fn) {
 // The tile of plate p that owns node (i, j).
 int tile_at(const lbm_ctx *c, int p, int i, int j) {
   const PlateHost &h = c->ph[(size_t)p];
-  const auto &col = h.strips[(size_t)std::min(i / h.sw, h.ns - 1)];
+  const auto &col = h.strips[(size_t)strip_of(h, i)];
   auto it = std::upper_bound(col.begin(), col.end(), std::make_pair(j, INT32_MAX));
   return std::prev(it)->second;
 }
@@ -633,7 +640,9 @@ void classify_two_step(lbm_ctx *c) {
 }
 
 // Interior tiles: per plate, column strips of at most lanes-2 columns (of
-// equal width, or of a multiple of align columns but the last) times row
+// equal width, or of a multiple of align columns but the last; with
+// edge_cols the first and last strip of a plate whose x axis is not periodic
+// are edge_cols wide and the others fill the columns between) times row
 // bands of `rows` rows; a band piece whose area or
 // halo ring holds boundary or second-row nodes (a tile with a prologue) is
 // cut into pieces of edge_rows rows, so that its boundary work plus its
@@ -658,13 +667,28 @@ void build_tiles(lbm_ctx *c) {
   std::vector<std::vector<uint8_t>> work(c->ph.size());
   for (size_t p = 0; p < c->ph.size(); p++) {
     PlateHost &h = c->ph[p];
-    if (c->align > 0 && own >= c->align) {
-      h.sw = own / c->align * c->align;
-      h.ns = (h.nx + h.sw - 1) / h.sw;
+    // strips over [a, b): aligned or equal widths of at most `own` columns
+    auto span = [&](int a, int b) {
+      const int n = b - a;
+      if (c->align > 0 && own >= c->align) {
+        const int w = own / c->align * c->align;
+        for (int x = a; x < b; x += w) h.sx.push_back(x);
+      } else {
+        const int k = (n + own - 1) / own, w = (n + k - 1) / k;
+        for (int x = a; x < b; x += w) h.sx.push_back(x);
+      }
+    };
+    h.sx.clear();
+    const int ec = c->edge_cols;
+    if (ec > 0 && !h.px && h.nx > 2 * ec + 2) {
+      h.sx.push_back(0);
+      span(ec, h.nx - ec);
+      h.sx.push_back(h.nx - ec);
     } else {
-      h.ns = (h.nx + own - 1) / own;
-      h.sw = (h.nx + h.ns - 1) / h.ns;
+      span(0, h.nx);
     }
+    h.ns = (int)h.sx.size();
+    h.sx.push_back(h.nx);
     const int nb = (h.ny + rows - 1) / rows;
     if (er < rows) work[p].assign((size_t)h.ns * nb, 0);
   }
@@ -672,7 +696,7 @@ void build_tiles(lbm_ctx *c) {
     auto mark = [&](int p, int i, int j) {
       const PlateHost &h = c->ph[(size_t)p];
       const int nb = (h.ny + rows - 1) / rows;
-      const int s0 = std::min(i / h.sw, h.ns - 1), b0 = band_of(j, rows, nb);
+      const int s0 = strip_of(h, i), b0 = band_of(j, rows, nb);
       for (int ds = -1; ds <= 1; ds++)
         for (int db = -1; db <= 1; db++) {
           int s = s0 + ds, b = b0 + db;
@@ -684,7 +708,7 @@ void build_tiles(lbm_ctx *c) {
             if (!h.py) continue;
             b = (b + nb) % nb;
           }
-          const int x0 = s * h.sw, x1 = std::min(h.nx, (s + 1) * h.sw);
+          const int x0 = h.sx[(size_t)s], x1 = h.sx[(size_t)s + 1];
           const int y0 = b * rows, y1 = std::min(h.ny, (b + 1) * rows);
           if (in_ring_r(i, x0, x1, h.nx, h.px, 1) && in_ring_r(j, y0, y1, h.ny, h.py, 1))
             work[(size_t)p][(size_t)s * nb + b] = 1;
@@ -695,11 +719,11 @@ void build_tiles(lbm_ctx *c) {
   }
   for (int p : plates) {
     PlateHost &h = c->ph[p];
-    const int ns = h.ns, w = h.sw;
+    const int ns = h.ns;
     const int nb = (h.ny + rows - 1) / rows;
     h.strips.assign((size_t)ns, {});
     auto add = [&](int s, int b) {
-      const int x0 = s * w, x1 = std::min(h.nx, (s + 1) * w);
+      const int x0 = h.sx[(size_t)s], x1 = h.sx[(size_t)s + 1];
       const int y0 = b * rows, y1 = std::min(h.ny, (b + 1) * rows);
       const int hgt = (er < rows && work[(size_t)p][(size_t)s * nb + b]) ? er : rows;
       for (int y = y0, piece = 0; y < y1; y += hgt, piece++) {
@@ -1486,6 +1510,7 @@ lbm_status lbm_create(const lbm_plate *plates, int32_t n_plates, lbm_storage sto
       c->rows = it->second.rows;
       c->order = it->second.order;
       c->edge_rows = it->second.edge_rows;
+      c->edge_cols = it->second.edge_cols;
       c->align = it->second.align;
       c->two = it->second.steps == 2 ? 1 : 0;
       if (c->two && ensure_third(c) != LBM_OK) c->two = 0;
@@ -1684,23 +1709,26 @@ lbm_status lbm_info(const lbm_ctx *c, lbm_info_t *info) {
   info->tile_align = c->align;
   info->tile_steps = c->two ? 2 : 1;
   info->n_tiles = (int32_t)c->tiles.size();
+  info->tile_edge_cols = c->edge_cols;
   return LBM_OK;
 }
 
 lbm_status lbm_set_tiling(lbm_ctx *c, const lbm_tiling *t) {
   if (!c || !t) return LBM_E_INVAL;
   const int32_t lanes = t->lanes, rows = t->rows, order = t->order, edge_rows = t->edge_rows,
-                align = t->align, steps = t->steps;
+                align = t->align, steps = t->steps, edge_cols = t->edge_cols;
   if ((lanes != 64 && lanes != 128 && lanes != 256) || rows < 1 || rows > 65536 || order < 0 ||
-      order > 2 || edge_rows < 0 || align < 0 || align > 4096 || steps < 0 || steps > 2)
+      order > 2 || edge_rows < 0 || align < 0 || align > 4096 || steps < 0 || steps > 2 ||
+      edge_cols < 0 || edge_cols > lanes - 4)
     return fail(c, LBM_E_INVAL,
                 "lanes must be 64, 128 or 256, rows >= 1, order 0..2, edge_rows >= 0, "
-                "align 0..4096, steps 0..2");
+                "align 0..4096, steps 0..2, edge_cols 0..lanes-4");
   HIP_TRY(c, hipStreamSynchronize(c->stream), "synchronize");
   c->lanes = lanes;
   c->rows = rows;
   c->order = order;
   c->edge_rows = edge_rows;
+  c->edge_cols = edge_cols;
   c->align = align;
   c->two = steps == 2 ? 1 : 0;
   if (c->two) {
@@ -1818,6 +1846,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
     c->rows = T.rows;
     c->order = T.order;
     c->edge_rows = T.edge_rows;
+    c->edge_cols = T.edge_cols;
     c->align = T.align;
     c->two = T.steps == 2 ? 1 : 0;
     build_tiles(c);
@@ -1846,7 +1875,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
     return 0.5 * (t1 + t2);
   };
   double best = 1e300;
-  lbm_tiling bt{c->lanes, c->rows, c->order, c->edge_rows, c->align, c->two ? 2 : 1};
+  lbm_tiling bt{c->lanes, c->rows, c->order, c->edge_rows, c->align, c->two ? 2 : 1, c->edge_cols};
   auto consider = [&](lbm_tiling T) {
     if (T.edge_rows >= T.rows) T.edge_rows = 0;
     const double per = eval(T);
@@ -1865,21 +1894,42 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
   {
     const lbm_tiling b0 = bt;
     for (int E : {0, 2, 4, 8})
-      if (E != b0.edge_rows) consider(lbm_tiling{b0.lanes, b0.rows, b0.order, E, b0.align, b0.steps});
+      if (E != b0.edge_rows) {
+        lbm_tiling T = b0;
+        T.edge_rows = E;
+        consider(T);
+      }
+  }
+  if (bt.steps == 2) {
+    const lbm_tiling b0 = bt;
+    for (int W : {0, 8, 16})
+      if (W != b0.edge_cols) {
+        lbm_tiling T = b0;
+        T.edge_cols = W;
+        consider(T);
+      }
   }
   {
-    const lbm_tiling b0 = bt;
-    consider(lbm_tiling{b0.lanes, b0.rows, b0.order, b0.edge_rows, b0.align ? 0 : 16, b0.steps});
+    lbm_tiling T = bt;
+    T.align = bt.align ? 0 : 16;
+    consider(T);
   }
   {
     const lbm_tiling b0 = bt;
     for (int R : {b0.rows / 2, b0.rows * 2})
-      if (R >= 4 && R <= 64) consider(lbm_tiling{b0.lanes, R, b0.order, b0.edge_rows, b0.align, b0.steps});
+      if (R >= 4 && R <= 64) {
+        lbm_tiling T = b0;
+        T.rows = R;
+        consider(T);
+      }
   }
   if (c->ph.size() > 1) {
     const lbm_tiling b0 = bt;
-    for (int O : {1, 2})
-      consider(lbm_tiling{b0.lanes, b0.rows, O, b0.edge_rows, b0.align, b0.steps});
+    for (int O : {1, 2}) {
+      lbm_tiling T = b0;
+      T.order = O;
+      consider(T);
+    }
   }
   // The second launch of a pair wrote the boundary nodes' u(t_{n+2}) where
   // the next step expects u(t_{n+1}): recompute that from u(t_n).
@@ -1896,6 +1946,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
   c->rows = bt.rows;
   c->order = bt.order;
   c->edge_rows = bt.edge_rows;
+  c->edge_cols = bt.edge_cols;
   c->align = bt.align;
   c->two = bt.steps == 2 ? 1 : 0;
   if (!c->two && !had_third) release_third(c);

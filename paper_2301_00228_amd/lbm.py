@@ -60,12 +60,14 @@ class lbm_info_t(C.Structure):
                 ("bytes_per_update", C.c_double), ("n_plates", C.c_int32),
                 ("storage", C.c_int32), ("tile_lanes", C.c_int32), ("tile_rows", C.c_int32),
                 ("tile_order", C.c_int32), ("tile_edge_rows", C.c_int32),
-                ("tile_align", C.c_int32), ("tile_steps", C.c_int32), ("n_tiles", C.c_int32)]
+                ("tile_align", C.c_int32), ("tile_steps", C.c_int32), ("n_tiles", C.c_int32),
+                ("tile_edge_cols", C.c_int32)]
 
 
 class lbm_tiling(C.Structure):
     _fields_ = [("lanes", C.c_int32), ("rows", C.c_int32), ("order", C.c_int32),
-                ("edge_rows", C.c_int32), ("align", C.c_int32), ("steps", C.c_int32)]
+                ("edge_rows", C.c_int32), ("align", C.c_int32), ("steps", C.c_int32),
+                ("edge_cols", C.c_int32)]
 
 
 class lbm_shape(C.Structure):
@@ -301,8 +303,9 @@ class Context:
         self._check(library().lbm_info(self._h, C.byref(i)))
         return {f: getattr(i, f) for f, _ in lbm_info_t._fields_}
 
-    def set_tiling(self, lanes, rows, order=0, edge_rows=0, align=0, steps=1):
-        t = lbm_tiling(int(lanes), int(rows), int(order), int(edge_rows), int(align), int(steps))
+    def set_tiling(self, lanes, rows, order=0, edge_rows=0, align=0, steps=1, edge_cols=0):
+        t = lbm_tiling(int(lanes), int(rows), int(order), int(edge_rows), int(align), int(steps),
+                       int(edge_cols))
         self._check(library().lbm_set_tiling(self._h, C.byref(t)))
 
     def autotune(self, steps=5):

@@ -55,7 +55,7 @@ def timed(cases, storage, steps, warmup, tune=True):
             ctx.autotune(3)
         i = ctx.info()
         print("tuned", [i["tile_lanes"], i["tile_rows"], i["tile_order"], i["tile_edge_rows"],
-                        i["tile_align"], i["tile_steps"]],
+                        i["tile_align"], i["tile_steps"], i["tile_edge_cols"]],
               f"in {time.perf_counter() - t1:.1f} s", file=sys.stderr, flush=True)
     ctx.step(warmup)
     torch.cuda.synchronize()
@@ -82,7 +82,8 @@ def timed(cases, storage, steps, warmup, tune=True):
            "two_step_nodes": info["nodes_two_step"],
            "bytes_per_lup": info["bytes_per_update"], "boundary_nodes": info["boundary_nodes"],
            "tile": [info["tile_lanes"], info["tile_rows"], info["tile_order"],
-                    info["tile_edge_rows"], info["tile_align"], info["tile_steps"]],
+                    info["tile_edge_rows"], info["tile_align"], info["tile_steps"],
+                    info["tile_edge_cols"]],
            "device_GB": info["device_bytes"] / 1e9, "setup_s": setup}
     return ctx, res
 

@@ -198,7 +198,9 @@ def test_tilings_graphs_and_eager_are_bitwise_identical():
                            ((64, 16, 2, 1), True), ((64, 8, 0, 2, 16), True),
                            ((128, 5, 1, 3, 32), False), ((256, 16, 0, 0, 48), True),
                            ((64, 8, 0, 2, 0, 2), True), ((128, 16, 1, 4, 16, 2), False),
-                           ((256, 5, 0, 0, 0, 2), True), ((64, 3, 0, 1, 0, 2), False)]:
+                           ((256, 5, 0, 0, 0, 2), True), ((64, 3, 0, 1, 0, 2), False),
+                           ((64, 8, 0, 2, 16, 2, 8), True), ((128, 7, 1, 3, 0, 2, 5), False),
+                           ((64, 8, 0, 4, 0, 1, 16), True)]:
         other = gpu_run(case, tiling=tiling, graphs=graphs)
         for k in FIELDS:
             assert np.array_equal(base[k], other[k]), (tiling, graphs, k)
@@ -217,6 +219,7 @@ def test_autotune_keeps_the_trajectory(first):
         assert info["tile_lanes"] in (64, 128, 256) and info["tile_order"] in (0, 1, 2)
         assert 1 <= info["tile_edge_rows"] <= info["tile_rows"]
         assert info["tile_align"] in (0, 16) and info["tile_steps"] in (1, 2)
+        assert info["tile_edge_cols"] in (0, 8, 16)
         done = info["steps_done"]
         assert done in (first, first + 1), done
         if first in (0, 50):
@@ -228,7 +231,8 @@ def test_autotune_keeps_the_trajectory(first):
             assert np.array_equal(a[k], b[k]), k
 
 
-TWO_STEP = [(64, 8, 0, 2, 0, 2), (128, 16, 0, 4, 16, 2), (256, 5, 1, 0, 0, 2)]
+TWO_STEP = [(64, 8, 0, 2, 0, 2), (128, 16, 0, 4, 16, 2), (256, 5, 1, 0, 0, 2), (64, 8, 0, 4, 16, 2, 8),
+            (128, 9, 2, 2, 0, 2, 4)]
 
 
 @pytest.mark.parametrize("tiling", TWO_STEP)
