@@ -1902,7 +1902,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
   }
   if (bt.steps == 2) {
     const lbm_tiling b0 = bt;
-    for (int W : {0, 8, 16})
+    for (int W : {0, 4, 8, 16})
       if (W != b0.edge_cols) {
         lbm_tiling T = b0;
         T.edge_cols = W;
