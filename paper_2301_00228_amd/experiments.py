@@ -221,9 +221,83 @@ def paper_run(kind, L, sync_every, cells="mask", storage="f64", samples=200, t_e
     return out
 
 
+def plane_wave_case(n, a0_phi, k=1, amp=1e-3, nu=0.25, periods=1.0):
+    """Periodic n x n square with the dilatational plane wave
+    u = (A sin(2 pi k x / n) cos(c_d kappa t), 0) at rest at t = 0 (fields
+    from the initial u by the method's finite differences).  Returns the
+    case and the exact u(t) as a function."""
+    lam = I.lame_lambda(nu)
+    cd = np.sqrt(lam + 2.0)
+    kappa = 2 * np.pi * k / n
+    dt = I.time_step(nu, a0_phi)
+    T = 2 * np.pi / (cd * kappa)
+    steps = int(round(periods * T / dt))
+    y, x = np.mgrid[0:n, 0:n].astype(np.float64)
+    u0 = np.stack([amp * np.sin(kappa * x), 0 * x])
+    case = I.Case(name=f"wave{n}", nx=n, ny=n, mask=None, periodic=(True, True), lam=lam, mu=1.0,
+                  rho=1.0, dh=1.0, dt=dt, sync_every=0, u0=u0, v0=np.zeros_like(u0), e0=None,
+                  w0=None, bcs=[], steps=steps, nu=nu, a0_phi=a0_phi)
+    exact = lambda t: np.stack([amp * np.sin(kappa * x) * np.cos(cd * kappa * t), 0 * x])
+    return case, exact
+
+
+def orders(sizes=(16, 32, 64, 128), a0s=(0.0, 0.5, 0.99), storage="f64"):
+    """Convergence of the interior scheme on a periodic plane wave: the
+    relative max error of u after one period against the exact solution, at
+    a fixed a0_phi (so dt scales with dh), for growing lattices (the wave is
+    the same on every lattice: its wavelength is the plate size)."""
+    out = []
+    for a0 in a0s:
+        errs = []
+        for n in sizes:
+            case, exact = plane_wave_case(n, a0)
+            with lbm.context_for(case, storage) as ctx:
+                ctx.step(case.steps)
+                u = ctx.fields(0, want=("u",))["u"]
+            ue = exact(case.steps * case.dt)
+            errs.append(float(np.abs(u - ue).max() / np.abs(ue).max()))
+        rates = [float(np.log2(errs[i] / errs[i + 1])) for i in range(len(errs) - 1)]
+        out.append({"experiment": "plane_wave_orders", "a0_phi": a0, "sizes": list(sizes),
+                    "rel_max_err_u": errs, "observed_orders": rates})
+    return out
+
+
+def stability_sweep(L=64, a0s=(0.9999, 0.999, 0.99, 0.9), syncs=(0, 10, 50, 200), t_end=2.0,
+                    storage="f64"):
+    """Blow-up time (units of L / c_s; None = stable to t_end) of the
+    tension example for each (a0_phi, synchronization period)."""
+    out = []
+    for a0 in a0s:
+        for l in syncs:
+            case = paper_case("tension", L, l, t_end=t_end)
+            nu = case.nu
+            case.dt = I.time_step(nu, a0)
+            case.a0_phi = a0
+            case.steps = int(round(t_end * L / case.dt))
+            every = max(1, case.steps // 40)
+            blew = None
+            with lbm.context_for(case, storage) as ctx:
+                done = 0
+                try:
+                    while done < case.steps:
+                        m = min(every, case.steps - done)
+                        ctx.step(m)
+                        done += m
+                        u = ctx.fields(0, want=("u",))["u"]
+                        if not np.isfinite(u).all() or np.abs(u).max() > 10.0 * L:
+                            blew = done * case.dt / L
+                            break
+                except lbm.LbmError:
+                    blew = done * case.dt / L
+            out.append({"experiment": "stability_tension", "L": L, "a0_phi": a0, "sync_every": l,
+                        "dt": case.dt, "steps": done, "blew_up_at": blew})
+            print(json.dumps(out[-1]), file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("experiment", choices=["disc", "paper"])
+    ap.add_argument("experiment", choices=["disc", "paper", "orders", "stability"])
     ap.add_argument("--L", type=int, default=128)
     ap.add_argument("--t-end", type=float, default=2.0)
     ap.add_argument("--radii", type=int, nargs="+", default=[8, 12, 16, 24, 32])
@@ -233,6 +307,14 @@ def main():
     import torch
     assert torch.cuda.is_available()
     torch.cuda.set_device(0)
+    if args.experiment == "orders":
+        for r in orders(storage=args.storage):
+            print(json.dumps(r), flush=True)
+        return
+    if args.experiment == "stability":
+        for r in stability_sweep(L=args.L, storage=args.storage, t_end=args.t_end):
+            print(json.dumps(r), flush=True)
+        return
     if args.experiment == "disc":
         for R in args.radii:
             for cells in ("mask", "exact"):
