@@ -90,6 +90,12 @@ typedef struct {
                                 NULL = 0                                                   */
   const double *e0, *w0;     /* optional initial dilatation / rotation (nx*ny); NULL =
                                 finite differences of u0 (Sec. 3, Fig. 4)                 */
+  int32_t integrator;        /* displacement update. 0: eq. integration as printed (u +=
+                                dt v + dt^2/2 a, v += dt a with a at t; first order in
+                                dt). 1: central difference (Newmark gamma = 1/2, second
+                                order): v is kept, and reported by lbm_fields, at t - dt/2
+                                (v0 is the velocity at t = 0); u is the same after the
+                                first step.  Other values: LBM_E_INVAL.                    */
 } lbm_plate;
 
 /* Optional device allocator (e.g. a framework's caching allocator).  alloc

@@ -33,7 +33,9 @@
  *  - correction-f (eq. correction-f) uses the flux of the populations stored
  *    at the boundary node at time t;
  *  - eq. LBE_mod: equilibrium of the averaged populations' own moments;
- *  - velocity update of eq. integration uses only the acceleration at t;
+ *  - velocity update of eq. integration uses only the acceleration at t
+ *    (orc_set_integrator(p, 1) switches to the central difference, Newmark
+ *    gamma = 1/2, for the variant study);
  *  - synchronization (Sec. 3.2) at the end of step m when m % l == 0, at
  *    every node, keeping the current flux;
  *  - Neumann load amplitude at t = n dt, Dirichlet at (n+1) dt, with t
@@ -68,6 +70,7 @@ struct orc_plate {
   double c, cd, cs;
   double a[2], a0[2];
   int sync_every;
+  int integrator; /* 0: eq. integration as printed; 1: central difference */
   int64_t n; /* completed steps */
   int started;
   uint8_t *in;  /* 1 = in body */
@@ -302,6 +305,12 @@ orc_plate *orc_create(int nx, int ny, const uint8_t *mask, int periodic_x, int p
   return p;
 }
 
+int orc_set_integrator(orc_plate *p, int integrator) {
+  if (!p || p->started || (integrator != 0 && integrator != 1)) return ORC_E_INVAL;
+  p->integrator = integrator;
+  return ORC_OK;
+}
+
 int orc_set_bc(orc_plate *p, int n, const int32_t *xy, const uint8_t *kind, const double *val,
                const double *cell, int n_knots, const double *knots) {
   if (!p || n < 0 || (n > 0 && (!xy || !kind || !val)) || n_knots < 0 || (n_knots > 0 && !knots))
@@ -435,8 +444,14 @@ static void one_step(orc_plate *p) {
         if (p->kind[k] == BC_DIRICHLET) {
           double g = load_amp(p, p->grp[k], t_next);
           double usx = g * p->bvx[k], usy = g * p->bvy[k];
-          p->ax[k] = 2.0 / (dt * dt) * (usx - p->ux[k]) - 2.0 / dt * p->vx[k];
-          p->ay[k] = 2.0 / (dt * dt) * (usy - p->uy[k]) - 2.0 / dt * p->vy[k];
+          if (p->integrator == 1 && p->n > 0) {
+            /* central difference: u(t+dt) = u + dt (v + dt a) with v at t - dt/2 */
+            p->ax[k] = (usx - p->ux[k]) / (dt * dt) - p->vx[k] / dt;
+            p->ay[k] = (usy - p->uy[k]) / (dt * dt) - p->vy[k] / dt;
+          } else {
+            p->ax[k] = 2.0 / (dt * dt) * (usx - p->ux[k]) - 2.0 / dt * p->vx[k];
+            p->ay[k] = 2.0 / (dt * dt) * (usy - p->uy[k]) - 2.0 / dt * p->vy[k];
+          }
         } else {
           double g = load_amp(p, p->grp[k], t_now);
           accel_neumann(p, i, j, g, &p->ax[k], &p->ay[k]);
@@ -454,10 +469,22 @@ static void one_step(orc_plate *p) {
       long k = (long)j * nx + i;
       if (!p->in[k]) continue;
       double ux = p->ux[k], uy = p->uy[k], vx = p->vx[k], vy = p->vy[k];
-      p->ux[k] = ux + dt * vx + dt * dt / 2.0 * p->ax[k];
-      p->uy[k] = uy + dt * vy + dt * dt / 2.0 * p->ay[k];
-      p->vx[k] = vx + dt * p->ax[k];
-      p->vy[k] = vy + dt * p->ay[k];
+      if (p->integrator == 1) {
+        /* central difference (Newmark gamma = 1/2, beta = 0) with the
+         * velocity at half steps: v(t+dt/2) = v(t-dt/2) + dt a(t), u(t+dt) =
+         * u(t) + dt v(t+dt/2); the first step starts from v(0):
+         * v(dt/2) = v(0) + dt/2 a(0) */
+        double h = p->n == 0 ? 0.5 * dt : dt;
+        p->vx[k] = vx + h * p->ax[k];
+        p->vy[k] = vy + h * p->ay[k];
+        p->ux[k] = ux + dt * p->vx[k];
+        p->uy[k] = uy + dt * p->vy[k];
+      } else {
+        p->ux[k] = ux + dt * vx + dt * dt / 2.0 * p->ax[k];
+        p->uy[k] = uy + dt * vy + dt * dt / 2.0 * p->ay[k];
+        p->vx[k] = vx + dt * p->ax[k];
+        p->vy[k] = vy + dt * p->ay[k];
+      }
     }
 
   /* 4. Boundary nodes: phi, psi from finite differences of u(t+dt)

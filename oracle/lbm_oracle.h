@@ -54,6 +54,9 @@ orc_plate *orc_create(int nx, int ny, const uint8_t *mask, int periodic_x, int p
  * the mask-derived cell.  knots: n_knots (t, g) pairs giving a piecewise
  * linear amplitude g(t) (clamped outside the knot range) that multiplies val;
  * NULL means g = 1.  Listing a node that is not a boundary node is an error. */
+/* Displacement update: 0 = eq. integration as printed (default), 1 = central
+ * difference with the velocity kept at half steps.  Before the first step. */
+int orc_set_integrator(orc_plate *p, int integrator);
 int orc_set_bc(orc_plate *p, int n, const int32_t *xy, const uint8_t *kind, const double *val,
                const double *cell, int n_knots, const double *knots);
 

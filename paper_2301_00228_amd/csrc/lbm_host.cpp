@@ -269,6 +269,8 @@ lbm_status plate_params(const lbm_plate &p, PlateDev &d) {
   d.rho_m = p.rho_m;
   d.lam = p.lambda;
   d.mu = p.mu;
+  if (p.integrator != 0 && p.integrator != 1) return LBM_E_INVAL;
+  d.integ = p.integrator;
   return LBM_OK;
 }
 

@@ -553,8 +553,14 @@ __device__ void boundary_task(const DevState &s, const PlateDev &P, const BTask 
   if (B.kind == LBM_BC_DIRICHLET) {
     const double g = load_amp(s, B.load, (double)(n + 1) * P.dt);
     const U usx = (U)(g * B.val[0]), usy = (U)(g * B.val[1]);
-    ax = U(2.0) / (dt * dt) * (usx - ux0) - U(2.0) / dt * vx0;
-    ay = U(2.0) / (dt * dt) * (usy - uy0) - U(2.0) / dt * vy0;
+    // the acceleration that makes u(t + dt) = u* under the update in use
+    if (P.integ && n != 0) {
+      ax = (usx - ux0) / (dt * dt) - vx0 / dt;
+      ay = (usy - uy0) / (dt * dt) - vy0 / dt;
+    } else {
+      ax = U(2.0) / (dt * dt) * (usx - ux0) - U(2.0) / dt * vx0;
+      ay = U(2.0) / (dt * dt) * (usy - uy0) - U(2.0) / dt * vy0;
+    }
   } else {
     const double g = load_amp(s, B.load, (double)n * P.dt);
     const U V = (U)B.cell[0], lE = (U)B.cell[1], lN = (U)B.cell[2], lW = (U)B.cell[3],
@@ -588,9 +594,8 @@ __device__ void boundary_task(const DevState &s, const PlateDev &P, const BTask 
     ax = (((tEx + tWx) + (tNx + tSx)) + Fx) / m;
     ay = (((tEy + tWy) + (tNy + tSy)) + Fy) / m;
   }
-  const U nux = ux0 + dt * vx0 + dt * dt / U(2.0) * ax;
-  const U nuy = uy0 + dt * vy0 + dt * dt / U(2.0) * ay;
-  const U nvx = vx0 + dt * ax, nvy = vy0 + dt * ay;
+  U nux, nuy, nvx, nvy;
+  newmark<U>(P, kick_of<U>(P, n == 0), ax, ay, ux0, uy0, vx0, vy0, nux, nuy, nvx, nvy);
   stg<U>(s.u[ub][0], k, nux);
   stg<U>(s.u[ub][1], k, nuy);
   stg<U>(s.v[ub][0], k, nvx);
@@ -739,17 +744,47 @@ __global__ void __launch_bounds__(kBoundaryThreads)
   }
 }
 
+// Displacement update of step n from u, v and the acceleration a at t_n,
+// as u += dt v + m a, v += k a with step coefficients (k, m):
+// integ 0, eq. integration as printed: k = dt, m = dt^2/2.
+// integ 1, central difference (Newmark gamma = 1/2, beta = 0) in
+// half-step form (v kept at t - dt/2: v += dt a, then u += dt v): k = dt,
+// m = dt^2; the first step (n = 0, v given at t = 0) takes half the velocity
+// increment, k = dt/2, m = dt^2/2, which gives the same u(t_1) as the
+// printed update.  The coefficients are uniform over a launch.
+template <class U>
+struct Kick {
+  U k, m;
+};
+template <class U>
+__device__ __forceinline__ Kick<U> kick_of(const PlateDev &P, bool first) {
+  const U dt = (U)P.dt;
+  if (P.integ) {
+    const U k = first ? U(0.5) * dt : dt;
+    return {k, dt * k};
+  }
+  return {dt, dt * dt / U(2.0)};
+}
+template <class U>
+__device__ __forceinline__ void newmark(const PlateDev &P, const Kick<U> &K, U ax, U ay, U ux,
+                                        U uy, U vx, U vy, U &nux, U &nuy, U &nvx, U &nvy) {
+  const U dt = (U)P.dt;
+  nux = ux + dt * vx + K.m * ax;
+  nuy = uy + dt * vy + K.m * ay;
+  nvx = vx + K.k * ax;
+  nvy = vy + K.k * ay;
+}
+
 // Interior acceleration of eq. navier, c_d^2 grad phi - c_s^2 curl(psi e_z)
 // with curl(psi e_z) = (d_y psi, -d_x psi) and central differences of the
 // neighbours' zeroth moments (E, W, N, S; field 0 = phi, 1 = psi), followed
-// by the Newmark update of eq. integration.  Shared by the interior kernel
+// by the displacement update with coefficients K.  Shared by the interior kernel
 // and the boundary kernel's recomputation so both give identical values.
 // Differences are scaled by the precomputed 1/(2 dh) (exact for dh = 1).
 template <class U>
-__device__ __forceinline__ void interior_update(const PlateDev &P, U e0, U w0, U n0, U s0, U e1,
-                                                U w1, U n1, U s1, U ux, U uy, U vx, U vy, U &nux,
-                                                U &nuy, U &nvx, U &nvy) {
-  const U dt = (U)P.dt;
+__device__ __forceinline__ void interior_update(const PlateDev &P, const Kick<U> &K, U e0, U w0,
+                                                U n0, U s0, U e1, U w1, U n1, U s1, U ux, U uy,
+                                                U vx, U vy, U &nux, U &nuy, U &nvx, U &nvy) {
   const U i2h = (U)P.inv_2h;
   const U cd2 = (U)P.cd2, cs2 = (U)P.cs2;
   const U dphix = (e0 - w0) * i2h;
@@ -758,10 +793,7 @@ __device__ __forceinline__ void interior_update(const PlateDev &P, U e0, U w0, U
   const U dpsiy = (n1 - s1) * i2h;
   const U ax = cd2 * dphix - cs2 * dpsiy;
   const U ay = cd2 * dphiy - cs2 * (-dpsix);
-  nux = ux + dt * vx + dt * dt / U(2.0) * ax;
-  nuy = uy + dt * vy + dt * dt / U(2.0) * ay;
-  nvx = vx + dt * ax;
-  nvy = vy + dt * ay;
+  newmark<U>(P, K, ax, ay, ux, uy, vx, vy, nux, nuy, nvx, nvy);
 }
 
 // -------------------------------------------------------- interior kernel
@@ -854,7 +886,8 @@ __device__ void march2(const DevState &s, const Tile &t, const StepBufs &sb,
   // neighbours (slot of row i), the behind row's and the ahead row's pops;
   // then the u, du/dt update from the neighbours' rho.
   auto finalize = [&](C(*ex)[X_N][TWL], int i, const C f0[2], const C fbe[2], const C fah[2],
-                      const C rbe[2], const C rah[2], const U uv[4], C f[2][5], U nu[4]) {
+                      const C rbe[2], const C rah[2], const U uv[4], C f[2][5], U nu[4],
+                      const Kick<U> &K) {
     const int sl = slot_of(i);
     // (the end lanes read a clamped neighbour; their results are not used)
     const int lw = lane > 0 ? lane - 1 : 0, le = lane < TWL - 1 ? lane + 1 : TWL - 1;
@@ -870,9 +903,12 @@ __device__ void march2(const DevState &s, const Tile &t, const StepBufs &sb,
     const C wr1 = ex[sl][X_RHO1][lw], er1 = ex[sl][X_RHO1][le];
     const C n0 = d > 0 ? rah[0] : rbe[0], s0 = d > 0 ? rbe[0] : rah[0];
     const C n1 = d > 0 ? rah[1] : rbe[1], s1 = d > 0 ? rbe[1] : rah[1];
-    interior_update<U>(P, (U)er0, (U)wr0, (U)n0, (U)s0, (U)er1, (U)wr1, (U)n1, (U)s1, uv[0], uv[1],
-                       uv[2], uv[3], nu[0], nu[1], nu[2], nu[3]);
+    interior_update<U>(P, K, (U)er0, (U)wr0, (U)n0, (U)s0, (U)er1, (U)wr1, (U)n1, (U)s1, uv[0],
+                       uv[1], uv[2], uv[3], nu[0], nu[1], nu[2], nu[3]);
   };
+  // displacement-update coefficients of steps n (the run's first if n = 0)
+  // and n + 1
+  const Kick<U> kickA = kick_of<U>(P, s.counter[sb.in] == 0ull), kickB = kick_of<U>(P, false);
 
   // t_n stage registers: row a-2 (rho, behind pop), row a-1 (rho, f0, behind pop)
   C a2_rho[2], a2_fb[2], a1_rho[2], a1_f0[2], a1_fb[2];
@@ -931,7 +967,7 @@ __device__ void march2(const DevState &s, const Tile &t, const StepBufs &sb,
     const C fa[2] = {ahead_pop(fs[0]), ahead_pop(fs[1])};
     C g[2][5];
     U nu[4];
-    finalize(exA, a - 1, a1_f0, a2_fb, fa, a2_rho, rho, uvA, g, nu);
+    finalize(exA, a - 1, a1_f0, a2_fb, fa, a2_rho, rho, uvA, g, nu, kickA);
     // u of row a (for the next row's step n) into the registers just used
     load_uv(a <= h ? a : h, uvA);
     const int ya = row_y(a - 1);
@@ -966,7 +1002,7 @@ __device__ void march2(const DevState &s, const Tile &t, const StepBufs &sb,
       const C fa1[2] = {ahead_pop(fs1[0]), ahead_pop(fs1[1])};
       C g2[2][5];
       U nu2[4];
-      finalize(exB, a - 2, b2_f0, b3_fb, fa1, b3_rho, rho1, uvB, g2, nu2);
+      finalize(exB, a - 2, b2_f0, b3_fb, fa1, b3_rho, rho1, uvB, g2, nu2, kickB);
       if (stepB) {
         const int64_t k = node_of(P, x, row_y(a - 2));
         stg<U>(s.u[sb.out2][0], k, nu2[0]);
@@ -1023,6 +1059,7 @@ __global__ void __launch_bounds__(TWL)
   }
   if (pro.enabled && t.chunk >= 0) prologue<CD>(s, pro, t.chunk, sb, (int)threadIdx.x, TWL);
   const PlateDev P = s.plates[t.plate];
+  const Kick<U> kick = kick_of<U>(P, s.counter[sb.in] == 0ull);
   const int lane = threadIdx.x;
   const int w = t.x1 - t.x0;
   int x = t.x0 - 1 + lane;
@@ -1171,8 +1208,8 @@ __global__ void __launch_bounds__(TWL)
       const C n0 = d > 0 ? nx_rho[0] : be_rho[0], s0 = d > 0 ? be_rho[0] : nx_rho[0];
       const C n1 = d > 0 ? nx_rho[1] : be_rho[1], s1 = d > 0 ? be_rho[1] : nx_rho[1];
       U nux, nuy, nvx, nvy;
-      interior_update<U>(P, (U)er0, (U)wr0, (U)n0, (U)s0, (U)er1, (U)wr1, (U)n1, (U)s1, uv0[0],
-                         uv0[1], uv0[2], uv0[3], nux, nuy, nvx, nvy);
+      interior_update<U>(P, kick, (U)er0, (U)wr0, (U)n0, (U)s0, (U)er1, (U)wr1, (U)n1, (U)s1,
+                         uv0[0], uv0[1], uv0[2], uv0[3], nux, nuy, nvx, nvy);
       stg<U>(s.u[un][0], kn, nux);
       stg<U>(s.u[un][1], kn, nuy);
       stg<U>(s.v[un][0], kn, nvx);

@@ -38,6 +38,8 @@ struct PlateDev {
   float af[2], a0f[2];   // the same in FP32
   float scale[2];        // 16-bit storage scale of the deviation moments
   float iscale[2];
+  int32_t integ;         // 0: v += dt a(t) (the paper's update); 1: central difference
+  int32_t pad;
 };
 
 // Interior-kernel tile: owned columns [x0, x1) and rows [y0, y1) of a plate;

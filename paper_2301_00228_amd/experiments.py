@@ -241,24 +241,34 @@ def plane_wave_case(n, a0_phi, k=1, amp=1e-3, nu=0.25, periods=1.0):
     return case, exact
 
 
-def orders(sizes=(16, 32, 64, 128), a0s=(0.0, 0.5, 0.99), storage="f64"):
+def orders(sizes=(16, 32, 64, 128), a0s=(0.0, 0.5, 0.99), storage="f64", integrators=(0, 1)):
     """Convergence of the interior scheme on a periodic plane wave: the
     relative max error of u after one period against the exact solution, at
     a fixed a0_phi (so dt scales with dh), for growing lattices (the wave is
-    the same on every lattice: its wavelength is the plate size)."""
+    the same on every lattice: its wavelength is the plate size), with the
+    paper's displacement update (integrator 0) and the central difference
+    (integrator 1)."""
+    out = []
+    for integ in integrators:
+        out += _orders(sizes, a0s, storage, integ)
+    return out
+
+
+def _orders(sizes, a0s, storage, integ):
     out = []
     for a0 in a0s:
         errs = []
         for n in sizes:
             case, exact = plane_wave_case(n, a0)
+            case.integrator = integ
             with lbm.context_for(case, storage) as ctx:
                 ctx.step(case.steps)
                 u = ctx.fields(0, want=("u",))["u"]
             ue = exact(case.steps * case.dt)
             errs.append(float(np.abs(u - ue).max() / np.abs(ue).max()))
         rates = [float(np.log2(errs[i] / errs[i + 1])) for i in range(len(errs) - 1)]
-        out.append({"experiment": "plane_wave_orders", "a0_phi": a0, "sizes": list(sizes),
-                    "rel_max_err_u": errs, "observed_orders": rates})
+        out.append({"experiment": "plane_wave_orders", "integrator": integ, "a0_phi": a0,
+                    "sizes": list(sizes), "rel_max_err_u": errs, "observed_orders": rates})
     return out
 
 

@@ -61,6 +61,8 @@ class Case:
     # hole (interior removed), 1 = bound (exterior removed); a node is in the
     # body iff its position is (points on an ellipse are)
     shapes: list = field(default_factory=list)
+    # displacement update: 0 as printed in the paper, 1 central difference
+    integrator: int = 0
 
     def in_body_nodes(self) -> int:
         return int(self.nx * self.ny if self.mask is None else int(np.count_nonzero(self.mask)))

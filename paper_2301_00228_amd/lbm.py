@@ -41,7 +41,8 @@ class lbm_plate(C.Structure):
                 ("lam", C.c_double), ("mu", C.c_double), ("rho_m", C.c_double),
                 ("dh", C.c_double), ("dt", C.c_double), ("sync_every", C.c_int32),
                 ("u0", C.POINTER(C.c_double)), ("v0", C.POINTER(C.c_double)),
-                ("e0", C.POINTER(C.c_double)), ("w0", C.POINTER(C.c_double))]
+                ("e0", C.POINTER(C.c_double)), ("w0", C.POINTER(C.c_double)),
+                ("integrator", C.c_int32)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -218,6 +219,7 @@ class Context:
             d.lam, d.mu, d.rho_m = float(p["lam"]), float(p["mu"]), float(p["rho"])
             d.dh, d.dt = float(p["dh"]), float(p["dt"])
             d.sync_every = int(p.get("sync_every", 0))
+            d.integrator = int(p.get("integrator", 0))
             for name, shape in (("u0", (2, ny, nx)), ("v0", (2, ny, nx)), ("e0", (ny, nx)),
                                 ("w0", (ny, nx))):
                 a = _f64(p.get(name), shape, name)
@@ -329,7 +331,7 @@ def plate_dict(case):
     return {"nx": case.nx, "ny": case.ny, "mask": case.mask, "periodic": case.periodic,
             "lam": case.lam, "mu": case.mu, "rho": case.rho, "dh": case.dh, "dt": case.dt,
             "sync_every": case.sync_every, "u0": case.u0, "v0": case.v0, "e0": case.e0,
-            "w0": case.w0}
+            "w0": case.w0, "integrator": getattr(case, "integrator", 0)}
 
 
 def context_for(cases, storage="f64", **kw):

@@ -183,6 +183,19 @@ def test_paper_example_setups_match_the_oracle(kind, sync):
     assert np.abs(err - p.cons_err()).max() <= 1e-12 * np.abs(ref["e"]).max()
 
 
+@pytest.mark.parametrize("tiling", [None, (64, 8, 0, 4, 0, 2, 4), (128, 5, 1, 2, 0, 1)])
+def test_central_difference_update_matches_the_oracle(tiling):
+    """The central-difference displacement update (integrator 1) on a plate
+    with Dirichlet and Neumann edges and on a plate with a hole."""
+    cases = [I.clamped_plate(n=96, ny=80, sigma=4.0, steps=201, sync_every=50, a0_phi=0.99),
+             I.plate_with_hole(n=100, radius=14, sigma=3.0, steps=150, sync_every=40)]
+    for case in cases:
+        case.integrator = 1
+        print("case", case.name, "central difference", tiling, flush=True)
+        ref, _ = run_case(case)
+        assert_parity(gpu_run(case, tiling=tiling), ref, what=case.name)
+
+
 def test_clamped_1024_short_run_full_size():
     case = I.clamped_plate(n=1024, steps=60)
     print("case", case.name, case.steps, flush=True)

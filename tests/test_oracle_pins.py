@@ -495,3 +495,50 @@ def test_bounded_plate_needs_the_papers_small_time_step():
         f, _ = run_case(case)
         bounded = np.isfinite(f["u"]).all() and np.abs(f["u"]).max() < 1e-2
         assert bounded == ok, a0
+
+
+def plane_wave_error(n, a0_phi, integrator, nu=0.25, amp=1e-3):
+    """Relative max error of u after one period of the dilatational plane
+    wave u = (A sin(2 pi x / n) cos(c_d kappa t), 0) on a periodic n x n
+    plate started at rest (the exact continuum solution)."""
+    lam = I.lame_lambda(nu)
+    cd = np.sqrt(lam + 2.0)
+    kappa = 2 * np.pi / n
+    dt = I.time_step(nu, a0_phi)
+    steps = int(round(2 * np.pi / (cd * kappa) / dt))
+    y, x = np.mgrid[0:n, 0:n].astype(np.float64)
+    u0 = np.stack([amp * np.sin(kappa * x), 0 * x])
+    p = OraclePlate(n, n, periodic=(True, True), lam=lam, dt=dt, u0=u0, v0=np.zeros_like(u0),
+                    integrator=integrator)
+    p.step(steps)
+    ue = amp * np.sin(kappa * x) * np.cos(cd * kappa * steps * dt)
+    return np.abs(p.fields()["u"][0] - ue).max() / amp
+
+
+def test_displacement_update_orders_on_a_plane_wave():
+    # eq. integration as printed (v += dt a(t)) converges at first order in
+    # dt; the central difference (Newmark gamma = 1/2) at second order.
+    e1 = [plane_wave_error(n, 0.5, 0) for n in (16, 32, 64)]
+    e2 = [plane_wave_error(n, 0.5, 1) for n in (16, 32, 64)]
+    r1 = [np.log2(e1[i] / e1[i + 1]) for i in range(2)]
+    r2 = [np.log2(e2[i] / e2[i + 1]) for i in range(2)]
+    assert all(0.9 < r < 1.1 for r in r1), r1
+    assert all(r > 1.9 for r in r2), r2
+    assert e2[-1] < 1e-3 * e1[-1]
+
+
+def test_central_difference_keeps_dirichlet_nodes_on_the_prescribed_path():
+    n = 24
+    nu = 0.3
+    dt = I.time_step(nu, 0.99)
+    p = OraclePlate(n, n, lam=I.lame_lambda(nu), dt=dt, sync_every=10, integrator=1)
+    bc = I.dirichlet_edges_bc(n, n, [I.LEFT])
+    ustar = np.tile([2e-3, -1e-3], (len(bc.xy), 1))
+    knots = np.array([[0.0, 0.0], [30 * dt, 1.0]])
+    p.set_bc(bc.xy, bc.kind, ustar, knots=knots)
+    for s in range(1, 61):
+        p.step(1)
+        u = p.fields()["u"]
+        g = min(s * dt / (30 * dt), 1.0)
+        got = u[:, bc.xy[:, 1], bc.xy[:, 0]].T
+        assert np.abs(got - g * ustar).max() < 8 * np.finfo(float).eps * 2e-3
