@@ -61,8 +61,20 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
 
 
-def cpu_baseline(case, budget_s=12.0):
-    """Time the FP64 oracle on a bounded sample of the same workload."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(case, budget_s=12.0, single_s=3.0):
+    """Time the FP64 oracle on a bounded sample of the same workload, with
+    all its OpenMP threads and with one."""
     from oracle import oracle
 
     p = oracle.OraclePlate(case.nx, case.ny, mask=case.mask, periodic=case.periodic,
@@ -70,18 +82,31 @@ def cpu_baseline(case, budget_s=12.0):
                            sync_every=case.sync_every, u0=case.u0, v0=case.v0)
     for bc in case.bcs:
         p.set_bc(bc.xy, bc.kind, bc.val, cell=bc.cell, knots=bc.knots)
-    t0 = time.perf_counter()
-    p.step(5)
-    probe = time.perf_counter() - t0
-    steps = max(5, int(budget_s / max(probe / 5, 1e-6)))
-    t0 = time.perf_counter()
-    p.step(steps)
-    dt = time.perf_counter() - t0
     nodes = case.in_body_nodes()
-    return {"value": nodes * steps / dt / 1e9, "unit": "GLUPS", "cores": oracle.threads(),
+    threads = oracle.threads()
+
+    def timed(budget, done):
+        p.step(1)  # (thread start-up)
+        t0 = time.perf_counter()
+        p.step(4)
+        probe = time.perf_counter() - t0
+        steps = max(4, int(budget / max(probe / 4, 1e-6)))
+        t0 = time.perf_counter()
+        p.step(steps)
+        return steps, time.perf_counter() - t0, done + 5
+
+    steps, dt, first = timed(budget_s, 0)
+    oracle.set_threads(1)
+    steps1, dt1, first1 = timed(single_s, first + steps)
+    oracle.set_threads(threads)
+    return {"value": nodes * steps / dt / 1e9, "unit": "GLUPS", "cores": threads,
             "kind": "oracle",
             "sample": f"{case.nx}x{case.ny} plate of the same workload, {steps} steps "
-                      f"(steps 6..{steps + 5}), {dt:.1f} s wall"}
+                      f"(steps {first + 1}..{first + steps}), {dt:.1f} s wall",
+            "single_thread_value": nodes * steps1 / dt1 / 1e9,
+            "single_thread_sample": f"steps {first1 + 1}..{first1 + steps1}, {dt1:.1f} s wall",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS")}
 
 
 def main():

@@ -90,7 +90,11 @@ int64_t orc_step_count(const orc_plate *p);
 int orc_threads(void);
 void orc_destroy(orc_plate *p);
 
+/* Set the number of OpenMP threads of the oracle's loops (n > 0). */
+void orc_set_threads(int n);
+
 #ifdef __cplusplus
 }
 #endif
+
 #endif

@@ -54,6 +54,7 @@ def lib():
         L.orc_destroy.argtypes = [C.c_void_p]
         L.orc_threads.restype = C.c_int
         L.orc_threads.argtypes = []
+        L.orc_set_threads.argtypes = [C.c_int]
         _lib = L
     return _lib
 
@@ -167,6 +168,11 @@ class OraclePlate:
 def threads():
     """OpenMP threads used by the oracle's loops."""
     return int(lib().orc_threads())
+
+
+def set_threads(n):
+    """Set the OpenMP threads of the oracle's loops."""
+    lib().orc_set_threads(int(n))
 
 
 def run_case(case, steps=None):
