@@ -37,14 +37,16 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
 
 
-def timed(cases, storage, steps, warmup, tune=True):
+def timed(cases, storage, steps, warmup, tune=True, tiling=None):
     import torch
     t0 = time.perf_counter()
     ctx = lbm.context_for(cases, storage)
     setup = time.perf_counter() - t0
     print(f"context {storage}: {setup:.1f} s", file=sys.stderr, flush=True)
     ctx.step(2)
-    if tune:
+    if tiling:
+        ctx.set_tiling(*tiling)
+    elif tune:
         t1 = time.perf_counter()
         t_set = time.perf_counter()
         ctx.set_tiling(128, 16, 0, 4, 16, 2)
@@ -96,6 +98,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--ref", default="f64",
                     help="storage of the reference run for the error ('' = no error)")
+    ap.add_argument("--tiling", default="", metavar="L,R,O,E,A,S,W",
+                    help="interior tiling instead of the autotuner's pick")
     ap.add_argument("--ref-plates", type=int, default=0,
                     help="compare only the first N plates and the last one (0 = all)")
     args = ap.parse_args()
@@ -105,7 +109,8 @@ def main():
     torch.cuda.set_device(0)
     print(f"building {args.workload}", file=sys.stderr, flush=True)
     cases = cases_for(args.workload, args.warmup + args.steps)
-    ctx, res = timed(cases, args.storage, args.steps, args.warmup)
+    tiling = [int(v) for v in args.tiling.split(",")] if args.tiling else None
+    ctx, res = timed(cases, args.storage, args.steps, args.warmup, tiling=tiling)
     res["workload"] = args.workload
     print(json.dumps(res), flush=True)
     if args.ref:
