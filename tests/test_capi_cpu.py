@@ -83,3 +83,16 @@ def test_valid_arguments_report_missing_device():
     with pytest.raises(lbm.LbmError) as ei:
         lbm.Context([_plate()])
     assert ei.value.code == lbm.E_DEVICE
+
+
+def test_unknown_integrator_rejected():
+    with pytest.raises(lbm.LbmError) as ei:
+        lbm.Context([_plate(integrator=2)])
+    assert ei.value.code == lbm.E_INVAL
+
+
+def test_consistency_error_needs_a_context():
+    L = lbm.library()
+    err = np.zeros(4)
+    assert L.lbm_consistency_error(None, 0, err.ctypes.data_as(lbm.C.POINTER(lbm.C.c_double))) \
+        == lbm.E_INVAL
