@@ -1,0 +1,99 @@
+"""The precision workload at full size against the FP64 CPU oracle.
+
+Not collected by pytest (an oracle run over 8192^2 nodes takes many minutes);
+run it by hand:
+
+    python -u tests/full_size_oracle.py --n 8192 --radius 1024 --steps 2000 \
+        --every 250 --out result.jsonl
+
+The plate with a central traction-free hole, outer edges clamped, a sigma 16
+displacement pulse, synchronization every 50 steps: every storage's GPU
+context and the oracle advance side by side, and at each checkpoint one JSON
+line gives, per storage, the relative max-norm and relative L2 error of e,
+omega and u against the oracle.  A line is written (and flushed) as soon as
+its checkpoint is reached, so a run cut short still leaves every earlier one.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+
+from oracle.oracle import OraclePlate, threads  # noqa: E402
+from paper_2301_00228_amd import inputs as I  # noqa: E402
+from paper_2301_00228_amd import lbm  # noqa: E402
+
+FIELDS = ("e", "omega", "u")
+
+
+def errors(got, ref):
+    out = {"rel_l2": {}, "rel_max": {}}
+    for k in FIELDS:
+        d = got[k] - ref[k]
+        out["rel_l2"][k] = float(np.linalg.norm(d) / np.linalg.norm(ref[k]))
+        out["rel_max"][k] = float(np.abs(d).max() / np.abs(ref[k]).max())
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--n", type=int, default=8192)
+    ap.add_argument("--radius", type=int, default=1024)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--every", type=int, default=250)
+    ap.add_argument("--storages", default="f64,f32dev,f16dev,bf16dev")
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--max-seconds", type=float, default=0.0,
+                    help="stop before a checkpoint the oracle would not reach in this wall time")
+    a = ap.parse_args()
+
+    import torch
+    torch.cuda.set_device(0)
+    case = I.plate_with_hole(n=a.n, radius=a.radius, steps=a.steps)
+    storages = a.storages.split(",")
+    ctxs = {st: lbm.context_for(case, st) for st in storages}
+    for st, ctx in ctxs.items():
+        print(f"gpu context {st}: tiling {ctx.info()['tile_lanes']}x{ctx.info()['tile_rows']}",
+              flush=True)
+    orc = OraclePlate(case.nx, case.ny, mask=case.mask, periodic=case.periodic, lam=case.lam,
+                      mu=case.mu, rho=case.rho, dh=case.dh, dt=case.dt,
+                      sync_every=case.sync_every, u0=case.u0, v0=case.v0, e0=case.e0,
+                      w0=case.w0, integrator=getattr(case, "integrator", 0))
+    for bc in case.bcs:
+        orc.set_bc(bc.xy, bc.kind, bc.val, cell=bc.cell, knots=bc.knots)
+    print(f"oracle ready, {threads()} threads, {case.in_body_nodes()} nodes", flush=True)
+
+    done, t_orc, t_start = 0, 0.0, time.perf_counter()
+    with open(a.out, "w") as fo:
+        while done < a.steps:
+            k = min(a.every, a.steps - done)
+            if a.max_seconds and done and \
+                    time.perf_counter() - t_start + t_orc / done * k * 1.2 > a.max_seconds:
+                print(f"stopping at step {done}: the next checkpoint would pass "
+                      f"{a.max_seconds:.0f} s", flush=True)
+                break
+            t0 = time.perf_counter()
+            for chunk in range(0, k, 50):  # progress every 50 steps
+                orc.step(min(50, k - chunk))
+                print(f"oracle step {done + min(chunk + 50, k)}", flush=True)
+            t_orc += time.perf_counter() - t0
+            done += k
+            ref = {kk: v for kk, v in orc.fields().items() if kk in FIELDS}
+            line = {"n": a.n, "radius": a.radius, "step": done, "nodes": case.in_body_nodes(),
+                    "oracle_threads": threads(), "oracle_glups": case.in_body_nodes() * done / t_orc / 1e9}
+            for st, ctx in ctxs.items():
+                ctx.step(k)
+                line[st] = errors(ctx.fields(0, want=FIELDS), ref)
+            fo.write(json.dumps(line) + "\n")
+            fo.flush()
+            print(json.dumps(line), flush=True)
+    for ctx in ctxs.values():
+        ctx.close()
+
+
+if __name__ == "__main__":
+    main()
