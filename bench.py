@@ -26,10 +26,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 # Interior tilings (lanes, rows, order, edge rows, alignment, steps per pass,
-# edge columns) that the library's autotuner picks for this workload on
-# MI355X, pinned so that runs and the committed rocprofv3 summaries use the
-# same launches (--autotune tunes again instead).
-TUNED = {st: (64, 8, 0, 4, 0, 2, 4) for st in ("f64", "f32", "f32dev", "f16dev", "bf16dev")}
+# edge columns) and overlapped pairs (lbm_use_overlap) that measured fastest
+# for this workload on MI355X, pinned so that runs and the committed
+# rocprofv3 summaries use the same launches (--autotune tunes again instead).
+TUNED = {"f64": ((64, 8, 0, 4, 0, 2, 4), True), "f32": ((64, 8, 0, 4, 0, 2, 4), True),
+         "f32dev": ((64, 8, 0, 4, 0, 2, 4), True), "f16dev": ((64, 8, 0, 2, 0, 2, 8), True),
+         "bf16dev": ((64, 8, 0, 2, 0, 2, 8), True)}
 METRIC = "GLUPS + % HBM roofline, FP64 vs FP16/FP32-storage at ≤1e-3 rel L2"
 
 
@@ -41,17 +43,18 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(storage, kind, tile):
+def measured_traffic(storage, kind, tile, overlap):
     """HBM bytes per launch of one interior-kernel kind from the committed
     rocprofv3 PMC summary, if it was taken on the current kernel source with
-    the same tiling."""
+    the same tiling and overlap setting."""
     path = os.path.join(ROOT, "profiles", f"interior_{storage}_clamped1024_traffic.json")
     try:
         with open(path) as fh:
             d = json.load(fh)
     except (OSError, ValueError):
         return None
-    if d.get("kernel_source_hash") != kernel_source_hash() or d.get("tile") != tile:
+    if (d.get("kernel_source_hash") != kernel_source_hash() or d.get("tile") != tile
+            or d.get("overlap", False) != overlap):
         return None
     return d.get("kernels", {}).get(kind, {}).get("hbm_bytes_per_launch")
 
@@ -121,6 +124,8 @@ def main():
     ap.add_argument("--tiling", default="", metavar="L,R,O,E,A,S[,W]",
                     help="interior tiling of the headline storage (lanes, rows, order, edge "
                          "rows, alignment, steps, edge columns) instead of the pinned one")
+    ap.add_argument("--overlap", type=int, default=-1, choices=(-1, 0, 1),
+                    help="overlapped pairs of the headline storage (-1: the pinned choice)")
     ap.add_argument("--autotune", action="store_true",
                     help="run the library's autotuner instead of the pinned tilings")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
@@ -157,7 +162,10 @@ def main():
         if args.tiling and storage == args.storage:
             ctx.set_tiling(*[int(v) for v in args.tiling.split(",")])
         elif not args.autotune:
-            ctx.set_tiling(*TUNED[storage])
+            ctx.set_tiling(*TUNED[storage][0])
+        if not args.autotune:
+            ov = args.overlap if (storage == args.storage and args.overlap >= 0) else TUNED[storage][1]
+            ctx.use_overlap(bool(ov))
         ctx.step(2)
         if args.autotune:
             ctx.autotune(5)
@@ -176,37 +184,54 @@ def main():
     f64_fields = ctx.fields(0)
     tile = [info["tile_lanes"], info["tile_rows"], info["tile_order"], info["tile_edge_rows"],
             info["tile_align"], info["tile_steps"], info["tile_edge_cols"]]
-    # Dominant kernel: the interior launch with the most device time -- the
-    # first launch of a two-step pair (two steps of the two-step tiles, one
-    # of the others) or the single-step launch.  Device time per launch from
-    # HIP events on the library's stream, eager back-to-back launches.
-    # achieved = algorithmic bytes per lattice update x the lattice updates
-    # the launch performs / its time; the launch streams each body node's
-    # state once, so with two steps per pass this exceeds the rate at which
-    # it actually streams (min_bytes / time) and the measured traffic.
+    # Dominant kernel: the interior launch with the most device time -- with
+    # overlapped pairs the deep tiles' launch (two steps of the two-step
+    # tiles away from the single-step ones, on the library's second stream
+    # beside the pair's other launches), else the first launch of a two-step
+    # pair (two steps of the two-step tiles, one of the others) or the
+    # single-step launch.  Device time per launch from HIP events on the
+    # stream it runs on, eager launches.  achieved = algorithmic bytes per
+    # lattice update x the lattice updates the launch performs / its time;
+    # the launch streams each of its nodes' state once, so with two steps per
+    # pass this exceeds the rate at which it actually streams (min_bytes /
+    # time) and the measured traffic.
     prof = ctx.profile(args.profile_steps)
     bnd_ms, bnd_n = prof["boundary"]
     bpu = info["bytes_per_update"]
-    kind = "two_step" if prof["two_step"][1] > 0 else "interior"
+    kind = ("deep" if prof["deep"][1] > 0 else
+            "two_step" if prof["two_step"][1] > 0 else "interior")
     k_ms, k_n = prof[kind]
     per_launch_s = k_ms / k_n / 1e3
-    n_two = info["nodes_two_step"] if kind == "two_step" else 0
-    lups = nodes + n_two
+    if kind == "deep":
+        own = info["nodes_deep"]
+        lups = 2 * own
+        kname = f"k_interior<{args.storage}, {info['tile_lanes']} lanes, two-step, deep tiles>"
+    elif kind == "two_step":
+        own = nodes
+        lups = nodes + info["nodes_two_step"]
+        kname = f"k_interior<{args.storage}, {info['tile_lanes']} lanes, two-step>"
+    else:
+        own = nodes
+        lups = nodes
+        kname = f"k_interior<{args.storage}, {info['tile_lanes']} lanes, single-step>"
     achieved = lups * bpu / per_launch_s / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(args.storage, kind, tile),
-                "kernel": f"k_interior<{args.storage}, {info['tile_lanes']} lanes, "
-                          f"{'two-step' if kind == 'two_step' else 'single-step'}>",
+                "traffic": measured_traffic(args.storage, kind, tile, bool(info["overlap"])),
+                "kernel": kname,
                 "bytes_per_lup": bpu, "lups_per_launch": lups,
                 "avg_launch_us": round(per_launch_s * 1e6, 2),
-                "min_bytes_per_launch": nodes * bpu,
-                "min_bytes_GBs": round(nodes * bpu / per_launch_s / 1e9, 1),
+                "min_bytes_per_launch": own * bpu,
+                "min_bytes_GBs": round(own * bpu / per_launch_s / 1e9, 1),
                 "boundary_kernel_avg_us": round(bnd_ms / max(bnd_n, 1) * 1e3, 2)}
-    if kind == "two_step":
+    if kind in ("deep", "two_step"):
         s_ms, s_n = prof["interior"]
-        roofline["two_step_nodes"] = n_two
+        roofline["two_step_nodes"] = info["nodes_two_step"]
         roofline["second_launch_avg_us"] = round(s_ms / max(s_n, 1) * 1e3, 2)
+    if kind == "deep":
+        f_ms, f_n = prof["two_step"]
+        roofline["deep_nodes"] = info["nodes_deep"]
+        roofline["frame_launch_avg_us"] = round(f_ms / max(f_n, 1) * 1e3, 2)
     # what one step per pass over HBM would have to stream at the measured
     # step rate
     roofline["effective_GBs"] = round(nodes * bpu / (dt / K) / 1e9, 1)
@@ -219,10 +244,17 @@ def main():
             c2, d2 = timed_run(st)
             fl = c2.fields(0)
             pr = c2.profile(min(args.profile_steps, 100))
-            two = pr["two_step"][1] > 0
-            i_ms, i_n = pr["two_step"] if two else pr["interior"]
-            bpu2 = c2.info()["bytes_per_update"]
-            lups2 = nodes + (c2.info()["nodes_two_step"] if two else 0)
+            i2 = c2.info()
+            bpu2 = i2["bytes_per_update"]
+            if pr["deep"][1] > 0:
+                i_ms, i_n = pr["deep"]
+                lups2 = 2 * i2["nodes_deep"]
+            elif pr["two_step"][1] > 0:
+                i_ms, i_n = pr["two_step"]
+                lups2 = nodes + i2["nodes_two_step"]
+            else:
+                i_ms, i_n = pr["interior"]
+                lups2 = nodes
             ach2 = lups2 * bpu2 / (i_ms / i_n / 1e3) / 1e9
             c2.close()
             variants[st] = {
@@ -249,7 +281,7 @@ def main():
                                "free), nu 0.3, a0_phi 0.9999, Gaussian pulse sigma 16 amp 1e-3, "
                                "sync every 50, FP64 populations and u",
                    "nodes": nodes, "storage": args.storage, "tile": tile,
-                   "graphs": True},
+                   "overlap": bool(info["overlap"]), "graphs": True},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "variants": variants,

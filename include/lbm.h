@@ -191,8 +191,12 @@ lbm_status lbm_exact_cells(int32_t nx, int32_t ny, uint8_t periodic_x, uint8_t p
 /* Advance every plate by n_steps time steps (Fig. 4: accelerations,
  * Newmark update, boundary reset, LBE with the second-row rule, and the
  * synchronization after every l-th step).  Stream-ordered and asynchronous:
- * returns once the work is enqueued.  A blow-up detected by earlier work is
- * reported as LBM_E_NONFINITE by this or the next synchronizing call. */
+ * returns once the work is enqueued.  With two-step tilings part of the work
+ * runs on a second stream of the library's that forks from and joins back
+ * into the context's stream with events within the call (see
+ * lbm_use_overlap), so to the caller the work is ordered on the context's
+ * stream.  A blow-up detected by earlier work is reported as
+ * LBM_E_NONFINITE by this or the next synchronizing call. */
 lbm_status lbm_step(lbm_ctx *ctx, int64_t n_steps);
 
 /* Copy one plate's state to host buffers (any may be NULL): e = sum of the
@@ -237,6 +241,9 @@ typedef struct {
   int32_t tile_steps;         /* time steps per pass over the tiles away from boundaries    */
   int32_t n_tiles;
   int32_t tile_edge_cols;     /* width of the first and last column strip (0: no such strip) */
+  int64_t nodes_deep;         /* body nodes in deep two-step tiles (see lbm_use_overlap)    */
+  int32_t overlap;            /* 1: pairs of steps overlapped on two streams                */
+  int32_t pad;
 } lbm_info_t;
 lbm_status lbm_info(const lbm_ctx *ctx, lbm_info_t *info);
 
@@ -285,25 +292,44 @@ lbm_status lbm_set_tiling(lbm_ctx *ctx, const lbm_tiling *tiling);
  * leaves the state unchanged, except at step 0, at a synchronization step
  * and right after a two-step pair, where the autotuner first takes one real
  * step (steps_done grows by one; the trajectory is the same as without the
- * autotuner).  Results are cached per (storage, single/multiple plates,
- * size bucket) for the life of the process and picked up by later
- * contexts.  best_ms (nullable) receives the fastest interior time per step
- * (for two-step tilings half the time of a pair's two launches). */
+ * autotuner).  With overlapped pairs on (lbm_use_overlap) two-step
+ * tilings are timed as overlapped pairs, and the best one is timed once
+ * more on one stream; if that is faster, overlap is turned off.  Results are
+ * cached per (storage, single/multiple plates, size bucket) for the life of
+ * the process and picked up by later contexts.  best_ms (nullable) receives
+ * the fastest interior time per step (for two-step tilings half the time of
+ * a pair's launches). */
 lbm_status lbm_autotune(lbm_ctx *ctx, int32_t steps, double *best_ms);
 
-/* Run n_steps steps eagerly (no graph), launches back to back with a HIP
- * event recorded on the context's stream before the first and after every
- * kernel launch, and return the summed time between consecutive events per
- * kernel kind in ms (a launch's device time plus the gap after the previous
- * one): ms[0] single-step interior launches (stream+collide of one step),
- * ms[1] boundary/second-row, ms[2] synchronization, ms[3] two-step interior
- * launches (the first launch of a pair: two steps of the two-step tiles, one
- * of the others); and the number of launches of each kind in
- * launches[0..3] (nullable).  Synchronizes the stream. */
+/* Run n_steps steps eagerly (no graph) with HIP events recorded before and
+ * after every kernel launch on the stream it runs on, and return the summed
+ * time between the two events per kernel kind in ms (a launch's device time
+ * plus the gap after the previous launch on its stream, or after what it
+ * waited for): ms[0] single-step interior launches (stream+collide of one
+ * step), ms[1] boundary/second-row, ms[2] synchronization, ms[3] two-step
+ * interior launches (the first launch of a pair: two steps of the two-step
+ * tiles -- of the frame tiles only when the pair is overlapped -- and one of
+ * the others), ms[4] the deep-tile launches of overlapped pairs (see
+ * lbm_use_overlap); and the number of launches of each kind in
+ * launches[0..4] (nullable).  Overlapped launches run at the same time, so
+ * the sum over kinds can exceed the wall time.  Synchronizes the stream. */
 lbm_status lbm_profile(lbm_ctx *ctx, int64_t n_steps, double *ms, int64_t *launches);
 
 /* Use (nonzero) or bypass (0) captured HIP graphs in lbm_step.  Default on. */
 lbm_status lbm_use_graphs(lbm_ctx *ctx, int32_t enable);
+
+/* Overlapped pairs (nonzero, the default) or one stream (0), for two-step
+ * tilings.  The two-step tiles split into frame tiles (a node of a
+ * single-step tile within two nodes of their area) and deep tiles (the
+ * others).  In an overlapped pair -- every pair but one starting at step 0
+ * -- the deep tiles take their two steps in a launch of their own on a
+ * second stream (default priority), ordered by events after the previous
+ * pair's first launch and before the next pair's first launch, so that it
+ * runs beside this pair's single-step launches; the frame tiles take theirs
+ * in the first launch of the pair, with the single-step tiles' first step.
+ * The launches beside each other read and write disjoint nodes: the results
+ * are bitwise the same either way.  Invalidates captured step graphs. */
+lbm_status lbm_use_overlap(lbm_ctx *ctx, int32_t enable);
 
 void lbm_destroy(lbm_ctx *ctx);
 

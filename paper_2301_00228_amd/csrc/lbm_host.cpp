@@ -77,7 +77,11 @@ size_t slot_bytes(int st) {
 size_t uv_bytes(int st) { return st == LBM_STORE_F32 ? 4 : 8; }
 
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int>, lbm_tiling> g_tune_cache;
+struct TuneEntry {
+  lbm_tiling t;
+  bool overlap;
+};
+std::map<std::tuple<int, int, int>, TuneEntry> g_tune_cache;
 
 }  // namespace
 
@@ -125,6 +129,8 @@ struct lbm_ctx {
   std::vector<LoadTable> loads;
   std::vector<Tile> tiles;
   std::vector<Tile> etiles;  // the single-step tiles (second launch of a two-step pair)
+  std::vector<Tile> ftiles;  // single-step and frame tiles (first launch of an overlapped pair)
+  std::vector<Tile> dtiles;  // deep two-step tiles (the side stream's launch)
   int lanes = 128, rows = 32, order = 0, edge_rows = 0, align = 0, two = 0, edge_cols = 0;
 
   std::vector<Buffer> bufs;
@@ -133,6 +139,16 @@ struct lbm_ctx {
   Tile *d_tiles = nullptr;
   Tile *d_etiles = nullptr;
   size_t etiles_cap = 0;
+  Tile *d_ftiles = nullptr, *d_dtiles = nullptr;
+  size_t ftiles_cap = 0, dtiles_cap = 0;
+  int64_t n_deep = 0;  // body nodes in deep tiles
+  // Overlapped pairs: the deep tiles of a pair run on a side stream beside
+  // the single-step launch of the previous pair.  ev_f[i]: after the first
+  // launch of a pair on the main stream; ev_d[i]: after a deep launch
+  // (alternating by pair, so that a wait never binds to a later record).
+  bool overlap = true;
+  hipStream_t side = nullptr;
+  hipEvent_t ev_f[2] = {nullptr, nullptr}, ev_d[2] = {nullptr, nullptr};
   BndNode *d_bnd = nullptr;
   SecNode *d_sec = nullptr;
   LoadTable *d_loads = nullptr;
@@ -615,6 +631,40 @@ void classify_two_step(lbm_ctx *c) {
   }
   for (const Tile &t : c->tiles)
     if (t.flags & TF_TWO) c->n_two += (int64_t)(t.x1 - t.x0) * (t.y1 - t.y0);
+  // Frame tiles: two-step tiles owning a node of the two-node ring of a
+  // single-step tile (the relation is symmetric), so that the other
+  // two-step tiles (deep tiles) neither read nor write what single-step
+  // tiles own.
+  for (const Tile &e : c->tiles) {
+    if (e.flags & TF_TWO) continue;
+    const PlateHost &h = c->ph[(size_t)e.plate];
+    auto frame = [&](int i, int j) {
+      if (i < 0 || i >= h.nx) {
+        if (!h.px) return;
+        i = ((i % h.nx) + h.nx) % h.nx;
+      }
+      if (j < 0 || j >= h.ny) {
+        if (!h.py) return;
+        j = ((j % h.ny) + h.ny) % h.ny;
+      }
+      Tile &o = c->tiles[(size_t)tile_at(c, e.plate, i, j)];
+      if (o.flags & TF_TWO) o.flags |= TF_FRAME;
+    };
+    for (int j = e.y0 - 2; j < e.y1 + 2; j++) {
+      if (j < e.y0 || j >= e.y1) {
+        for (int i = e.x0 - 2; i < e.x1 + 2; i++) frame(i, j);
+      } else {
+        frame(e.x0 - 2, j);
+        frame(e.x0 - 1, j);
+        frame(e.x1, j);
+        frame(e.x1 + 1, j);
+      }
+    }
+  }
+  c->n_deep = 0;
+  for (const Tile &t : c->tiles)
+    if ((t.flags & TF_TWO) && !(t.flags & TF_FRAME))
+      c->n_deep += (int64_t)(t.x1 - t.x0) * (t.y1 - t.y0);
   for (const Tile &e : c->tiles) {
     if (e.flags & TF_TWO) continue;
     const PlateHost &h = c->ph[(size_t)e.plate];
@@ -653,7 +703,9 @@ void classify_two_step(lbm_ctx *c) {
 // plate, band by band (strips of a band adjacent); 1: plate by plate, strip
 // by strip (bands of a strip adjacent); 2: as 0 with the plates by decreasing
 // size.  Consecutive tiles land on the same XCD (see k_interior), so the
-// order decides which halo rows / columns share an L2.
+// order decides which halo rows / columns share an L2.  With overlapped
+// two-step pairs the band pieces around those with boundary work are cut to
+// edge_rows as well (they hold the frame tiles, see classify_two_step).
 void build_tiles(lbm_ctx *c) {
   c->tiles.clear();
   const int own = c->lanes - (c->two ? 4 : 2);
@@ -718,6 +770,33 @@ void build_tiles(lbm_ctx *c) {
     };
     for (const BndNode &B : c->bnd) mark(B.plate, B.i, B.j);
     for (const SecNode &S : c->sec) mark(S.plate, S.i, S.j);
+    // With overlapped two-step pairs, the band pieces next to those are cut
+    // too: they hold the frame tiles, whose two steps a single-step launch
+    // waits for.
+    if (c->two && c->overlap) {
+      for (size_t p = 0; p < c->ph.size(); p++) {
+        const PlateHost &h = c->ph[p];
+        const int nb = (h.ny + rows - 1) / rows;
+        const std::vector<uint8_t> w0 = work[p];
+        for (int s = 0; s < h.ns; s++)
+          for (int b = 0; b < nb; b++) {
+            if (!w0[(size_t)s * nb + b]) continue;
+            for (int ds = -1; ds <= 1; ds++)
+              for (int db = -1; db <= 1; db++) {
+                int s2 = s + ds, b2 = b + db;
+                if (s2 < 0 || s2 >= h.ns) {
+                  if (!h.px) continue;
+                  s2 = (s2 + h.ns) % h.ns;
+                }
+                if (b2 < 0 || b2 >= nb) {
+                  if (!h.py) continue;
+                  b2 = (b2 + nb) % nb;
+                }
+                work[p][(size_t)s2 * nb + b2] = 1;
+              }
+          }
+      }
+    }
   }
   for (int p : plates) {
     PlateHost &h = c->ph[p];
@@ -905,9 +984,20 @@ lbm_status upload_tile_list(lbm_ctx *c, const std::vector<Tile> &v, Tile *&d, si
 
 lbm_status upload_tiles(lbm_ctx *c) {
   c->etiles.clear();
-  for (const Tile &t : c->tiles)
+  c->ftiles.clear();
+  c->dtiles.clear();
+  for (const Tile &t : c->tiles) {
     if (!(t.flags & TF_TWO)) c->etiles.push_back(t);
+    if ((t.flags & TF_TWO) && !(t.flags & TF_FRAME))
+      c->dtiles.push_back(t);
+    else
+      c->ftiles.push_back(t);
+  }
   lbm_status st = upload_tile_list(c, c->tiles, c->d_tiles, c->tiles_cap);
+  if (st) return st;
+  st = upload_tile_list(c, c->ftiles, c->d_ftiles, c->ftiles_cap);
+  if (st) return st;
+  st = upload_tile_list(c, c->dtiles, c->d_dtiles, c->dtiles_cap);
   if (st) return st;
   return upload_tile_list(c, c->etiles, c->d_etiles, c->etiles_cap);
 }
@@ -1007,72 +1097,125 @@ Prologue make_prologue(const lbm_ctx *c, bool enabled) {
 // launch finishing step s + k - 1, which leaves the state complete at
 // t_{s+k}; then the synchronization if s + k is a multiple of l.  cur and
 // prev (buffers of t_s and of the boundary populations of t_{s-1}) are
-// advanced.  rec (profiling): an event after every launch, with the
-// launch's kind (0 single-step interior, 1 boundary, 2 synchronization,
-// 3 two-step interior).
+// advanced.
+//
+// Overlapped pairs (c->overlap, pairs after the run's first step): the deep
+// tiles' two steps go to a launch of their own on the side stream, which
+// waits for the first launch of the previous pair (the frame tiles' part of
+// its ring) and which the first launch of the next pair waits for; so it
+// runs beside this pair's first launch (single-step and frame tiles) and
+// its second launch, whose tiles and buffers it does not touch: it reads
+// buffer cur at deep and frame nodes only, writes buffer cur ^ 1 at deep
+// nodes only, and the other launches write cur ^ 1 and buffer 2 at other
+// nodes only and read cur ^ 1 at boundary nodes only.
+//
+// rec (profiling): events before and after every launch on its stream,
+// with the launch's kind (0 single-step interior, 1 boundary, 2
+// synchronization, 3 two-step interior, 4 deep tiles).
 struct LaunchRecorder {
-  std::vector<hipEvent_t> ev;  // ev[0] before the first launch, ev[i + 1] after launch i
-  std::vector<int> kind;
+  struct Rec {
+    hipEvent_t a, b;
+    int kind;
+  };
+  std::vector<Rec> recs;
 };
+
+bool overlapped_pair(const lbm_ctx *c, int64_t n) {
+  return c->two && c->overlap && n > 0 && !c->dtiles.empty() && c->side != nullptr;
+}
 
 hipError_t enqueue_segment(lbm_ctx *c, int64_t s, int64_t k, int &cur, int &prev, hipStream_t st,
                            LaunchRecorder *rec) {
-  auto timed = [&](int kind, auto &&fn) -> hipError_t {
-    auto mark = [&]() -> hipError_t {
-      hipEvent_t e;
-      hipError_t r = hipEventCreate(&e);
-      if (r != hipSuccess) return r;
-      rec->ev.push_back(e);
-      return hipEventRecord(e, st);
-    };
-    if (rec && rec->ev.empty()) {
-      hipError_t r = mark();
-      if (r != hipSuccess) return r;
-    }
-    hipError_t e = fn();
-    if (rec && e == hipSuccess) {
-      e = mark();
-      rec->kind.push_back(kind);
-    }
+  auto timed = [&](int kind, hipStream_t on, auto &&fn) -> hipError_t {
+    if (!rec) return fn();
+    LaunchRecorder::Rec r{nullptr, nullptr, kind};
+    hipError_t e = hipEventCreate(&r.a);
+    if (e == hipSuccess) e = hipEventCreate(&r.b);
+    if (e == hipSuccess) e = hipEventRecord(r.a, on);
+    if (e == hipSuccess) e = fn();
+    if (e == hipSuccess) e = hipEventRecord(r.b, on);
+    if (r.a || r.b) rec->recs.push_back(r);
     return e;
   };
   const int T = 2;  // intermediate buffer of a two-step pair
   hipError_t e = hipSuccess;
+  bool pend_d = false;  // a deep launch that st has not waited for: ev_d[par ^ 1]
+  bool have_f = false;  // ev_f[par ^ 1] marks what the next deep launch waits for
+  int par = 0;          // parity of the pair (events alternate)
+  auto join = [&]() -> hipError_t {
+    if (!pend_d) return hipSuccess;
+    pend_d = false;
+    return hipStreamWaitEvent(st, c->ev_d[par ^ 1], 0);
+  };
   for (int64_t n = s; n < s + k && e == hipSuccess;) {
     if (c->two && s + k - n >= 2) {
       const StepBufs b1{cur, T, prev, (int)(n & 1), cur ^ 1};
       const Prologue p1 = make_prologue(c, n > s);
-      e = timed(3, [&] {
-        return launch_interior(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), c->lanes, b1,
-                               p1, st);
-      });
-      if (e != hipSuccess) break;
       const StepBufs b2{T, cur ^ 1, cur, (int)((n + 1) & 1), -1};
       const Prologue p2 = make_prologue(c, true);
-      e = timed(0, [&] {
-        return launch_interior(c->storage, c->ds, c->d_etiles, (int)c->etiles.size(), c->lanes,
-                               b2, p2, st);
-      });
+      if (overlapped_pair(c, n)) {
+        e = join();
+        if (e == hipSuccess && !have_f) e = hipEventRecord(c->ev_f[par ^ 1], st);
+        if (e == hipSuccess)
+          e = timed(3, st, [&] {
+            return launch_interior(c->storage, c->ds, c->d_ftiles, (int)c->ftiles.size(),
+                                   c->lanes, b1, p1, st);
+          });
+        if (e == hipSuccess) e = hipEventRecord(c->ev_f[par], st);
+        if (e == hipSuccess)
+          e = timed(0, st, [&] {
+            return launch_interior(c->storage, c->ds, c->d_etiles, (int)c->etiles.size(),
+                                   c->lanes, b2, p2, st);
+          });
+        if (e == hipSuccess) e = hipStreamWaitEvent(c->side, c->ev_f[par ^ 1], 0);
+        if (e == hipSuccess)
+          e = timed(4, c->side, [&] {
+            return launch_deep(c->storage, c->ds, c->d_dtiles, (int)c->dtiles.size(), c->lanes,
+                               b1, c->side);
+          });
+        if (e == hipSuccess) e = hipEventRecord(c->ev_d[par], c->side);
+        if (e != hipSuccess) break;
+        pend_d = true;
+        have_f = true;
+        par ^= 1;
+      } else {
+        e = join();
+        if (e == hipSuccess)
+          e = timed(3, st, [&] {
+            return launch_interior(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), c->lanes,
+                                   b1, p1, st);
+          });
+        if (e == hipSuccess)
+          e = timed(0, st, [&] {
+            return launch_interior(c->storage, c->ds, c->d_etiles, (int)c->etiles.size(),
+                                   c->lanes, b2, p2, st);
+          });
+        have_f = false;
+      }
       prev = T;
       cur ^= 1;
       n += 2;
     } else {
       const StepBufs b1{cur, cur ^ 1, prev, (int)(n & 1), -1};
       const Prologue p1 = make_prologue(c, n > s);
-      e = timed(0, [&] {
-        return launch_interior(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), c->lanes, b1,
-                               p1, st);
-      });
+      e = join();
+      if (e == hipSuccess)
+        e = timed(0, st, [&] {
+          return launch_interior(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), c->lanes,
+                                 b1, p1, st);
+        });
+      have_f = false;
       prev = cur;
       cur ^= 1;
       n += 1;
     }
   }
+  if (e == hipSuccess) e = join();
   if (e != hipSuccess) return e;
   // The boundary work of step s + k - 1; the boundary nodes' u(t_{s+k+1})
   // goes to both buffers the next step may write.
   const int c_now = cur, p_now = prev;
-  e = timed(1, [&] {
+  e = timed(1, st, [&] {
     return launch_boundary(c->storage, c->ds, c->d_chunks, (int)c->chunks.size(), c->d_unodes,
                            c->d_gnodes, c->d_btasks, c->d_stasks, c_now, p_now, c_now ^ 1,
                            have_third(c) ? T : -1,
@@ -1080,7 +1223,7 @@ hipError_t enqueue_segment(lbm_ctx *c, int64_t s, int64_t k, int &cur, int &prev
   });
   if (e != hipSuccess) return e;
   if (c->sync_every > 0 && (s + k) % c->sync_every == 0) {
-    e = timed(2, [&] {
+    e = timed(2, st, [&] {
       return launch_sync(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), c->lanes, c_now,
                          st);
     });
@@ -1180,6 +1323,14 @@ lbm_status check_flag(lbm_ctx *c, bool wait) {
 
 lbm_status start(lbm_ctx *c) {
   if (c->started) return LBM_OK;
+  // side stream and events of overlapped pairs (default priority)
+  if (!c->side) {
+    HIP_TRY(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking), "side stream");
+    for (int i = 0; i < 2; i++) {
+      HIP_TRY(c, hipEventCreateWithFlags(&c->ev_f[i], hipEventDisableTiming), "pair event");
+      HIP_TRY(c, hipEventCreateWithFlags(&c->ev_d[i], hipEventDisableTiming), "pair event");
+    }
+  }
   if (c->bnd_dirty) {
     lbm_status st = upload_boundary(c);
     if (st) return st;
@@ -1236,6 +1387,14 @@ void lbm_destroy(lbm_ctx *c) {
   (void)hipStreamSynchronize(c->stream);
   drop_graph(c);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  if (c->side) {
+    (void)hipStreamSynchronize(c->side);
+    (void)hipStreamDestroy(c->side);
+  }
+  for (int i = 0; i < 2; i++) {
+    if (c->ev_f[i]) (void)hipEventDestroy(c->ev_f[i]);
+    if (c->ev_d[i]) (void)hipEventDestroy(c->ev_d[i]);
+  }
 
   if (c->flag_ev) (void)hipEventDestroy(c->flag_ev);
   if (c->h_flag) (void)hipHostFree(c->h_flag);
@@ -1508,13 +1667,15 @@ lbm_status lbm_create(const lbm_plate *plates, int32_t n_plates, lbm_storage sto
                                (int)std::lround(std::log2((double)std::max<int64_t>(1, c->n_body))));
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
-      c->lanes = it->second.lanes;
-      c->rows = it->second.rows;
-      c->order = it->second.order;
-      c->edge_rows = it->second.edge_rows;
-      c->edge_cols = it->second.edge_cols;
-      c->align = it->second.align;
-      c->two = it->second.steps == 2 ? 1 : 0;
+      const lbm_tiling &t = it->second.t;
+      c->lanes = t.lanes;
+      c->rows = t.rows;
+      c->order = t.order;
+      c->edge_rows = t.edge_rows;
+      c->edge_cols = t.edge_cols;
+      c->align = t.align;
+      c->two = t.steps == 2 ? 1 : 0;
+      c->overlap = it->second.overlap;
       if (c->two && ensure_third(c) != LBM_OK) c->two = 0;
     } else {
       // what the autotuner picks on 1024^2 (unaligned) and 4096^2 plates
@@ -1712,6 +1873,8 @@ lbm_status lbm_info(const lbm_ctx *c, lbm_info_t *info) {
   info->tile_steps = c->two ? 2 : 1;
   info->n_tiles = (int32_t)c->tiles.size();
   info->tile_edge_cols = c->edge_cols;
+  info->nodes_deep = c->two ? c->n_deep : 0;
+  info->overlap = (c->two && c->overlap) ? 1 : 0;
   return LBM_OK;
 }
 
@@ -1756,17 +1919,34 @@ lbm_status lbm_use_graphs(lbm_ctx *c, int32_t enable) {
   return LBM_OK;
 }
 
+lbm_status lbm_use_overlap(lbm_ctx *c, int32_t enable) {
+  if (!c) return LBM_E_INVAL;
+  if (c->overlap == (enable != 0)) return LBM_OK;
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "synchronize");
+  c->overlap = enable != 0;
+  // (the frame tiles are cut shorter with overlapped pairs)
+  build_tiles(c);
+  build_tile_tables(c);
+  lbm_status st = upload_tiles(c);
+  if (st) return st;
+  st = upload_tile_tables(c);
+  if (st) return st;
+  drop_graph(c);
+  return LBM_OK;
+}
+
 lbm_status lbm_profile(lbm_ctx *c, int64_t n, double *ms, int64_t *launches) {
   if (!c || n < 0 || !ms) return LBM_E_INVAL;
   lbm_status st = check_flag(c, false);
   if (st) return st;
   st = start(c);
   if (st) return st;
-  // Launches go back to back; the time between the events around a launch
-  // is its device time plus the gap to the previous launch's end.
+  // Launches on one stream go back to back; the time between the events
+  // around a launch is its device time plus the gap to the previous
+  // launch's end (on the side stream: to the end of what it waited for).
   LaunchRecorder rec;
-  double acc[4] = {0, 0, 0, 0};
-  int64_t cnt[4] = {0, 0, 0, 0};
+  double acc[5] = {0, 0, 0, 0, 0};
+  int64_t cnt[5] = {0, 0, 0, 0, 0};
   hipError_t e = hipSuccess;
   while (n > 0 && e == hipSuccess) {
     const int64_t k = segment_limit(c, c->step, n);
@@ -1776,16 +1956,19 @@ lbm_status lbm_profile(lbm_ctx *c, int64_t n, double *ms, int64_t *launches) {
       n -= k;
     }
   }
-  if (e == hipSuccess && !rec.ev.empty()) e = hipEventSynchronize(rec.ev.back());
-  for (size_t i = 0; e == hipSuccess && i < rec.kind.size(); i++) {
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  for (size_t i = 0; e == hipSuccess && i < rec.recs.size(); i++) {
     float t = 0;
-    (void)hipEventElapsedTime(&t, rec.ev[i], rec.ev[i + 1]);
-    acc[rec.kind[i]] += t;
-    cnt[rec.kind[i]] += 1;
+    (void)hipEventElapsedTime(&t, rec.recs[i].a, rec.recs[i].b);
+    acc[rec.recs[i].kind] += t;
+    cnt[rec.recs[i].kind] += 1;
   }
-  for (hipEvent_t ev : rec.ev) (void)hipEventDestroy(ev);
+  for (auto &r : rec.recs) {
+    if (r.a) (void)hipEventDestroy(r.a);
+    if (r.b) (void)hipEventDestroy(r.b);
+  }
   if (e != hipSuccess) return hip_fail(c, e, "profiled step");
-  for (int k = 0; k < 4; k++) {
+  for (int k = 0; k < 5; k++) {
     ms[k] = acc[k];
     if (launches) launches[k] = cnt[k];
   }
@@ -1803,9 +1986,9 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
   // single-step launch rewrites the boundary values of t_n and t_{n+1} with
   // the values they already hold and the t_{n+1} buffers from the t_n ones,
   // so repeating it leaves the state unchanged; so do the two launches of a
-  // two-step pair, repeated, except that the second one overwrites the side
-  // buffer the first one's prologue reads, which is saved and restored
-  // around them.  That needs the boundary populations of t_{n-1} in a
+  // two-step pair, repeated, except that the second one writes the side
+  // buffer the first one's prologue reads: the timed second launches write
+  // a scratch buffer in its place.  That needs the boundary populations of t_{n-1} in a
   // buffer neither launch writes and a state of t_n that does not come from
   // a synchronization (nor n = 0): otherwise one real step is taken first.
   const bool syncs_now = c->sync_every > 0 && c->step % c->sync_every == 0;
@@ -1819,14 +2002,15 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
   const int64_t n = c->step;
   const size_t side_bytes = (size_t)std::max<int64_t>(1, c->ds.nsec) * 10 *
                             (c->storage == LBM_STORE_F64 ? sizeof(double) : sizeof(float));
-  void *side_save = dev_alloc(c, side_bytes);
-  if (!side_save) return fail(c, LBM_E_NOMEM, "autotuner scratch allocation failed");
-  void *side_n = c->ds.side[n & 1];
-  HIP_TRY(c, hipMemcpyAsync(side_save, side_n, side_bytes, hipMemcpyDeviceToDevice, c->stream),
-          "side save");
+  void *side_scratch = dev_alloc(c, side_bytes);
+  if (!side_scratch) return fail(c, LBM_E_NOMEM, "autotuner scratch allocation failed");
   // two-step candidates only if the third state buffer fits in memory
   const bool had_third = have_third(c);
   const int max_steps = ensure_third(c) == LBM_OK ? 2 : 1;
+  // state of the timed second launches: all buffers as allocated by now,
+  // side buffer n & 1 replaced by the scratch buffer
+  DevState ds_b = c->ds;
+  ds_b.side[n & 1] = side_scratch;
   hipEvent_t e0, e1;
   HIP_TRY(c, hipEventCreate(&e0), "event");
   HIP_TRY(c, hipEventCreate(&e1), "event");
@@ -1842,8 +2026,50 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
     return t / steps;
   };
   const int cur = c->cur, prev = c->prev;
-  // interior time per step of one tiling (1e300 if it cannot run)
-  auto eval = [&](const lbm_tiling &T) -> double {
+  // Overlapped pairs as enqueue_segment runs them, repeated: the deep launch
+  // of a pair waits for the previous pair's first launch and the next pair's
+  // first launch for it.
+  auto time_overlapped = [&](const StepBufs &b1, const StepBufs &b2, const Prologue &p1,
+                             const Prologue &p2) -> double {
+    hipError_t e = hipEventRecord(c->ev_f[1], c->stream);
+    int par = 0;
+    bool pend = false;
+    auto pair = [&]() {
+      if (e == hipSuccess && pend) e = hipStreamWaitEvent(c->stream, c->ev_d[par ^ 1], 0);
+      if (e == hipSuccess)
+        e = launch_interior(c->storage, c->ds, c->d_ftiles, (int)c->ftiles.size(), c->lanes, b1,
+                            p1, c->stream);
+      if (e == hipSuccess) e = hipEventRecord(c->ev_f[par], c->stream);
+      if (e == hipSuccess)
+        e = launch_interior(c->storage, ds_b, c->d_etiles, (int)c->etiles.size(), c->lanes, b2,
+                            p2, c->stream);
+      if (e == hipSuccess) e = hipStreamWaitEvent(c->side, c->ev_f[par ^ 1], 0);
+      if (e == hipSuccess)
+        e = launch_deep(c->storage, c->ds, c->d_dtiles, (int)c->dtiles.size(), c->lanes, b1,
+                        c->side);
+      if (e == hipSuccess) e = hipEventRecord(c->ev_d[par], c->side);
+      pend = true;
+      par ^= 1;
+    };
+    auto join = [&]() {
+      if (e == hipSuccess && pend) e = hipStreamWaitEvent(c->stream, c->ev_d[par ^ 1], 0);
+      pend = false;
+    };
+    pair();
+    join();
+    if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+    for (int k = 0; k < steps && e == hipSuccess; k++) pair();
+    join();
+    if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e != hipSuccess) return 1e300;
+    float t = 0;
+    (void)hipEventElapsedTime(&t, e0, e1);
+    return t / steps;
+  };
+  // interior time per step of one tiling (1e300 if it cannot run), with
+  // overlapped pairs if ov
+  auto eval = [&](const lbm_tiling &T, bool ov) -> double {
     c->lanes = T.lanes;
     c->rows = T.rows;
     c->order = T.order;
@@ -1851,6 +2077,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
     c->edge_cols = T.edge_cols;
     c->align = T.align;
     c->two = T.steps == 2 ? 1 : 0;
+    c->overlap = ov;
     build_tiles(c);
     build_tile_tables(c);
     if (upload_tiles(c) != LBM_OK || upload_tile_tables(c) != LBM_OK) return 1e300;
@@ -1862,25 +2089,28 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
                                pro, c->stream);
       });
     }
+    // (two-step launches use buffer 2, in both state copies)
+    if (!have_third(c) || !ds_b.pop[2][0][0] || !ds_b.u[2][0]) return 1e300;
     const StepBufs b1{cur, 2, prev, (int)(n & 1), cur ^ 1};
     const StepBufs b2{2, cur ^ 1, cur, (int)((n + 1) & 1), -1};
     const Prologue pro2 = make_prologue(c, true);
-    const double t1 = time_launches([&] {
-      return launch_interior(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), T.lanes, b1,
-                             pro, c->stream);
-    });
-    const double t2 = time_launches([&] {
-      return launch_interior(c->storage, c->ds, c->d_etiles, (int)c->etiles.size(), T.lanes, b2,
+    if (ov && !c->dtiles.empty() && c->side) return 0.5 * time_overlapped(b1, b2, pro, pro2);
+    // one stream: the pair's two launches in turn, as enqueue_segment runs them
+    return 0.5 * time_launches([&] {
+      hipError_t e = launch_interior(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), T.lanes,
+                                     b1, pro, c->stream);
+      if (e != hipSuccess) return e;
+      return launch_interior(c->storage, ds_b, c->d_etiles, (int)c->etiles.size(), T.lanes, b2,
                              pro2, c->stream);
     });
-    (void)hipMemcpyAsync(side_n, side_save, side_bytes, hipMemcpyDeviceToDevice, c->stream);
-    return 0.5 * (t1 + t2);
   };
   double best = 1e300;
   lbm_tiling bt{c->lanes, c->rows, c->order, c->edge_rows, c->align, c->two ? 2 : 1, c->edge_cols};
+  const bool ov_user = c->overlap;  // the search keeps it; the end may turn it off
+  bool best_ov = ov_user;
   auto consider = [&](lbm_tiling T) {
     if (T.edge_rows >= T.rows) T.edge_rows = 0;
-    const double per = eval(T);
+    const double per = eval(T, ov_user);
     if (per < best) {
       best = per;
       bt = T;
@@ -1933,6 +2163,15 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
       consider(T);
     }
   }
+  // Overlapped pairs pay off where the single-step launches are short
+  // beside the deep tiles' work; else one stream.
+  if (ov_user && bt.steps == 2) {
+    const double one = eval(bt, false);
+    if (one < best) {
+      best = one;
+      best_ov = false;
+    }
+  }
   // The second launch of a pair wrote the boundary nodes' u(t_{n+2}) where
   // the next step expects u(t_{n+1}): recompute that from u(t_n).
   HIP_TRY(c, launch_boundary(c->storage, c->ds, c->d_chunks, (int)c->chunks.size(), c->d_unodes,
@@ -1941,7 +2180,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
                              (int)(n & 1), 0, c->stream),
           "boundary accelerations");
   (void)hipStreamSynchronize(c->stream);
-  dev_free(c, side_save);
+  dev_free(c, side_scratch);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   c->lanes = bt.lanes;
@@ -1951,6 +2190,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
   c->edge_cols = bt.edge_cols;
   c->align = bt.align;
   c->two = bt.steps == 2 ? 1 : 0;
+  c->overlap = best_ov;
   if (!c->two && !had_third) release_third(c);
   build_tiles(c);
   build_tile_tables(c);
@@ -1963,7 +2203,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto key = std::make_tuple(c->storage, c->ph.size() > 1 ? 1 : 0,
                                (int)std::lround(std::log2((double)std::max<int64_t>(1, c->n_body))));
-    g_tune_cache[key] = bt;
+    g_tune_cache[key] = TuneEntry{bt, best_ov};
   }
   if (best_ms) *best_ms = best;
   return LBM_OK;

@@ -12,6 +12,12 @@ namespace lbm {
 // the previous step's boundary work if pro.enabled.  lanes: 64, 128 or 256.
 hipError_t launch_interior(int storage, const DevState &s, const Tile *tiles, int ntiles,
                            int lanes, const StepBufs &b, const Prologue &pro, hipStream_t stream);
+// The two steps n, n + 1 of deep two-step tiles (no boundary, second-row or
+// single-step tile within two nodes; b.out2 >= 0): the launch may run beside
+// the other launches of the step, whose tiles it neither reads nor writes,
+// and is never the run's first step.
+hipError_t launch_deep(int storage, const DevState &s, const Tile *tiles, int ntiles, int lanes,
+                       const StepBufs &b, hipStream_t stream);
 // Boundary kernel over nchunks chunks (see k_boundary): the boundary work of
 // step n - 1 on the state of t_n in buffer bc (resets and second-row pulls
 // only if do_reset).

@@ -820,10 +820,13 @@ __device__ __forceinline__ int tile_index(int b, int q) { return (b & 7) * q + (
 // direction (i = -2, -1, h, h+1: halo rows).  The front row a of t_n is
 // collided while row a - 1 takes step n and row a - 2 step n + 1; each
 // stage hands its post-collision values to the x-neighbours through its own
-// triple-buffered LDS slots (exA: t_n, exB: t_{n+1}).
+// triple-buffered LDS slots (exA: t_n, exB: t_{n+1}).  deep: a launch of
+// deep tiles, never the run's first step (it does not read the step
+// counters, which the launches beside it may be writing).
 template <class CD, int TWL>
 __device__ void march2(const DevState &s, const Tile &t, const StepBufs &sb,
-                       typename CD::C (*exA)[X_N][TWL], typename CD::C (*exB)[X_N][TWL]) {
+                       typename CD::C (*exA)[X_N][TWL], typename CD::C (*exB)[X_N][TWL],
+                       bool deep) {
   using C = typename CD::C;
   using U = typename CD::U;
   using Slot = typename CD::Slot;
@@ -908,7 +911,8 @@ __device__ void march2(const DevState &s, const Tile &t, const StepBufs &sb,
   };
   // displacement-update coefficients of steps n (the run's first if n = 0)
   // and n + 1
-  const Kick<U> kickA = kick_of<U>(P, s.counter[sb.in] == 0ull), kickB = kick_of<U>(P, false);
+  const Kick<U> kickA = kick_of<U>(P, !deep && s.counter[sb.in] == 0ull),
+                kickB = kick_of<U>(P, false);
 
   // t_n stage registers: row a-2 (rho, behind pop), row a-1 (rho, f0, behind pop)
   C a2_rho[2], a2_fb[2], a1_rho[2], a1_f0[2], a1_fb[2];
@@ -1034,7 +1038,10 @@ __device__ void march2(const DevState &s, const Tile &t, const StepBufs &sb,
 
 // (FP64 with two-step tiles of one wave: at most 168 VGPRs, so that three
 // waves fit per SIMD; with more lanes per tile LDS allows only two.)
-template <int ST, int TWL, bool TWO>
+// DEEP: a launch of deep two-step tiles (no boundary or single-step tile
+// within two nodes), which runs beside the launches that own the step
+// counters and so leaves them alone.
+template <int ST, int TWL, bool TWO, bool DEEP>
 __global__ void __launch_bounds__(TWL)
     __attribute__((amdgpu_waves_per_eu((TWO && ST == LBM_STORE_F64 && TWL == 64) ? 3 : 1)))
     k_interior(DevState s, const Tile *__restrict__ tiles, int ntiles, int q, StepBufs sb,
@@ -1049,12 +1056,16 @@ __global__ void __launch_bounds__(TWL)
 
   // populations and u, du/dt of t_n in buffers sb.in, of t_{n+1} in sb.out
   const int pc = sb.in, pn = sb.out, uc = sb.in, un = sb.out;
-  if (blockIdx.x == 0 && threadIdx.x == 0) s.counter[un] = s.counter[uc] + 1ull;
+  if (!DEEP && blockIdx.x == 0 && threadIdx.x == 0) s.counter[un] = s.counter[uc] + 1ull;
   const int tix = tile_index(blockIdx.x, q);
   if (tix >= ntiles) return;
   const Tile t = tiles[tix];
+  if constexpr (DEEP) {
+    march2<CD, TWL>(s, t, sb, exs, exs + NS, true);
+    return;
+  }
   if (TWO && sb.out2 >= 0 && (t.flags & TF_TWO)) {
-    march2<CD, TWL>(s, t, sb, exs, exs + NS);
+    march2<CD, TWL>(s, t, sb, exs, exs + NS, false);
     return;
   }
   if (pro.enabled && t.chunk >= 0) prologue<CD>(s, pro, t.chunk, sb, (int)threadIdx.x, TWL);
@@ -1389,7 +1400,7 @@ __global__ void k_cons_err(DevState s, int plate, int b, double *err) {
 
 // --------------------------------------------------------------- launchers
 
-template <int ST, bool TWO>
+template <int ST, bool TWO, bool DEEP>
 static hipError_t launch_interior_t(const DevState &s, const Tile *tiles, int ntiles, int lanes,
                                     const StepBufs &b, const Prologue &pro, hipStream_t st) {
   // at least one block: block 0 advances the step counter
@@ -1397,16 +1408,16 @@ static hipError_t launch_interior_t(const DevState &s, const Tile *tiles, int nt
   const dim3 grid(8 * q);
   switch (lanes) {
     case 64:
-      hipLaunchKernelGGL((k_interior<ST, 64, TWO>), grid, dim3(64), 0, st, s, tiles, ntiles, q, b,
-                         pro);
+      hipLaunchKernelGGL((k_interior<ST, 64, TWO, DEEP>), grid, dim3(64), 0, st, s, tiles, ntiles,
+                         q, b, pro);
       break;
     case 128:
-      hipLaunchKernelGGL((k_interior<ST, 128, TWO>), grid, dim3(128), 0, st, s, tiles, ntiles, q,
-                         b, pro);
+      hipLaunchKernelGGL((k_interior<ST, 128, TWO, DEEP>), grid, dim3(128), 0, st, s, tiles,
+                         ntiles, q, b, pro);
       break;
     case 256:
-      hipLaunchKernelGGL((k_interior<ST, 256, TWO>), grid, dim3(256), 0, st, s, tiles, ntiles, q,
-                         b, pro);
+      hipLaunchKernelGGL((k_interior<ST, 256, TWO, DEEP>), grid, dim3(256), 0, st, s, tiles,
+                         ntiles, q, b, pro);
       break;
     default:
       return hipErrorInvalidValue;
@@ -1448,10 +1459,22 @@ static hipError_t launch_sync_t(const DevState &s, const Tile *tiles, int ntiles
 hipError_t launch_interior(int st, const DevState &s, const Tile *tiles, int ntiles, int lanes,
                            const StepBufs &b, const Prologue &pro, hipStream_t stream) {
   if (b.out2 >= 0) {
-    LBM_DISPATCH(st, return (launch_interior_t<ST, true>(s, tiles, ntiles, lanes, b, pro, stream)));
+    LBM_DISPATCH(st, return (launch_interior_t<ST, true, false>(s, tiles, ntiles, lanes, b, pro,
+                                                                stream)));
   } else {
-    LBM_DISPATCH(st, return (launch_interior_t<ST, false>(s, tiles, ntiles, lanes, b, pro, stream)));
+    LBM_DISPATCH(st, return (launch_interior_t<ST, false, false>(s, tiles, ntiles, lanes, b, pro,
+                                                                 stream)));
   }
+  return hipSuccess;
+}
+
+hipError_t launch_deep(int st, const DevState &s, const Tile *tiles, int ntiles, int lanes,
+                       const StepBufs &b, hipStream_t stream) {
+  if (ntiles <= 0) return hipSuccess;
+  if (b.out2 < 0) return hipErrorInvalidValue;
+  const Prologue none{};
+  LBM_DISPATCH(st, return (launch_interior_t<ST, true, true>(s, tiles, ntiles, lanes, b, none,
+                                                             stream)));
   return hipSuccess;
 }
 

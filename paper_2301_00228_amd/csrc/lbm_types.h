@@ -49,10 +49,12 @@ struct Tile {
   int32_t chunk;  // prologue work list (-1: none)
   int32_t dir;    // 1: the march visits the rows downwards
   // bits 0-3: export the t_{n+1} populations of the first/last owned column
-  // and row (W, E, S, N) of a two-step tile; bit 4: two-step tile
+  // and row (W, E, S, N) of a two-step tile; bit 4: two-step tile; bit 5:
+  // frame tile (a two-step tile with a node of a single-step tile in its
+  // two-node ring)
   int32_t flags;
 };
-enum { TF_EXP_W = 1, TF_EXP_E = 2, TF_EXP_S = 4, TF_EXP_N = 8, TF_TWO = 16 };
+enum { TF_EXP_W = 1, TF_EXP_E = 2, TF_EXP_S = 4, TF_EXP_N = 8, TF_TWO = 16, TF_FRAME = 32 };
 
 // Boundary node record (one per node with a missing neighbour).
 struct BndNode {

@@ -24,7 +24,7 @@ BC_NEUMANN, BC_DIRICHLET = 0, 1
 
 # Every entry point declared in include/lbm.h.
 EXPORTS = ["lbm_create", "lbm_set_bc", "lbm_step", "lbm_fields", "lbm_fields_device", "lbm_info",
-           "lbm_set_tiling", "lbm_autotune", "lbm_profile", "lbm_use_graphs", "lbm_destroy",
+           "lbm_set_tiling", "lbm_autotune", "lbm_profile", "lbm_use_graphs", "lbm_use_overlap", "lbm_destroy",
            "lbm_last_error", "lbm_version", "lbm_exact_cells", "lbm_consistency_error"]
 SHAPE_HOLE, SHAPE_BOUND = 0, 1
 
@@ -62,7 +62,8 @@ class lbm_info_t(C.Structure):
                 ("storage", C.c_int32), ("tile_lanes", C.c_int32), ("tile_rows", C.c_int32),
                 ("tile_order", C.c_int32), ("tile_edge_rows", C.c_int32),
                 ("tile_align", C.c_int32), ("tile_steps", C.c_int32), ("n_tiles", C.c_int32),
-                ("tile_edge_cols", C.c_int32)]
+                ("tile_edge_cols", C.c_int32), ("nodes_deep", C.c_int64), ("overlap", C.c_int32),
+                ("pad", C.c_int32)]
 
 
 class lbm_tiling(C.Structure):
@@ -110,6 +111,8 @@ def library():
     L.lbm_profile.argtypes = [vp, C.c_int64, dp, C.POINTER(C.c_int64)]
     L.lbm_use_graphs.restype = C.c_int
     L.lbm_use_graphs.argtypes = [vp, C.c_int32]
+    L.lbm_use_overlap.restype = C.c_int
+    L.lbm_use_overlap.argtypes = [vp, C.c_int32]
     L.lbm_destroy.restype = None
     L.lbm_destroy.argtypes = [vp]
     L.lbm_last_error.restype = C.c_char_p
@@ -316,14 +319,17 @@ class Context:
         return best.value
 
     def profile(self, n):
-        ms = (C.c_double * 4)()
-        cnt = (C.c_int64 * 4)()
+        ms = (C.c_double * 5)()
+        cnt = (C.c_int64 * 5)()
         self._check(library().lbm_profile(self._h, int(n), ms, cnt))
-        names = ("interior", "boundary", "sync", "two_step")
+        names = ("interior", "boundary", "sync", "two_step", "deep")
         return {k: (ms[i], cnt[i]) for i, k in enumerate(names)}
 
     def use_graphs(self, on=True):
         self._check(library().lbm_use_graphs(self._h, int(bool(on))))
+
+    def use_overlap(self, on=True):
+        self._check(library().lbm_use_overlap(self._h, int(bool(on))))
 
 
 def plate_dict(case):

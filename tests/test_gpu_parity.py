@@ -276,6 +276,37 @@ def test_two_step_batch_and_split_stepping_bitwise():
             assert np.array_equal(a[k], b[k]), k
 
 
+@pytest.mark.parametrize("storage", ["f64", "f16dev"])
+def test_overlapped_pairs_are_bitwise_identical(storage):
+    """Deep two-step tiles on a second stream beside the single-step
+    launches (the default) against one stream, eager and in graphs, on a
+    batch with clamped and free edges and on a periodic plate (no
+    single-step tiles: every two-step tile is deep)."""
+    batch = I.plate_batch(count=7, side_lo=20, side_hi=300, steps=0)
+    per = I.periodic_square(n=96)
+    for cases, tiling in [(batch, (64, 8, 0, 4, 0, 2, 4)), (batch, (64, 16, 1, 2, 16, 2, 8)),
+                          (batch, (128, 9, 2, 3, 0, 2, 4)), ([per], (64, 8, 0, 2, 0, 2))]:
+        outs = []
+        for overlap, graphs in [(False, False), (True, False), (True, True)]:
+            with lbm.context_for(cases, storage) as ctx:
+                ctx.set_tiling(*tiling)
+                ctx.use_overlap(overlap)
+                ctx.use_graphs(graphs)
+                ctx.step(1)
+                ctx.step(150)
+                info = ctx.info()
+                assert info["overlap"] == int(overlap)
+                assert 0 < info["nodes_deep"] <= info["nodes_two_step"]
+                prof = ctx.profile(20)
+                assert (prof["deep"][1] > 0) == overlap, prof
+                ctx.step(7)
+                outs.append([ctx.fields(p) for p in range(len(cases))])
+        for o in outs[1:]:
+            for a, b in zip(outs[0], o):
+                for k in FIELDS:
+                    assert np.array_equal(a[k], b[k]), (storage, tiling, k)
+
+
 @pytest.mark.parametrize("storage", ["f32", "f32dev", "f16dev", "bf16dev"])
 def test_reduced_storages_bitwise_across_tilings(storage):
     """The two-step pass applies the storage rounding to its intermediate
