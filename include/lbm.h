@@ -292,9 +292,10 @@ lbm_status lbm_set_tiling(lbm_ctx *ctx, const lbm_tiling *tiling);
  * leaves the state unchanged, except at step 0, at a synchronization step
  * and right after a two-step pair, where the autotuner first takes one real
  * step (steps_done grows by one; the trajectory is the same as without the
- * autotuner).  With overlapped pairs on (lbm_use_overlap) two-step
- * tilings are timed as overlapped pairs, and the best one is timed once
- * more on one stream; if that is faster, overlap is turned off.  Results are
+ * autotuner).  The search times one-stream pairs; with overlapped pairs
+ * allowed (lbm_use_overlap on, the default) the best two-step tiling is then
+ * timed overlapped (also with frame tiles of 2 and 4 rows), and overlap is
+ * kept on only if that is at least 3 % faster, else turned off.  Results are
  * cached per (storage, single/multiple plates, size bucket) for the life of
  * the process and picked up by later contexts.  best_ms (nullable) receives
  * the fastest interior time per step (for two-step tilings half the time of

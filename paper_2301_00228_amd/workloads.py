@@ -67,20 +67,28 @@ def timed(cases, storage, steps, warmup, tune=True, tiling=None):
     dt = time.perf_counter() - t0
     info = ctx.info()
     prof = ctx.profile(4)
-    # the launch that reads and writes every body node once: the first of a
-    # two-step pair, else the single-step launch
-    kind = "two_step" if prof["two_step"][1] > 0 else "interior"
+    # the dominant launch: with overlapped pairs the deep tiles' launch (two
+    # steps of its nodes), else the first of a two-step pair (every body node
+    # read and written once), else the single-step launch; achieved =
+    # lattice updates x bytes per update / launch time
+    kind = ("deep" if prof["deep"][1] > 0 else
+            "two_step" if prof["two_step"][1] > 0 else "interior")
     i_ms, i_n = prof[kind]
     b_ms, b_n = prof["boundary"]
     per = i_ms / i_n / 1e3
     nodes = info["nodes_in_body"]
-    achieved = nodes * info["bytes_per_update"] / per / 1e9
+    streamed = info["nodes_deep"] if kind == "deep" else nodes
+    achieved = streamed * info["bytes_per_update"] / per / 1e9
+
+    def avg_us(k):
+        return prof[k][0] / prof[k][1] * 1e3 if prof[k][1] else None
     res = {"storage": storage, "plates": info["n_plates"], "nodes": nodes, "steps": steps,
            "glups": nodes * steps / dt / 1e9, "ms_per_step": dt / steps * 1e3,
            "interior_kind": kind, "interior_us": per * 1e6, "interior_GBs": achieved,
            "interior_frac": achieved / HBM_PEAK_GBS, "boundary_us": b_ms / max(b_n, 1) * 1e3,
-           "second_launch_us": (prof["interior"][0] / max(prof["interior"][1], 1) * 1e3
-                                if kind == "two_step" else None),
+           "first_launch_us": avg_us("two_step"),
+           "second_launch_us": avg_us("interior") if kind != "interior" else None,
+           "overlap": bool(info["overlap"]), "deep_nodes": info["nodes_deep"],
            "two_step_nodes": info["nodes_two_step"],
            "bytes_per_lup": info["bytes_per_update"], "boundary_nodes": info["boundary_nodes"],
            "tile": [info["tile_lanes"], info["tile_rows"], info["tile_order"],
