@@ -2014,16 +2014,17 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
   hipEvent_t e0, e1;
   HIP_TRY(c, hipEventCreate(&e0), "event");
   HIP_TRY(c, hipEventCreate(&e1), "event");
+  int reps = steps;  // timed repetitions per candidate
   auto time_launches = [&](auto &&launch) -> double {
     hipError_t e = launch();
     (void)hipEventRecord(e0, c->stream);
-    for (int k = 0; k < steps && e == hipSuccess; k++) e = launch();
+    for (int k = 0; k < reps && e == hipSuccess; k++) e = launch();
     (void)hipEventRecord(e1, c->stream);
     (void)hipEventSynchronize(e1);
     if (e != hipSuccess) return 1e300;
     float t = 0;
     (void)hipEventElapsedTime(&t, e0, e1);
-    return t / steps;
+    return t / reps;
   };
   const int cur = c->cur, prev = c->prev;
   // Overlapped pairs as enqueue_segment runs them, repeated: the deep launch
@@ -2058,14 +2059,14 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
     pair();
     join();
     if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
-    for (int k = 0; k < steps && e == hipSuccess; k++) pair();
+    for (int k = 0; k < reps && e == hipSuccess; k++) pair();
     join();
     if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     if (e != hipSuccess) return 1e300;
     float t = 0;
     (void)hipEventElapsedTime(&t, e0, e1);
-    return t / steps;
+    return t / reps;
   };
   // interior time per step of one tiling (1e300 if it cannot run), with
   // overlapped pairs if ov
@@ -2116,6 +2117,19 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
       bt = T;
     }
   };
+  // Warm-up with the current tiling for at least 20 ms (the clocks ramp up
+  // from idle; on small plates the whole search takes well under a second),
+  // then at least 2 ms of launches per candidate.
+  {
+    lbm_tiling T0 = bt;
+    if (T0.steps == 2 && max_steps < 2) T0.steps = 1;
+    const double t0 = eval(T0, false);
+    if (t0 < 1e299) {
+      reps = std::max(steps, std::min(2000, (int)std::ceil(20.0 / (2.0 * t0))));
+      (void)eval(T0, false);
+      reps = std::max(steps, std::min(400, (int)std::ceil(2.0 / (2.0 * t0))));
+    }
+  }
   // Stage 1: steps per pass x lanes x rows, short tiles near boundaries,
   // strips aligned on large plates.
   const int a0 = c->n_body >= ((int64_t)4 << 20) ? 16 : 0;
@@ -2166,8 +2180,11 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
   // Overlapped pairs pay off where the single-step launches are short
   // beside the deep tiles' work: tried with the best tiling and frame tiles
   // of 2 and 4 rows, and kept if at least 3 % faster (the timed pairs lack
-  // the filling and draining of the overlap at each synchronization).
-  if (ov_user && bt.steps == 2) {
+  // the filling and draining of the overlap at each synchronization).  Both
+  // sides are timed over at least 5 ms of pairs.
+  if (ov_user && bt.steps == 2 && best < 1e299) {
+    reps = std::max(steps, std::min(400, (int)std::ceil(5.0 / (2.0 * best))));
+    best = eval(bt, false);
     const lbm_tiling b0 = bt;
     double ov_best = 1e300;
     lbm_tiling ov_t = b0;
