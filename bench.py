@@ -80,11 +80,7 @@ def cpu_baseline(case, budget_s=12.0, single_s=3.0):
     all its OpenMP threads and with one."""
     from oracle import oracle
 
-    p = oracle.OraclePlate(case.nx, case.ny, mask=case.mask, periodic=case.periodic,
-                           lam=case.lam, mu=case.mu, rho=case.rho, dh=case.dh, dt=case.dt,
-                           sync_every=case.sync_every, u0=case.u0, v0=case.v0)
-    for bc in case.bcs:
-        p.set_bc(bc.xy, bc.kind, bc.val, cell=bc.cell, knots=bc.knots)
+    p = oracle_plate(case)
     nodes = case.in_body_nodes()
     threads = oracle.threads()
 
@@ -112,6 +108,41 @@ def cpu_baseline(case, budget_s=12.0, single_s=3.0):
             "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS")}
 
 
+def oracle_plate(case):
+    from oracle import oracle
+
+    p = oracle.OraclePlate(case.nx, case.ny, mask=case.mask, periodic=case.periodic,
+                           lam=case.lam, mu=case.mu, rho=case.rho, dh=case.dh, dt=case.dt,
+                           sync_every=case.sync_every, u0=case.u0, v0=case.v0)
+    for bc in case.bcs:
+        p.set_bc(bc.xy, bc.kind, bc.val, cell=bc.cell, knots=bc.knots)
+    return p
+
+
+def cpu_workload_samples():
+    """The FP64 oracle on sampled subsets of the batched workloads (all its
+    OpenMP threads): 4 plates of the 256-plate batch x 100 steps, and one
+    4096^2 plate of the 1.2 G-node batch x 20 steps."""
+    from paper_2301_00228_amd import inputs
+
+    out = {}
+    for name, cases, steps in (("batch256", inputs.plate_batch(count=256, steps=0)[:4], 100),
+                               ("large", inputs.large_batch(count=1, strip=None, steps=0), 20)):
+        lup, secs = 0, 0.0
+        for case in cases:
+            p = oracle_plate(case)
+            p.step(1)
+            t0 = time.perf_counter()
+            p.step(steps)
+            secs += time.perf_counter() - t0
+            lup += case.in_body_nodes() * steps
+            del p
+        out[name] = {"value": lup / secs / 1e6, "unit": "MLUPS",
+                     "sample": f"{len(cases)} plate(s) ({', '.join(f'{c.nx}x{c.ny}' for c in cases)})"
+                               f" x {steps} steps, {secs:.1f} s"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,6 +150,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--cpu-workloads", action="store_true",
+                    help="also time the oracle on samples of the batched workloads")
     ap.add_argument("--profile-steps", type=int, default=200)
     ap.add_argument("--storage", default="f64", help="storage of the headline run")
     ap.add_argument("--tiling", default="", metavar="L,R,O,E,A,S[,W]",
@@ -272,6 +305,8 @@ def main():
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(case)
+        if args.cpu_workloads:
+            cpu["workload_samples"] = cpu_workload_samples()
 
     line = {
         "metric": METRIC, "value": round(glups, 4), "unit": "GLUPS", "n_gpus": 1, "steps": K,
