@@ -307,6 +307,28 @@ def test_overlapped_pairs_are_bitwise_identical(storage):
                     assert np.array_equal(a[k], b[k]), (storage, tiling, k)
 
 
+def test_overlap_switched_mid_run_and_odd_step_counts():
+    """Overlap switched on and off between lbm_step calls of odd lengths
+    (pairs cut at synchronizations and at the end of a call), against one
+    call on one stream."""
+    cases = I.plate_batch(count=4, side_lo=120, side_hi=260, steps=0)
+    with lbm.context_for(cases) as ctx:
+        ctx.set_tiling(64, 8, 0, 4, 0, 2, 4)
+        ctx.use_overlap(False)
+        ctx.step(211)
+        base = [ctx.fields(p) for p in range(len(cases))]
+    with lbm.context_for(cases) as ctx:
+        ctx.set_tiling(64, 8, 0, 4, 0, 2, 4)
+        for n, ov in ((1, True), (2, True), (37, True), (10, False), (51, True), (3, False),
+                      (64, True), (43, True)):
+            ctx.use_overlap(ov)
+            ctx.step(n)
+        got = [ctx.fields(p) for p in range(len(cases))]
+    for a, b in zip(base, got):
+        for k in FIELDS:
+            assert np.array_equal(a[k], b[k]), k
+
+
 @pytest.mark.parametrize("storage", ["f32", "f32dev", "f16dev", "bf16dev"])
 def test_reduced_storages_bitwise_across_tilings(storage):
     """The two-step pass applies the storage rounding to its intermediate
