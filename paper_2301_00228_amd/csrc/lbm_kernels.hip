@@ -659,15 +659,17 @@ __device__ void second_row_task(const DevState &s, const PlateDev &P, const STas
 // halo ring (resets and pulls into buffer sb.in, which the march then reads,
 // from the populations of t_{n-1} in buffer sb.prev and the side buffer
 // sb.sp) and the next boundary accelerations of the tile's own boundary
-// nodes (u buffer sb.in to sb.out).  Gradients of u(t_n) go through a
-// per-tile scratch area.
+// nodes (u buffer sb.in to sb.out).  Gradients of u(t_n) go to LDS (lds,
+// lds_bytes: the march's exchange buffer, unused until the march starts) if
+// they fit, else to a per-tile scratch area in global memory.
 template <class CD>
 __device__ void prologue(const DevState &s, const Prologue &pro, int chunk, const StepBufs &sb,
-                         int tid, int nthreads) {
+                         int tid, int nthreads, void *lds, int lds_bytes) {
   using U = typename CD::U;
   const TileChunk ch = pro.chunks[chunk];
   const PlateDev P = s.plates[ch.plate];
-  U *grad = static_cast<U *>(pro.grad) + (int64_t)4 * ch.g0;
+  const bool in_lds = (int64_t)(ch.g1 - ch.g0) * 4 * (int64_t)sizeof(U) <= (int64_t)lds_bytes;
+  U *grad = in_lds ? static_cast<U *>(lds) : static_cast<U *>(pro.grad) + (int64_t)4 * ch.g0;
   const U *ux = static_cast<const U *>(s.u[sb.in][0]);
   const U *uy = static_cast<const U *>(s.u[sb.in][1]);
   for (int g = ch.g0 + tid; g < ch.g1; g += nthreads) {
@@ -1051,7 +1053,7 @@ __global__ void __launch_bounds__(TWL)
   using U = typename CD::U;
   using Slot = typename CD::Slot;
   constexpr int NS = ex_rows(TWL);
-  __shared__ C exs[TWO ? 2 * NS : NS][X_N][TWL];
+  __shared__ __align__(16) C exs[TWO ? 2 * NS : NS][X_N][TWL];
   C(*ex)[X_N][TWL] = exs;
 
   // populations and u, du/dt of t_n in buffers sb.in, of t_{n+1} in sb.out
@@ -1068,7 +1070,8 @@ __global__ void __launch_bounds__(TWL)
     march2<CD, TWL>(s, t, sb, exs, exs + NS, false);
     return;
   }
-  if (pro.enabled && t.chunk >= 0) prologue<CD>(s, pro, t.chunk, sb, (int)threadIdx.x, TWL);
+  if (pro.enabled && t.chunk >= 0)
+    prologue<CD>(s, pro, t.chunk, sb, (int)threadIdx.x, TWL, exs, (int)sizeof(exs));
   const PlateDev P = s.plates[t.plate];
   const Kick<U> kick = kick_of<U>(P, s.counter[sb.in] == 0ull);
   const int lane = threadIdx.x;
