@@ -294,7 +294,8 @@ lbm_status lbm_set_tiling(lbm_ctx *ctx, const lbm_tiling *tiling);
  * step (steps_done grows by one; the trajectory is the same as without the
  * autotuner).  The search times one-stream pairs; with overlapped pairs
  * allowed (lbm_use_overlap on, the default) the best two-step tiling is then
- * timed overlapped (also with frame tiles of 2 and 4 rows), and overlap is
+ * timed overlapped (also with frame tiles of 2 and 4 rows) against one
+ * stream, both captured in HIP graphs as lbm_step runs them, and overlap is
  * kept on only if that is at least 3 % faster, else turned off.  Results are
  * cached per (storage, single/multiple plates, size bucket) for the life of
  * the process and picked up by later contexts.  best_ms (nullable) receives

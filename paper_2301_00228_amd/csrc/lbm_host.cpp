@@ -2015,62 +2015,45 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
   HIP_TRY(c, hipEventCreate(&e0), "event");
   HIP_TRY(c, hipEventCreate(&e1), "event");
   int reps = steps;  // timed repetitions per candidate
-  auto time_launches = [&](auto &&launch) -> double {
-    hipError_t e = launch();
-    (void)hipEventRecord(e0, c->stream);
-    for (int k = 0; k < reps && e == hipSuccess; k++) e = launch();
-    (void)hipEventRecord(e1, c->stream);
-    (void)hipEventSynchronize(e1);
+  // Time body(st, k), which enqueues k repetitions of the timed launches on
+  // stream st: eagerly (one repetition to warm up, then `reps` timed on the
+  // library stream) or captured in a graph of `reps` repetitions (launched
+  // once to warm up and once timed), as lbm_step runs its steps.
+  auto time_body = [&](auto &&body, bool graph) -> double {
+    hipError_t e = hipSuccess;
+    if (!graph) {
+      e = body(c->stream, 1);
+      if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+      if (e == hipSuccess) e = body(c->stream, reps);
+      if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+    } else {
+      if (!c->cap_stream) e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) return 1e300;
+      const hipError_t eb = body(c->cap_stream, reps);
+      hipGraph_t g = nullptr;
+      e = hipStreamEndCapture(c->cap_stream, &g);
+      if (eb != hipSuccess) e = eb;
+      hipGraphExec_t ge = nullptr;
+      if (e == hipSuccess) e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+      if (e == hipSuccess) e = hipGraphLaunch(ge, c->stream);
+      if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+      if (e == hipSuccess) e = hipGraphLaunch(ge, c->stream);
+      if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      if (ge) (void)hipGraphExecDestroy(ge);
+      if (g) (void)hipGraphDestroy(g);
+    }
     if (e != hipSuccess) return 1e300;
     float t = 0;
     (void)hipEventElapsedTime(&t, e0, e1);
     return t / reps;
   };
   const int cur = c->cur, prev = c->prev;
-  // Overlapped pairs as enqueue_segment runs them, repeated: the deep launch
-  // of a pair waits for the previous pair's first launch and the next pair's
-  // first launch for it.
-  auto time_overlapped = [&](const StepBufs &b1, const StepBufs &b2, const Prologue &p1,
-                             const Prologue &p2) -> double {
-    hipError_t e = hipEventRecord(c->ev_f[1], c->stream);
-    int par = 0;
-    bool pend = false;
-    auto pair = [&]() {
-      if (e == hipSuccess && pend) e = hipStreamWaitEvent(c->stream, c->ev_d[par ^ 1], 0);
-      if (e == hipSuccess)
-        e = launch_interior(c->storage, c->ds, c->d_ftiles, (int)c->ftiles.size(), c->lanes, b1,
-                            p1, c->stream);
-      if (e == hipSuccess) e = hipEventRecord(c->ev_f[par], c->stream);
-      if (e == hipSuccess)
-        e = launch_interior(c->storage, ds_b, c->d_etiles, (int)c->etiles.size(), c->lanes, b2,
-                            p2, c->stream);
-      if (e == hipSuccess) e = hipStreamWaitEvent(c->side, c->ev_f[par ^ 1], 0);
-      if (e == hipSuccess)
-        e = launch_deep(c->storage, c->ds, c->d_dtiles, (int)c->dtiles.size(), c->lanes, b1,
-                        c->side);
-      if (e == hipSuccess) e = hipEventRecord(c->ev_d[par], c->side);
-      pend = true;
-      par ^= 1;
-    };
-    auto join = [&]() {
-      if (e == hipSuccess && pend) e = hipStreamWaitEvent(c->stream, c->ev_d[par ^ 1], 0);
-      pend = false;
-    };
-    pair();
-    join();
-    if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
-    for (int k = 0; k < reps && e == hipSuccess; k++) pair();
-    join();
-    if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
-    if (e == hipSuccess) e = hipEventSynchronize(e1);
-    if (e != hipSuccess) return 1e300;
-    float t = 0;
-    (void)hipEventElapsedTime(&t, e0, e1);
-    return t / reps;
-  };
   // interior time per step of one tiling (1e300 if it cannot run), with
-  // overlapped pairs if ov
-  auto eval = [&](const lbm_tiling &T, bool ov) -> double {
+  // overlapped pairs if ov, timed eagerly or in a graph
+  auto eval = [&](const lbm_tiling &T, bool ov, bool graph) -> double {
     c->lanes = T.lanes;
     c->rows = T.rows;
     c->order = T.order;
@@ -2085,25 +2068,58 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
     const Prologue pro = make_prologue(c, with_prologue);
     if (T.steps == 1) {
       const StepBufs sb{cur, cur ^ 1, prev, (int)(n & 1), -1};
-      return time_launches([&] {
-        return launch_interior(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), T.lanes, sb,
-                               pro, c->stream);
-      });
+      return time_body([&](hipStream_t st, int k) {
+        hipError_t e = hipSuccess;
+        for (int i = 0; i < k && e == hipSuccess; i++)
+          e = launch_interior(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), T.lanes, sb,
+                              pro, st);
+        return e;
+      }, graph);
     }
     // (two-step launches use buffer 2, in both state copies)
     if (!have_third(c) || !ds_b.pop[2][0][0] || !ds_b.u[2][0]) return 1e300;
     const StepBufs b1{cur, 2, prev, (int)(n & 1), cur ^ 1};
     const StepBufs b2{2, cur ^ 1, cur, (int)((n + 1) & 1), -1};
     const Prologue pro2 = make_prologue(c, true);
-    if (ov && !c->dtiles.empty() && c->side) return 0.5 * time_overlapped(b1, b2, pro, pro2);
+    if (ov && !c->dtiles.empty() && c->side) {
+      // overlapped pairs as enqueue_segment runs them: the deep launch of a
+      // pair waits for the previous pair's first launch and the next pair's
+      // first launch for it
+      return 0.5 * time_body([&](hipStream_t st, int k) {
+        hipError_t e = hipEventRecord(c->ev_f[1], st);
+        int par = 0;
+        for (int i = 0; i < k && e == hipSuccess; i++) {
+          if (i > 0) e = hipStreamWaitEvent(st, c->ev_d[par ^ 1], 0);
+          if (e == hipSuccess)
+            e = launch_interior(c->storage, c->ds, c->d_ftiles, (int)c->ftiles.size(), c->lanes,
+                                b1, pro, st);
+          if (e == hipSuccess) e = hipEventRecord(c->ev_f[par], st);
+          if (e == hipSuccess)
+            e = launch_interior(c->storage, ds_b, c->d_etiles, (int)c->etiles.size(), c->lanes,
+                                b2, pro2, st);
+          if (e == hipSuccess) e = hipStreamWaitEvent(c->side, c->ev_f[par ^ 1], 0);
+          if (e == hipSuccess)
+            e = launch_deep(c->storage, c->ds, c->d_dtiles, (int)c->dtiles.size(), c->lanes, b1,
+                            c->side);
+          if (e == hipSuccess) e = hipEventRecord(c->ev_d[par], c->side);
+          par ^= 1;
+        }
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, c->ev_d[par ^ 1], 0);
+        return e;
+      }, graph);
+    }
     // one stream: the pair's two launches in turn, as enqueue_segment runs them
-    return 0.5 * time_launches([&] {
-      hipError_t e = launch_interior(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), T.lanes,
-                                     b1, pro, c->stream);
-      if (e != hipSuccess) return e;
-      return launch_interior(c->storage, ds_b, c->d_etiles, (int)c->etiles.size(), T.lanes, b2,
-                             pro2, c->stream);
-    });
+    return 0.5 * time_body([&](hipStream_t st, int k) {
+      hipError_t e = hipSuccess;
+      for (int i = 0; i < k && e == hipSuccess; i++) {
+        e = launch_interior(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), T.lanes, b1, pro,
+                            st);
+        if (e == hipSuccess)
+          e = launch_interior(c->storage, ds_b, c->d_etiles, (int)c->etiles.size(), T.lanes, b2,
+                              pro2, st);
+      }
+      return e;
+    }, graph);
   };
   double best = 1e300;
   lbm_tiling bt{c->lanes, c->rows, c->order, c->edge_rows, c->align, c->two ? 2 : 1, c->edge_cols};
@@ -2111,7 +2127,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
   bool best_ov = false;
   auto consider = [&](lbm_tiling T) {
     if (T.edge_rows >= T.rows) T.edge_rows = 0;
-    const double per = eval(T, false);
+    const double per = eval(T, false, false);
     if (per < best) {
       best = per;
       bt = T;
@@ -2123,10 +2139,10 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
   {
     lbm_tiling T0 = bt;
     if (T0.steps == 2 && max_steps < 2) T0.steps = 1;
-    const double t0 = eval(T0, false);
+    const double t0 = eval(T0, false, false);
     if (t0 < 1e299) {
       reps = std::max(steps, std::min(2000, (int)std::ceil(20.0 / (2.0 * t0))));
-      (void)eval(T0, false);
+      (void)eval(T0, false, false);
       reps = std::max(steps, std::min(400, (int)std::ceil(2.0 / (2.0 * t0))));
     }
   }
@@ -2181,10 +2197,11 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
   // beside the deep tiles' work: tried with the best tiling and frame tiles
   // of 2 and 4 rows, and kept if at least 3 % faster (the timed pairs lack
   // the filling and draining of the overlap at each synchronization).  Both
-  // sides are timed over at least 5 ms of pairs.
+  // sides are timed in graphs of at least 5 ms of pairs, as lbm_step runs
+  // them (eager launches of overlapped pairs pay for more API calls).
   if (ov_user && bt.steps == 2 && best < 1e299) {
     reps = std::max(steps, std::min(400, (int)std::ceil(5.0 / (2.0 * best))));
-    best = eval(bt, false);
+    best = eval(bt, false, true);
     const lbm_tiling b0 = bt;
     double ov_best = 1e300;
     lbm_tiling ov_t = b0;
@@ -2195,7 +2212,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
       if (std::find(rows_tried.begin(), rows_tried.end(), T.edge_rows) != rows_tried.end())
         continue;
       rows_tried.push_back(T.edge_rows);
-      const double per = eval(T, true);
+      const double per = eval(T, true, true);
       if (per < ov_best) {
         ov_best = per;
         ov_t = T;
