@@ -330,7 +330,10 @@ lbm_status lbm_use_graphs(lbm_ctx *ctx, int32_t enable);
  * runs beside this pair's single-step launches; the frame tiles take theirs
  * in the first launch of the pair, with the single-step tiles' first step.
  * The launches beside each other read and write disjoint nodes: the results
- * are bitwise the same either way.  Invalidates captured step graphs. */
+ * are bitwise the same either way.  Synchronizes the stream; rebuilds the
+ * tiles (frame tiles are cut to edge_rows rows with overlap); invalidates
+ * captured step graphs.  Errors: LBM_E_INVAL (NULL ctx), LBM_E_NOMEM,
+ * LBM_E_DEVICE. */
 lbm_status lbm_use_overlap(lbm_ctx *ctx, int32_t enable);
 
 void lbm_destroy(lbm_ctx *ctx);
