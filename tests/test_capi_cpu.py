@@ -96,3 +96,9 @@ def test_consistency_error_needs_a_context():
     err = np.zeros(4)
     assert L.lbm_consistency_error(None, 0, err.ctypes.data_as(lbm.C.POINTER(lbm.C.c_double))) \
         == lbm.E_INVAL
+
+
+def test_switches_need_a_context():
+    L = lbm.library()
+    assert L.lbm_use_overlap(None, 1) == lbm.E_INVAL
+    assert L.lbm_use_graphs(None, 1) == lbm.E_INVAL
