@@ -307,6 +307,34 @@ def test_overlapped_pairs_are_bitwise_identical(storage):
                     assert np.array_equal(a[k], b[k]), (storage, tiling, k)
 
 
+@pytest.mark.parametrize("storage", ["f32", "f32dev", "bf16dev"])
+def test_overlapped_pairs_other_storages_and_modes(storage):
+    """Overlap on against off, bitwise: plates with elliptic holes, no
+    synchronization, the central-difference update, and a plate periodic
+    in x beside clamped ones."""
+    big = I.plate_with_ellipse_hole(nx=260, ny=200, hole=(131.2, 99.7, 30.0, 17.0, 0.4), a0_phi=0.9999,
+                                    steps=0, sync_every=0, sigma=5.0)
+    cd = I.plate_with_ellipse_hole(nx=230, ny=190, hole=(80.3, 120.1, 22.0, 11.0, 1.2), a0_phi=0.9999,
+                                   steps=0, sync_every=0, sigma=5.0)
+    cd.integrator = 1
+    per = I.clamped_plate(n=200, ny=150, sigma=5.0, steps=0, sync_every=0)
+    per.periodic = (True, False)
+    per.bcs = []
+    outs = []
+    for ov in (False, True):
+        with lbm.context_for([big, cd, per], storage) as ctx:
+            ctx.set_tiling(64, 8, 0, 4, 0, 2, 8)
+            ctx.use_overlap(ov)
+            assert ctx.info()["nodes_deep"] > 0
+            ctx.step(3)
+            ctx.step(120)
+            outs.append([ctx.fields(p) for p in range(3)])
+    for a, b in zip(*outs):
+        for k in FIELDS:
+            assert np.isfinite(a[k]).all()
+            assert np.array_equal(a[k], b[k]), (storage, k)
+
+
 def test_overlap_switched_mid_run_and_odd_step_counts():
     """Overlap switched on and off between lbm_step calls of odd lengths
     (pairs cut at synchronizations and at the end of a call), against one
