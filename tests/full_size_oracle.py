@@ -1,7 +1,7 @@
 """The precision workload at full size against the FP64 CPU oracle.
 
 Not collected by pytest (an oracle run over 8192^2 nodes takes many minutes);
-run it by hand:
+run it by hand.  Side by side on the GPU host:
 
     python -u tests/full_size_oracle.py --n 8192 --radius 1024 --steps 2000 \
         --every 250 --out result.jsonl
@@ -12,6 +12,13 @@ context and the oracle advance side by side, and at each checkpoint one JSON
 line gives, per storage, the relative max-norm and relative L2 error of e,
 omega and u against the oracle.  A line is written (and flushed) as soon as
 its checkpoint is reached, so a run cut short still leaves every earlier one.
+
+Or in two parts on two machines, compared on sampled rows (every
+`--row-every`-th row, all columns) after all steps:
+
+    python -u tests/full_size_oracle.py --rows gpu --out gpu_rows/       # GPU machine
+    python -u tests/full_size_oracle.py --rows oracle --out oracle_rows/ # any host
+    python tests/full_size_oracle.py --compare gpu_rows/ oracle_rows/
 """
 import argparse
 import json
@@ -39,6 +46,70 @@ def errors(got, ref):
     return out
 
 
+def sampled_rows(n, row_every):
+    return np.arange(0, n, row_every)
+
+
+def save_rows(path, fields, rows, meta):
+    np.savez(path, e=fields["e"][rows], omega=fields["omega"][rows], u=fields["u"][:, rows],
+             rows=rows, meta=json.dumps(meta))
+
+
+def rows_part(a):
+    """One side of the two-machine comparison: every storage on the GPU, or
+    the oracle, after all steps; the sampled rows to .npz files."""
+    os.makedirs(a.out, exist_ok=True)
+    case = I.plate_with_hole(n=a.n, radius=a.radius, steps=a.steps)
+    rows = sampled_rows(a.n, a.row_every)
+    meta = {"n": a.n, "radius": a.radius, "steps": a.steps, "row_every": a.row_every,
+            "nodes": case.in_body_nodes()}
+    if a.rows == "gpu":
+        import torch
+        torch.cuda.set_device(0)
+        for st in a.storages.split(","):
+            t0 = time.perf_counter()
+            with lbm.context_for(case, st) as ctx:
+                for done in range(0, a.steps, 250):
+                    ctx.step(min(250, a.steps - done))
+                    print(f"gpu {st} step {min(done + 250, a.steps)}", flush=True)
+                f = ctx.fields(0, want=FIELDS)
+            save_rows(os.path.join(a.out, f"{st}.npz"), f, rows,
+                      dict(meta, storage=st, seconds=time.perf_counter() - t0))
+            print(f"gpu {st}: {time.perf_counter() - t0:.1f} s", flush=True)
+        return
+    orc = OraclePlate(case.nx, case.ny, mask=case.mask, periodic=case.periodic, lam=case.lam,
+                      mu=case.mu, rho=case.rho, dh=case.dh, dt=case.dt,
+                      sync_every=case.sync_every, u0=case.u0, v0=case.v0, e0=case.e0,
+                      w0=case.w0, integrator=getattr(case, "integrator", 0))
+    for bc in case.bcs:
+        orc.set_bc(bc.xy, bc.kind, bc.val, cell=bc.cell, knots=bc.knots)
+    del case
+    t0 = time.perf_counter()
+    for done in range(0, a.steps, 50):
+        orc.step(min(50, a.steps - done))
+        el = time.perf_counter() - t0
+        print(f"oracle step {min(done + 50, a.steps)}: {el:.0f} s", flush=True)
+    save_rows(os.path.join(a.out, "oracle.npz"), orc.fields(), rows,
+              dict(meta, storage="oracle", threads=threads(), seconds=time.perf_counter() - t0))
+
+
+def compare(gpu_dir, oracle_dir):
+    ref = np.load(os.path.join(oracle_dir, "oracle.npz"))
+    rm = json.loads(str(ref["meta"]))
+    out = {"n": rm["n"], "radius": rm["radius"], "steps": rm["steps"],
+           "sampled_rows": int(len(ref["rows"])), "row_every": rm["row_every"],
+           "oracle_threads": rm["threads"], "oracle_s": rm["seconds"]}
+    for f in sorted(os.listdir(gpu_dir)):
+        if not f.endswith(".npz"):
+            continue
+        g = np.load(os.path.join(gpu_dir, f))
+        gm = json.loads(str(g["meta"]))
+        assert (gm["n"], gm["steps"], gm["row_every"]) == (rm["n"], rm["steps"], rm["row_every"])
+        assert np.array_equal(g["rows"], ref["rows"])
+        out[gm["storage"]] = errors({k: g[k] for k in FIELDS}, {k: ref[k] for k in FIELDS})
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--n", type=int, default=8192)
@@ -46,10 +117,22 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--every", type=int, default=250)
     ap.add_argument("--storages", default="f64,f32dev,f16dev,bf16dev")
-    ap.add_argument("--out", required=True)
+    ap.add_argument("--out")
     ap.add_argument("--max-seconds", type=float, default=0.0,
                     help="stop before a checkpoint the oracle would not reach in this wall time")
+    ap.add_argument("--rows", choices=("gpu", "oracle"),
+                    help="one side of the two-machine comparison on sampled rows")
+    ap.add_argument("--row-every", type=int, default=256)
+    ap.add_argument("--compare", nargs=2, metavar=("GPU_DIR", "ORACLE_DIR"))
     a = ap.parse_args()
+    if a.compare:
+        compare(*a.compare)
+        return
+    if a.rows:
+        rows_part(a)
+        return
+    if not a.out:
+        ap.error("--out is required")
 
     import torch
     torch.cuda.set_device(0)
