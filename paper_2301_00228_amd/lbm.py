@@ -319,6 +319,9 @@ class Context:
         return best.value
 
     def profile(self, n):
+        """lbm_profile: {kind: (ms, launches)} over n eager steps, kinds
+        interior (single-step), boundary, sync, two_step (first launch of a
+        pair), deep (deep tiles of overlapped pairs)."""
         ms = (C.c_double * 5)()
         cnt = (C.c_int64 * 5)()
         self._check(library().lbm_profile(self._h, int(n), ms, cnt))
@@ -326,9 +329,12 @@ class Context:
         return {k: (ms[i], cnt[i]) for i, k in enumerate(names)}
 
     def use_graphs(self, on=True):
+        """lbm_use_graphs: captured HIP graphs in step (default on)."""
         self._check(library().lbm_use_graphs(self._h, int(bool(on))))
 
     def use_overlap(self, on=True):
+        """lbm_use_overlap: deep two-step tiles on a second stream beside the
+        single-step launches (default on; bitwise the same results)."""
         self._check(library().lbm_use_overlap(self._h, int(bool(on))))
 
 
