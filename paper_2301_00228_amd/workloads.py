@@ -37,7 +37,7 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
 
 
-def timed(cases, storage, steps, warmup, tune=True, tiling=None):
+def timed(cases, storage, steps, warmup, tune=True, tiling=None, overlap=None):
     import torch
     t0 = time.perf_counter()
     ctx = lbm.context_for(cases, storage)
@@ -46,6 +46,8 @@ def timed(cases, storage, steps, warmup, tune=True, tiling=None):
     ctx.step(2)
     if tiling:
         ctx.set_tiling(*tiling)
+        if overlap is not None:
+            ctx.use_overlap(overlap)
     elif tune:
         t1 = time.perf_counter()
         t_set = time.perf_counter()
@@ -108,6 +110,8 @@ def main():
                     help="storage of the reference run for the error ('' = no error)")
     ap.add_argument("--tiling", default="", metavar="L,R,O,E,A,S,W",
                     help="interior tiling instead of the autotuner's pick")
+    ap.add_argument("--overlap", type=int, choices=(0, 1), default=None,
+                    help="with --tiling: overlapped pairs on (1) or off (0); default on")
     ap.add_argument("--ref-plates", type=int, default=0,
                     help="compare only the first N plates and the last one (0 = all)")
     args = ap.parse_args()
@@ -118,7 +122,8 @@ def main():
     print(f"building {args.workload}", file=sys.stderr, flush=True)
     cases = cases_for(args.workload, args.warmup + args.steps)
     tiling = [int(v) for v in args.tiling.split(",")] if args.tiling else None
-    ctx, res = timed(cases, args.storage, args.steps, args.warmup, tiling=tiling)
+    overlap = None if args.overlap is None else bool(args.overlap)
+    ctx, res = timed(cases, args.storage, args.steps, args.warmup, tiling=tiling, overlap=overlap)
     res["workload"] = args.workload
     print(json.dumps(res), flush=True)
     if args.ref:
