@@ -31,8 +31,12 @@
  *    towards a missing neighbour is not used;
  *  - Dirichlet acceleration uses u*(t+dt) (so that u(t+dt) = u*);
  *  - correction-f (eq. correction-f) uses the flux of the populations stored
- *    at the boundary node at time t;
- *  - eq. LBE_mod: equilibrium of the averaged populations' own moments;
+ *    at the boundary node at time t (reading R1; orc_set_readings switches
+ *    to R2: the flux of the post-collision populations that stream into the
+ *    boundary node from its body neighbours, a missing neighbour adding 0);
+ *  - eq. LBE_mod: equilibrium of the averaged populations' own moments
+ *    (reading M1; orc_set_readings switches to M2: the equilibrium of the
+ *    boundary node's populations at t);
  *  - velocity update of eq. integration uses only the acceleration at t
  *    (orc_set_integrator(p, 1) switches to the central difference, Newmark
  *    gamma = 1/2, for the variant study);
@@ -71,6 +75,8 @@ struct orc_plate {
   double a[2], a0[2];
   int sync_every;
   int integrator; /* 0: eq. integration as printed; 1: central difference */
+  int flux_reading; /* eq. correction-f: 0 = R1, 1 = R2 (see file header) */
+  int eq_reading;   /* eq. LBE_mod: 0 = M1, 1 = M2 (see file header) */
   int64_t n; /* completed steps */
   int started;
   uint8_t *in;  /* 1 = in body */
@@ -311,6 +317,15 @@ int orc_set_integrator(orc_plate *p, int integrator) {
   return ORC_OK;
 }
 
+int orc_set_readings(orc_plate *p, int flux_reading, int eq_reading) {
+  if (!p || p->started || (flux_reading != 0 && flux_reading != 1) ||
+      (eq_reading != 0 && eq_reading != 1))
+    return ORC_E_INVAL;
+  p->flux_reading = flux_reading;
+  p->eq_reading = eq_reading;
+  return ORC_OK;
+}
+
 int orc_set_bc(orc_plate *p, int n, const int32_t *xy, const uint8_t *kind, const double *val,
                const double *cell, int n_knots, const double *knots) {
   if (!p || n < 0 || (n > 0 && (!xy || !kind || !val)) || n_knots < 0 || (n_knots > 0 && !knots))
@@ -489,7 +504,11 @@ static void one_step(orc_plate *p) {
 
   /* 4. Boundary nodes: phi, psi from finite differences of u(t+dt)
    *    (eq. psi_phi_at_bound), populations by eq. correction-f with the
-   *    flux J(x_k, t) of the populations stored there at time t. */
+   *    flux J(x_k, t): R1, that of the populations stored there at time t;
+   *    R2, that of the populations the LBE streams in from the body
+   *    neighbours x_k - c^alpha dt (their post-collision populations at t,
+   *    eq. LBE with dt/tau = 2), a missing neighbour contributing 0. */
+  const double omega = dt / (0.5 * dt);
 #pragma omp parallel for schedule(static)
   for (int j = 0; j < ny; j++)
     for (int i = 0; i < nx; i++) {
@@ -498,15 +517,30 @@ static void one_step(orc_plate *p) {
       double dv, cu;
       div_curl(p, p->ux, p->uy, i, j, &dv, &cu);
       double fld[2] = {dv, cu};
-      for (int fl = 0; fl < 2; fl++)
-        for (int al = 0; al < NQ; al++)
-          p->fn[fl][al][k] = feq(p, fl, al, fld[fl], p->jx[fl][k], p->jy[fl][k]);
+      for (int fl = 0; fl < 2; fl++) {
+        double jx = p->jx[fl][k], jy = p->jy[fl][k];
+        if (p->flux_reading == 1) {
+          jx = 0.0;
+          jy = 0.0;
+          for (int al = 1; al < NQ; al++) {
+            long ky = nbr(p, i, j, -CX[al], -CY[al]);
+            if (ky < 0) continue;
+            double fy = p->f[fl][al][ky];
+            double fe = feq(p, fl, al, p->rho[fl][ky], p->jx[fl][ky], p->jy[fl][ky]);
+            double fs = fy - omega * (fy - fe);
+            jx += (p->c * CX[al]) * fs;
+            jy += (p->c * CY[al]) * fs;
+          }
+        }
+        for (int al = 0; al < NQ; al++) p->fn[fl][al][k] = feq(p, fl, al, fld[fl], jx, jy);
+      }
     }
 
   /* 5. Interior nodes: LBE (eq. LBE, dt/tau = 2) pulled from the upwind
    *    neighbour; a population that leaves a boundary node is transported by
-   *    eq. LBE_mod with the time-averaged boundary populations. */
-  const double omega = dt / (0.5 * dt);
+   *    eq. LBE_mod with the time-averaged boundary populations, collided
+   *    towards the equilibrium of their own moments (M1) or of the boundary
+   *    node's populations at t (M2). */
 #pragma omp parallel for schedule(static)
   for (int j = 0; j < ny; j++)
     for (int i = 0; i < nx; i++) {
@@ -518,7 +552,11 @@ static void one_step(orc_plate *p) {
           double fhat[NQ], rho, jx, jy;
           if (p->cls[ks] == CLS_BND) {
             for (int q = 0; q < NQ; q++) fhat[q] = 0.5 * (p->fn[fl][q][ks] + p->f[fl][q][ks]);
-            moments(p, fhat, &rho, &jx, &jy);
+            if (p->eq_reading == 1) {
+              rho = p->rho[fl][ks]; jx = p->jx[fl][ks]; jy = p->jy[fl][ks];
+            } else {
+              moments(p, fhat, &rho, &jx, &jy);
+            }
           } else {
             for (int q = 0; q < NQ; q++) fhat[q] = p->f[fl][q][ks];
             rho = p->rho[fl][ks]; jx = p->jx[fl][ks]; jy = p->jy[fl][ks];

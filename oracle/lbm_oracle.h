@@ -47,6 +47,18 @@ orc_plate *orc_create(int nx, int ny, const uint8_t *mask, int periodic_x, int p
                       int sync_every, const double *u0, const double *v0,
                       const double *e0, const double *w0, int *err);
 
+/* Displacement update: 0 = eq. integration as printed (default), 1 = central
+ * difference with the velocity kept at half steps.  Before the first step. */
+int orc_set_integrator(orc_plate *p, int integrator);
+/* Readings of two points the paper leaves open (Sec. 3.1), before the first
+ * step.  flux_reading, the flux J(x_k, t) of eq. correction-f: 0 = R1, that
+ * of the populations stored at the boundary node at t (default); 1 = R2,
+ * that of the post-collision populations streaming into it from its body
+ * neighbours (a missing neighbour contributes 0).  eq_reading, the
+ * equilibrium of eq. LBE_mod: 0 = M1, that of the time-averaged populations'
+ * own moments (default); 1 = M2, that of the boundary node's populations at
+ * t. */
+int orc_set_readings(orc_plate *p, int flux_reading, int eq_reading);
 /* Boundary data for n boundary nodes.  xy: 2n ints (i, j).  kind: n bytes,
  * 0 = Neumann, 1 = Dirichlet.  val: 2n doubles, Dirichlet u* or Neumann
  * integrated external force over the cell's external boundary (per unit
@@ -54,9 +66,6 @@ orc_plate *orc_create(int nx, int ny, const uint8_t *mask, int periodic_x, int p
  * the mask-derived cell.  knots: n_knots (t, g) pairs giving a piecewise
  * linear amplitude g(t) (clamped outside the knot range) that multiplies val;
  * NULL means g = 1.  Listing a node that is not a boundary node is an error. */
-/* Displacement update: 0 = eq. integration as printed (default), 1 = central
- * difference with the velocity kept at half steps.  Before the first step. */
-int orc_set_integrator(orc_plate *p, int integrator);
 int orc_set_bc(orc_plate *p, int n, const int32_t *xy, const uint8_t *kind, const double *val,
                const double *cell, int n_knots, const double *knots);
 

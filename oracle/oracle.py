@@ -38,6 +38,8 @@ def lib():
                                  C.POINTER(C.c_int)]
         L.orc_set_integrator.restype = C.c_int
         L.orc_set_integrator.argtypes = [C.c_void_p, C.c_int]
+        L.orc_set_readings.restype = C.c_int
+        L.orc_set_readings.argtypes = [C.c_void_p, C.c_int, C.c_int]
         L.orc_set_bc.restype = C.c_int
         L.orc_set_bc.argtypes = [C.c_void_p, C.c_int, ip, up, dp, dp, C.c_int, dp]
         L.orc_step.restype = C.c_int
@@ -78,7 +80,8 @@ class OraclePlate:
     """One plate advanced by the oracle."""
 
     def __init__(self, nx, ny, mask=None, periodic=(False, False), lam=1.0, mu=1.0, rho=1.0,
-                 dh=1.0, dt=0.5, sync_every=0, u0=None, v0=None, e0=None, w0=None, integrator=0):
+                 dh=1.0, dt=0.5, sync_every=0, u0=None, v0=None, e0=None, w0=None, integrator=0,
+                 readings=(0, 0)):
         L = lib()
         self.nx, self.ny = int(nx), int(ny)
         shp, vshp = (self.ny, self.nx), (2, self.ny, self.nx)
@@ -99,6 +102,12 @@ class OraclePlate:
             rc = L.orc_set_integrator(self._h, int(integrator))
             if rc:
                 raise OracleError(rc, "orc_set_integrator")
+        if tuple(readings) != (0, 0):
+            # (flux reading of eq. correction-f: 0 R1 / 1 R2, equilibrium of
+            # eq. LBE_mod: 0 M1 / 1 M2)
+            rc = L.orc_set_readings(self._h, int(readings[0]), int(readings[1]))
+            if rc:
+                raise OracleError(rc, "orc_set_readings")
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -181,7 +190,8 @@ def run_case(case, steps=None):
     p = OraclePlate(case.nx, case.ny, mask=case.mask, periodic=case.periodic, lam=case.lam,
                     mu=case.mu, rho=case.rho, dh=case.dh, dt=case.dt, sync_every=case.sync_every,
                     u0=case.u0, v0=case.v0, e0=case.e0, w0=case.w0,
-                    integrator=getattr(case, "integrator", 0))
+                    integrator=getattr(case, "integrator", 0),
+                    readings=getattr(case, "readings", (0, 0)))
     for bc in case.bcs:
         p.set_bc(bc.xy, bc.kind, bc.val, cell=bc.cell, knots=bc.knots)
     p.step(case.steps if steps is None else steps)

@@ -63,6 +63,11 @@ class Case:
     shapes: list = field(default_factory=list)
     # displacement update: 0 as printed in the paper, 1 central difference
     integrator: int = 0
+    # readings of Sec. 3.1: (flux of eq. correction-f: 0 = R1 the boundary
+    # node's own populations, 1 = R2 the populations streamed in from its
+    # body neighbours; equilibrium of eq. LBE_mod: 0 = M1 the averaged
+    # populations' own, 1 = M2 the boundary node's populations at t)
+    readings: Tuple[int, int] = (0, 0)
 
     def in_body_nodes(self) -> int:
         return int(self.nx * self.ny if self.mask is None else int(np.count_nonzero(self.mask)))

@@ -542,3 +542,158 @@ def test_central_difference_keeps_dirichlet_nodes_on_the_prescribed_path():
         g = min(s * dt / (30 * dt), 1.0)
         got = u[:, bc.xy[:, 1], bc.xy[:, 0]].T
         assert np.abs(got - g * ustar).max() < 8 * np.finfo(float).eps * 2e-3
+
+
+# ------------------------------------------------ second-row rule (LBE_mod)
+
+CX5 = (0, 1, 0, -1, 0)
+CY5 = (0, 0, 1, 0, -1)
+OPP5 = (0, 3, 4, 1, 2)
+
+
+def _moving_boundary_run(readings, pre_steps=25):
+    """A holed plate whose boundary fields change every step: a pulse next
+    to the hole, the left edge clamped to a ramped displacement and a ramped
+    traction on the hole rim.  Returns the plate's populations and fields
+    just before and just after one step taken after pre_steps steps."""
+    nx, ny = 24, 20
+    mask = _holed_mask(nx, ny)
+    nu = 0.3
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    g = 1e-3 * np.exp(-((x - 14.0) ** 2 + (y - 12.0) ** 2) / (2 * 2.0 ** 2))
+    u0 = np.stack([0.6 * g, -0.8 * g]) * mask[None]
+    u0[:, :, 0] = 0.0
+    dt = I.time_step(nu, 0.99)
+    p = OraclePlate(nx, ny, mask=mask, lam=I.lame_lambda(nu), dt=dt, u0=u0, readings=readings)
+    left = np.array([(0, j) for j in range(ny)], np.int32)
+    ramp = np.array([[0.0, 0.0], [40 * dt, 1.0]])
+    p.set_bc(left, np.ones(ny, np.uint8), np.tile([1e-4, -2e-4], (ny, 1)), knots=ramp)
+    rim = np.array([(i, j) for i, j in _boundary_nodes(mask) if 0 < i < nx - 1 and 0 < j < ny - 1],
+                   np.int32)
+    rng = np.random.default_rng(7)
+    p.set_bc(rim, np.zeros(len(rim), np.uint8), rng.uniform(-1e-4, 1e-4, (len(rim), 2)),
+             knots=ramp)
+    p.step(pre_steps)
+    before = (p.pops(), p.fields())
+    p.step(1)
+    after = (p.pops(), p.fields())
+    return p, mask, before, after
+
+
+def _pulls_from_boundary(p, mask):
+    """(field, alpha, interior node x, boundary node y = x - c^alpha) for every
+    population an interior node pulls from a boundary neighbour."""
+    cls = p.classes()
+    ny, nx = mask.shape
+    out = []
+    for j in range(ny):
+        for i in range(nx):
+            if cls[j, i] != 1:
+                continue
+            for al in range(1, 5):
+                yi, yj = i - CX5[al], j - CY5[al]
+                if cls[yj, yi] == 2:
+                    out.append((al, (i, j), (yi, yj)))
+    return out
+
+
+@pytest.mark.parametrize("eq_reading", [0, 1])
+def test_second_row_pull_is_the_time_averaged_boundary_population(eq_reading):
+    """Eq. LBE_mod at a second-row node x pulling population alpha from a
+    boundary node y.  Under reading R1 the flux of correction-f at y is that of
+    y's own populations, 0 from the start (J = 0 initially), so y's
+    populations are f_eq(phi_B, 0) at every step and the average f~ of
+    those at t and t + dt is again an equilibrium: with M1 (equilibrium of
+    f~'s own moments) the collision leaves it unchanged and x receives
+    a phi_B-average, a (phi_B(y, t) + phi_B(y, t + dt)) / 2; with M2
+    (equilibrium of y's populations at t) it receives 2 a phi_B(y, t) - that
+    average.  phi_B is read as the field output (sum of populations) before
+    and after the step."""
+    p, mask, (f0, d0), (f1, d1) = _moving_boundary_run((0, eq_reading))
+    q = p.params()
+    a = (q["a_phi"], q["a_psi"])
+    pulls = _pulls_from_boundary(p, mask)
+    assert len(pulls) > 40
+    worst, moved = 0.0, 0.0
+    for fl, key in ((0, "e"), (1, "omega")):
+        scale = np.abs(d1[key]).max()
+        for al, (i, j), (yi, yj) in pulls:
+            b0, b1 = d0[key][yj, yi], d1[key][yj, yi]
+            avg = a[fl] * 0.5 * (b0 + b1)
+            want = avg if eq_reading == 0 else 2 * a[fl] * b0 - avg
+            worst = max(worst, abs(f1[fl, al, j, i] - want) / scale)
+            moved = max(moved, a[fl] * abs(b1 - b0) / scale)
+    assert worst < 1e-13, worst
+    # the boundary field moves: dropping the average (or the rule) or
+    # swapping M1 and M2 changes the pulled values by ~moved
+    assert moved > 1e-9, moved
+
+
+def test_boundary_flux_under_reading_r1_stays_zero():
+    """Reading R1 of eq. correction-f: the flux at a boundary node is that of
+    its own populations, which start at rest, so it stays exactly 0."""
+    p, mask, _, (f1, _) = _moving_boundary_run((0, 0))
+    bn = p.classes() == 2
+    assert np.all(f1[:, 1][:, bn] == f1[:, 3][:, bn])
+    assert np.all(f1[:, 2][:, bn] == f1[:, 4][:, bn])
+
+
+@pytest.mark.parametrize("eq_reading", [0, 1])
+def test_boundary_flux_under_reading_r2_is_the_streamed_in_flux(eq_reading):
+    """Reading R2 of eq. correction-f: the flux at boundary node x_k is the
+    first moment of the post-collision populations that stream into it from
+    its body neighbours y = x_k - c^alpha (a missing one adds 0).  With
+    dt/tau = 2 the post-collision population alpha of any node is
+    2 a rho(y) - f^{-alpha}(y) (the collision reflects the non-equilibrium
+    part), so the expected flux follows from the populations and fields at t
+    alone.  The second-row pull then follows eq. LBE_mod with f~ the average
+    of y's populations at t and t + dt: f~ is an equilibrium (a linear
+    combination of equilibria with the same weights), so under M1 the pull is
+    f~^alpha, under M2 2 f^alpha(y, t) - f~^alpha."""
+    p, mask, (f0, d0), (f1, d1) = _moving_boundary_run((1, eq_reading))
+    q = p.params()
+    a = (q["a_phi"], q["a_psi"])
+    c = q["c"]
+    cls = p.classes()
+    ny, nx = mask.shape
+    worst_j, big_j = 0.0, 0.0
+    for fl, key in ((0, "e"), (1, "omega")):
+        jscale = c * max(np.abs(f0[fl, 1] - f0[fl, 3]).max(), np.abs(f0[fl, 2] - f0[fl, 4]).max())
+        for j in range(ny):
+            for i in range(nx):
+                if cls[j, i] != 2:
+                    continue
+                jx = jy = 0.0
+                for al in range(1, 5):
+                    yi, yj = i - CX5[al], j - CY5[al]
+                    if not (0 <= yi < nx and 0 <= yj < ny) or not mask[yj, yi]:
+                        continue
+                    g = 2 * a[fl] * d0[key][yj, yi] - f0[fl, OPP5[al], yj, yi]
+                    jx += c * CX5[al] * g
+                    jy += c * CY5[al] * g
+                gx = c * (f1[fl, 1, j, i] - f1[fl, 3, j, i])
+                gy = c * (f1[fl, 2, j, i] - f1[fl, 4, j, i])
+                worst_j = max(worst_j, abs(gx - jx) / jscale, abs(gy - jy) / jscale)
+                big_j = max(big_j, abs(jx), abs(jy))
+    assert worst_j < 1e-12, worst_j
+    assert big_j > 1e-7, big_j
+    worst = 0.0
+    for fl, key in ((0, "e"), (1, "omega")):
+        scale = np.abs(d1[key]).max()
+        for al, (i, j), (yi, yj) in _pulls_from_boundary(p, mask):
+            avg = 0.5 * (f0[fl, al, yj, yi] + f1[fl, al, yj, yi])
+            want = avg if eq_reading == 0 else 2 * f0[fl, al, yj, yi] - avg
+            worst = max(worst, abs(f1[fl, al, j, i] - want) / scale)
+    assert worst < 1e-13, worst
+
+
+def test_readings_are_set_before_the_first_step_only():
+    p = OraclePlate(8, 8, dt=0.3)
+    p.step(1)
+    with pytest.raises(OracleError):
+        lib_set = __import__("oracle.oracle", fromlist=["lib"]).lib().orc_set_readings
+        rc = lib_set(p._h, 1, 0)
+        if rc:
+            raise OracleError(rc, "orc_set_readings")
+    with pytest.raises(OracleError):
+        OraclePlate(8, 8, dt=0.3, readings=(2, 0))
