@@ -212,6 +212,22 @@ lbm_status lbm_fields(lbm_ctx *ctx, int32_t plate, double *e, double *omega, dou
 lbm_status lbm_fields_device(lbm_ctx *ctx, int32_t plate, double *e, double *omega, double *u,
                              double *v);
 
+/* As lbm_fields, for callers that cannot allocate device memory (code that
+ * must not call hipMalloc: tight serving loops, harnesses that forbid it).
+ * The fields are staged in a fixed 48 MiB area of device memory that the
+ * library holds on each GPU it runs on until the process ends (looked up at
+ * lbm_create); the call allocates nothing.  The requested outputs of the
+ * plate must fit that area: (n_e + n_omega + 2 n_u + 2 n_v) * nx * ny * 8
+ * bytes <= 48 MiB, where n_x is 1 if that output is requested (all four:
+ * nx * ny <= 1,048,576); otherwise LBM_E_INVAL with the sizes in the error
+ * text.  Every context on one GPU shares the area, so calls that overlap in
+ * time on one GPU (from several threads) race; serialize them.  Each call
+ * writes every element it copies back, so nothing from an earlier call is
+ * read.  Synchronizes the stream.  Other errors as lbm_fields; LBM_E_DEVICE
+ * if the area could not be located at lbm_create. */
+lbm_status lbm_fields_noalloc(lbm_ctx *ctx, int32_t plate, double *e, double *omega, double *u,
+                              double *v);
+
 /* Consistency error of Sec. 4 (tension example, the error measure e(x, t)):
  * for each body node of one plate the 2-norm of (omega - (curl u).e_z,
  * e - div u), where omega and e are the sums of the rotation and dilatation

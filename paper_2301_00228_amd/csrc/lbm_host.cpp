@@ -157,6 +157,9 @@ struct lbm_ctx {
   uint8_t *d_cls = nullptr;
   double *d_scratch = nullptr;
   size_t scratch_bytes = 0;
+  // fixed staging area of lbm_fields_noalloc on this context's device
+  double *na_stage = nullptr;
+  hipError_t na_err = hipSuccess;
   size_t tiles_cap = 0;
 
   int64_t step = 0;
@@ -1529,6 +1532,13 @@ lbm_status lbm_create(const lbm_plate *plates, int32_t n_plates, lbm_storage sto
     delete c;
     return fail(nullptr, LBM_E_DEVICE, "hipGetDevice failed");
   }
+  {
+    // the staging area of lbm_fields_noalloc, looked up once per device
+    // with the device current; a failure only disables that entry point
+    void *p = nullptr;
+    c->na_err = noalloc_staging(c->device, &p);
+    c->na_stage = static_cast<double *>(p);
+  }
   auto bail = [&](lbm_status st, const std::string &m) {
     g_create_error = m;
     lbm_destroy(c);
@@ -1819,6 +1829,44 @@ lbm_status lbm_fields(lbm_ctx *c, int32_t plate, double *e, double *w, double *u
   double *de = c->d_scratch, *dw = de + n, *du = dw + n, *dv = du + 2 * n;
   lbm_status st = lbm_fields_device(c, plate, e ? de : nullptr, w ? dw : nullptr,
                                     u ? du : nullptr, v ? dv : nullptr);
+  if (st) return st;
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "synchronize");
+  if (e) HIP_TRY(c, hipMemcpy(e, de, n * sizeof(double), hipMemcpyDeviceToHost), "copy e");
+  if (w) HIP_TRY(c, hipMemcpy(w, dw, n * sizeof(double), hipMemcpyDeviceToHost), "copy omega");
+  if (u) HIP_TRY(c, hipMemcpy(u, du, 2 * n * sizeof(double), hipMemcpyDeviceToHost), "copy u");
+  if (v) HIP_TRY(c, hipMemcpy(v, dv, 2 * n * sizeof(double), hipMemcpyDeviceToHost), "copy v");
+  int flag = 0;
+  HIP_TRY(c, hipMemcpy(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost), "copy flag");
+  if (flag) c->nonfinite = true;
+  return check_flag(c, true);
+}
+
+lbm_status lbm_fields_noalloc(lbm_ctx *c, int32_t plate, double *e, double *w, double *u,
+                              double *v) {
+  if (!c) return LBM_E_INVAL;
+  if (plate < 0 || plate >= (int)c->ph.size()) return fail(c, LBM_E_INVAL, "bad plate index");
+  if (!c->na_stage)
+    return fail(c, LBM_E_DEVICE, std::string("fixed staging area unavailable: ") +
+                                     hipGetErrorString(c->na_err));
+  const PlateHost &h = c->ph[plate];
+  const size_t n = (size_t)h.nx * h.ny;
+  const size_t need = ((e ? n : 0) + (w ? n : 0) + (u ? 2 * n : 0) + (v ? 2 * n : 0)) * sizeof(double);
+  if (need > kNoAllocBytes)
+    return fail(c, LBM_E_INVAL,
+                "lbm_fields_noalloc: the requested fields of plate " + std::to_string(plate) +
+                    " need " + std::to_string(need) + " bytes of staging; the fixed area holds " +
+                    std::to_string(kNoAllocBytes));
+  double *q = c->na_stage;
+  double *de = e ? q : nullptr;
+  q += e ? n : 0;
+  double *dw = w ? q : nullptr;
+  q += w ? n : 0;
+  double *du = u ? q : nullptr;
+  q += u ? 2 * n : 0;
+  double *dv = v ? q : nullptr;
+  // every element of the requested outputs is written by the field kernel
+  // (0 outside the body), so nothing left by an earlier call is read
+  lbm_status st = lbm_fields_device(c, plate, de, dw, du, dv);
   if (st) return st;
   HIP_TRY(c, hipStreamSynchronize(c->stream), "synchronize");
   if (e) HIP_TRY(c, hipMemcpy(e, de, n * sizeof(double), hipMemcpyDeviceToHost), "copy e");

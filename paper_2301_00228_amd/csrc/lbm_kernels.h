@@ -37,4 +37,10 @@ hipError_t launch_fields(int storage, const DevState &s, int plate, int64_t node
 hipError_t launch_cons_err(int storage, const DevState &s, int plate, int64_t nodes, int b,
                            double *err, hipStream_t stream);
 
+// Size of the fixed device staging area of lbm_fields_noalloc (per GPU).
+constexpr size_t kNoAllocBytes = (size_t)48 << 20;
+// Device address of that area on `device`, which must be the current
+// device; looked up on the first call per device and kept (thread-safe).
+hipError_t noalloc_staging(int device, void **ptr);
+
 }  // namespace lbm

@@ -35,6 +35,8 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "../../include/lbm.h"
 #include "lbm_kernels.h"
 #include "lbm_types.h"
@@ -1536,6 +1538,39 @@ hipError_t launch_cons_err(int st, const DevState &s, int plate, int64_t nodes, 
   LBM_DISPATCH(st, hipLaunchKernelGGL((k_cons_err<ST>), dim3((unsigned)blocks), dim3(256), 0,
                                       stream, s, plate, b, err));
   return hipGetLastError();
+}
+
+// ------------------------------------------- fixed staging of lbm_fields_noalloc
+//
+// Device memory of the library's own, for callers that cannot allocate: a
+// file-scope array that every context on a GPU shares (each GPU holds its
+// own copy, at its own address, until the process ends).  Host code never
+// passes the array's name to a kernel or a copy (on the host it only stands
+// for the symbol); it uses the device address hipGetSymbolAddress returns,
+// looked up once per device with that device current.
+static __device__ __align__(256) double scratch[kNoAllocBytes / sizeof(double)];
+
+namespace {
+std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+void *g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+bool g_scratch_done[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_staging(int device, void **ptr) {
+  *ptr = nullptr;
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_done[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    g_scratch_err[device] = e;
+    g_scratch_ptr[device] = e == hipSuccess ? p : nullptr;
+    g_scratch_done[device] = true;
+  }
+  *ptr = g_scratch_ptr[device];
+  return g_scratch_err[device];
 }
 
 }  // namespace lbm

@@ -25,7 +25,8 @@ BC_NEUMANN, BC_DIRICHLET = 0, 1
 # Every entry point declared in include/lbm.h.
 EXPORTS = ["lbm_create", "lbm_set_bc", "lbm_step", "lbm_fields", "lbm_fields_device", "lbm_info",
            "lbm_set_tiling", "lbm_autotune", "lbm_profile", "lbm_use_graphs", "lbm_use_overlap", "lbm_destroy",
-           "lbm_last_error", "lbm_version", "lbm_exact_cells", "lbm_consistency_error"]
+           "lbm_last_error", "lbm_version", "lbm_exact_cells", "lbm_consistency_error",
+           "lbm_fields_noalloc"]
 SHAPE_HOLE, SHAPE_BOUND = 0, 1
 
 
@@ -99,6 +100,8 @@ def library():
     L.lbm_step.argtypes = [vp, C.c_int64]
     L.lbm_fields.restype = C.c_int
     L.lbm_fields.argtypes = [vp, C.c_int32, dp, dp, dp, dp]
+    L.lbm_fields_noalloc.restype = C.c_int
+    L.lbm_fields_noalloc.argtypes = [vp, C.c_int32, dp, dp, dp, dp]
     L.lbm_fields_device.restype = C.c_int
     L.lbm_fields_device.argtypes = [vp, C.c_int32, vp, vp, vp, vp]
     L.lbm_info.restype = C.c_int
@@ -284,6 +287,19 @@ class Context:
         v = np.zeros((2, ny, nx)) if "v" in want else None
         self._check(library().lbm_fields(self._h, int(plate), _dptr(e), _dptr(w), _dptr(u),
                                          _dptr(v)))
+        out = {"e": e, "omega": w, "u": u, "v": v}
+        return {k: out[k] for k in want}
+
+    def fields_noalloc(self, plate=0, want=("e", "omega", "u", "v")):
+        """lbm_fields_noalloc: as fields(), staged through the library's fixed
+        device area (no device allocation)."""
+        nx, ny = self.shapes[plate]
+        e = np.zeros((ny, nx)) if "e" in want else None
+        w = np.zeros((ny, nx)) if "omega" in want else None
+        u = np.zeros((2, ny, nx)) if "u" in want else None
+        v = np.zeros((2, ny, nx)) if "v" in want else None
+        self._check(library().lbm_fields_noalloc(self._h, int(plate), _dptr(e), _dptr(w),
+                                                 _dptr(u), _dptr(v)))
         out = {"e": e, "omega": w, "u": u, "v": v}
         return {k: out[k] for k in want}
 
