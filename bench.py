@@ -5,12 +5,15 @@ with the u recovery, boundary reset and accelerations, second-row rule,
 synchronization every 50th step) on the workload below, with the state
 resident in HBM.  Prints ONE JSON line.
 
-Workload (FP64, the headline value): 1024 x 1024 plate, left edge clamped
-(u* = 0), other edges traction free, nu = 0.3, a0_phi = 0.9999, one seeded
-Gaussian displacement pulse (sigma 16, amplitude 1e-3), synchronization
-every 50 steps.  The same workload is also timed with the FP32 and the
-reduced (deviation) storages, each with its relative L2 error against the
-FP64 run after the same number of steps.
+Workload (the precision workload; FP64 is the headline value): 8192 x 8192
+plate with a central circular hole of radius 1024 (traction-free rim), outer
+edges clamped (u* = 0), nu = 0.3, a0_phi = 0.9999, one seeded Gaussian
+displacement pulse (sigma 16, amplitude 1e-3) on the annulus around the
+hole, synchronization every 50 steps.  The same workload is timed with the
+FP32 and the reduced (deviation) storages; in an untimed leg every storage
+runs on to step 2000, where the relative L2 error of e, omega and u of each
+reduced storage against FP64 is taken.  The FP64 path itself is compared
+with the CPU oracle on the same plate after the oracle's timed sample.
 """
 import argparse
 import hashlib
@@ -25,14 +28,26 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+WORKLOAD = "hole8192"
+PRECISION_STEPS = 2000
 # Interior tilings (lanes, rows, order, edge rows, alignment, steps per pass,
-# edge columns) and overlapped pairs (lbm_use_overlap) that measured fastest
-# for this workload on MI355X, pinned so that runs and the committed
-# rocprofv3 summaries use the same launches (--autotune tunes again instead).
-TUNED = {"f64": ((64, 8, 0, 4, 0, 2, 4), True), "f32": ((64, 8, 0, 2, 0, 2, 8), True),
-         "f32dev": ((64, 8, 0, 2, 0, 2, 8), True), "f16dev": ((64, 8, 0, 2, 0, 2, 8), True),
-         "bf16dev": ((64, 8, 0, 2, 0, 2, 8), True)}
+# edge columns) and overlapped pairs (lbm_use_overlap) that the library's
+# autotuner picks for this workload on MI355X, pinned so that runs and the
+# committed rocprofv3 summaries use the same launches (--autotune tunes
+# again instead).
+TUNED = {"f64": ((128, 16, 0, 4, 16, 2, 16), False),
+         "f32": ((256, 16, 0, 8, 16, 2, 16), False),
+         "f32dev": ((256, 16, 0, 8, 16, 2, 16), False),
+         "f16dev": ((256, 16, 0, 8, 16, 2, 16), False),
+         "bf16dev": ((256, 16, 0, 8, 16, 2, 16), False)}
+VARIANTS = ("f32", "f32dev", "f16dev", "bf16dev")
 METRIC = "GLUPS + % HBM roofline, FP64 vs FP16/FP32-storage at ≤1e-3 rel L2"
+KIND_NAMES = {"deep": "deep tiles of overlapped pairs", "two_step": "first launch of a two-step pair",
+              "interior": "single-step launch"}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_source_hash():
@@ -45,9 +60,9 @@ def kernel_source_hash():
 
 def measured_traffic(storage, kind, tile, overlap):
     """HBM bytes per launch of one interior-kernel kind from the committed
-    rocprofv3 PMC summary, if it was taken on the current kernel source with
-    the same tiling and overlap setting."""
-    path = os.path.join(ROOT, "profiles", f"interior_{storage}_clamped1024_traffic.json")
+    rocprofv3 PMC summary of this workload, if it was taken on the current
+    kernel source with the same tiling and overlap setting."""
+    path = os.path.join(ROOT, "profiles", f"interior_{storage}_{WORKLOAD}_traffic.json")
     try:
         with open(path) as fh:
             d = json.load(fh)
@@ -75,39 +90,6 @@ def cpu_model():
     return None
 
 
-def cpu_baseline(case, budget_s=12.0, single_s=3.0):
-    """Time the FP64 oracle on a bounded sample of the same workload, with
-    all its OpenMP threads and with one."""
-    from oracle import oracle
-
-    p = oracle_plate(case)
-    nodes = case.in_body_nodes()
-    threads = oracle.threads()
-
-    def timed(budget, done):
-        p.step(1)  # (thread start-up)
-        t0 = time.perf_counter()
-        p.step(4)
-        probe = time.perf_counter() - t0
-        steps = max(4, int(budget / max(probe / 4, 1e-6)))
-        t0 = time.perf_counter()
-        p.step(steps)
-        return steps, time.perf_counter() - t0, done + 5
-
-    steps, dt, first = timed(budget_s, 0)
-    oracle.set_threads(1)
-    steps1, dt1, first1 = timed(single_s, first + steps)
-    oracle.set_threads(threads)
-    return {"value": nodes * steps / dt / 1e9, "unit": "GLUPS", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{case.nx}x{case.ny} plate of the same workload, {steps} steps "
-                      f"(steps {first + 1}..{first + steps}), {dt:.1f} s wall",
-            "single_thread_value": nodes * steps1 / dt1 / 1e9,
-            "single_thread_sample": f"steps {first1 + 1}..{first1 + steps1}, {dt1:.1f} s wall",
-            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
-            "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS")}
-
-
 def oracle_plate(case):
     from oracle import oracle
 
@@ -119,40 +101,65 @@ def oracle_plate(case):
     return p
 
 
-def cpu_workload_samples():
-    """The FP64 oracle on sampled subsets of the batched workloads (all its
-    OpenMP threads): 4 plates of the 256-plate batch x 100 steps, and one
-    4096^2 plate of the 1.2 G-node batch x 20 steps."""
-    from paper_2301_00228_amd import inputs
+def cpu_baseline(case, budget_s):
+    """Time the FP64 oracle on a bounded sample of the same workload (the
+    same plate from t = 0, as many steps as fit the budget, all its OpenMP
+    threads).  Returns the record and the oracle plate (at its last step)."""
+    from oracle import oracle
 
-    out = {}
-    for name, cases, steps in (("batch256", inputs.plate_batch(count=256, steps=0)[:4], 100),
-                               ("large", inputs.large_batch(count=1, strip=None, steps=0), 20)):
-        lup, secs = 0, 0.0
-        for case in cases:
-            p = oracle_plate(case)
-            p.step(1)
-            t0 = time.perf_counter()
-            p.step(steps)
-            secs += time.perf_counter() - t0
-            lup += case.in_body_nodes() * steps
-            del p
-        out[name] = {"value": lup / secs / 1e6, "unit": "MLUPS",
-                     "sample": f"{len(cases)} plate(s) ({', '.join(f'{c.nx}x{c.ny}' for c in cases)})"
-                               f" x {steps} steps, {secs:.1f} s"}
-    return out
+    t0 = time.perf_counter()
+    p = oracle_plate(case)
+    setup = time.perf_counter() - t0
+    nodes = case.in_body_nodes()
+    threads = oracle.threads()
+    p.step(1)  # (thread start-up)
+    t0 = time.perf_counter()
+    p.step(1)
+    one = time.perf_counter() - t0
+    steps = max(2, int(budget_s / max(one, 1e-6)))
+    t0 = time.perf_counter()
+    p.step(steps)
+    dt = time.perf_counter() - t0
+    rec = {"value": nodes * steps / dt / 1e9, "unit": "GLUPS", "cores": threads, "kind": "oracle",
+           "sample": f"the same {case.nx}x{case.ny} holed plate from t = 0, {steps} steps "
+                     f"(steps 3..{steps + 2}) timed, {dt:.1f} s wall ({setup:.0f} s set-up "
+                     f"not counted)",
+           "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+           "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS")}
+    return rec, p
+
+
+def copy_rate_gbs(gib=2.0, reps=10):
+    """A plain device-to-device copy (torch) as the practical HBM ceiling."""
+    import torch
+    n = int(gib * 2**30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * n * 8 * reps / dt / 1e9
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5000)
-    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-budget", type=float, default=15.0,
+                    help="seconds of timed oracle steps in the CPU baseline")
     ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--cpu-workloads", action="store_true",
-                    help="also time the oracle on samples of the batched workloads")
-    ap.add_argument("--profile-steps", type=int, default=200)
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the untimed leg to step 2000 and the rel L2 errors")
+    ap.add_argument("--profile-steps", type=int, default=8)
     ap.add_argument("--storage", default="f64", help="storage of the headline run")
     ap.add_argument("--tiling", default="", metavar="L,R,O,E,A,S[,W]",
                     help="interior tiling of the headline storage (lanes, rows, order, edge "
@@ -186,12 +193,15 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 5}))
         return
-    case = inputs.clamped_plate(n=1024, steps=args.steps)
-    nodes = case.in_body_nodes()
     K, W = args.steps, args.warmup
+    log(f"building the {WORKLOAD} workload")
+    case = inputs.plate_with_hole(n=8192, radius=1024, steps=PRECISION_STEPS)
+    nodes = case.in_body_nodes()
 
     def timed_run(storage):
+        t0 = time.perf_counter()
         ctx = lbm.context_for(case, storage)
+        log(f"{storage}: context in {time.perf_counter() - t0:.1f} s")
         if args.tiling and storage == args.storage:
             ctx.set_tiling(*[int(v) for v in args.tiling.split(",")])
         elif not args.autotune:
@@ -201,122 +211,158 @@ def main():
             ctx.use_overlap(bool(ov))
         ctx.step(2)
         if args.autotune:
-            ctx.autotune(5)
+            ctx.autotune(3)
         ctx.step(W)
+        # the graphs of the timed call are captured before the timer starts
+        ctx.prepare_steps(K)
+        before = ctx.info()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ctx.step(K)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        return ctx, dt
+        after = ctx.info()
+        window = {"first_step": before["steps_done"], "graph_steps":
+                  after["steps_in_graphs"] - before["steps_in_graphs"],
+                  "sync_steps": after["syncs_done"] - before["syncs_done"]}
+        log(f"{storage}: {K} steps in {dt * 1e3:.2f} ms ({nodes * K / dt / 1e9:.2f} GLUPS)")
+        return ctx, dt, window
 
-    ctx, dt = timed_run(args.storage)
+    def roofline_of(ctx, storage, psteps):
+        """Dominant interior launch, timed with HIP events on its stream over
+        psteps eager steps (lbm_profile)."""
+        info = ctx.info()
+        prof = ctx.profile(psteps)
+        kind = ("deep" if prof["deep"][1] > 0 else
+                "two_step" if prof["two_step"][1] > 0 else "interior")
+        k_ms, k_n = prof[kind]
+        per = k_ms / k_n / 1e3
+        bpu = info["bytes_per_update"]
+        # nodes whose state the launch streams (read once, written once) and
+        # the lattice updates it performs
+        if kind == "deep":
+            own, lups = info["nodes_deep"], 2 * info["nodes_deep"]
+        elif kind == "two_step":
+            own, lups = nodes, nodes + info["nodes_two_step"]
+        else:
+            own, lups = nodes, nodes
+        return info, prof, kind, per, own, lups, bpu
+
+    # ---- headline storage
+    ctx, dt, window = timed_run(args.storage)
     ms_per_step = dt / K * 1e3
     glups = nodes * K / dt / 1e9
-    info = ctx.info()
-    f64_fields = ctx.fields(0)
+    info, prof, kind, per, own, lups, bpu = roofline_of(ctx, args.storage, args.profile_steps)
     tile = [info["tile_lanes"], info["tile_rows"], info["tile_order"], info["tile_edge_rows"],
             info["tile_align"], info["tile_steps"], info["tile_edge_cols"]]
-    # Dominant kernel: the interior launch with the most device time -- with
-    # overlapped pairs the deep tiles' launch (two steps of the two-step
-    # tiles away from the single-step ones, on the library's second stream
-    # beside the pair's other launches), else the first launch of a two-step
-    # pair (two steps of the two-step tiles, one of the others) or the
-    # single-step launch.  Device time per launch from HIP events on the
-    # stream it runs on, eager launches.  achieved = algorithmic bytes per
-    # lattice update x the lattice updates the launch performs / its time;
-    # the launch streams each of its nodes' state once, so with two steps per
-    # pass this exceeds the rate at which it actually streams (min_bytes /
-    # time) and the measured traffic.
-    prof = ctx.profile(args.profile_steps)
-    bnd_ms, bnd_n = prof["boundary"]
-    bpu = info["bytes_per_update"]
-    kind = ("deep" if prof["deep"][1] > 0 else
-            "two_step" if prof["two_step"][1] > 0 else "interior")
-    k_ms, k_n = prof[kind]
-    per_launch_s = k_ms / k_n / 1e3
-    if kind == "deep":
-        own = info["nodes_deep"]
-        lups = 2 * own
-        kname = f"k_interior<{args.storage}, {info['tile_lanes']} lanes, two-step, deep tiles>"
-    elif kind == "two_step":
-        own = nodes
-        lups = nodes + info["nodes_two_step"]
-        kname = f"k_interior<{args.storage}, {info['tile_lanes']} lanes, two-step>"
-    else:
-        own = nodes
-        lups = nodes
-        kname = f"k_interior<{args.storage}, {info['tile_lanes']} lanes, single-step>"
-    achieved = lups * bpu / per_launch_s / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(args.storage, kind, tile, bool(info["overlap"])),
-                "kernel": kname,
-                "bytes_per_lup": bpu, "lups_per_launch": lups,
-                "avg_launch_us": round(per_launch_s * 1e6, 2),
-                "min_bytes_per_launch": own * bpu,
-                "min_bytes_GBs": round(own * bpu / per_launch_s / 1e9, 1),
-                "boundary_kernel_avg_us": round(bnd_ms / max(bnd_n, 1) * 1e3, 2)}
-    if kind in ("deep", "two_step"):
-        s_ms, s_n = prof["interior"]
-        roofline["two_step_nodes"] = info["nodes_two_step"]
-        roofline["second_launch_avg_us"] = round(s_ms / max(s_n, 1) * 1e3, 2)
-    if kind == "deep":
-        f_ms, f_n = prof["two_step"]
-        roofline["deep_nodes"] = info["nodes_deep"]
-        roofline["frame_launch_avg_us"] = round(f_ms / max(f_n, 1) * 1e3, 2)
-    # what one step per pass over HBM would have to stream at the measured
-    # step rate
-    roofline["effective_GBs"] = round(nodes * bpu / (dt / K) / 1e9, 1)
+    overlap = bool(info["overlap"])
+    achieved = own * bpu / per / 1e9
+    traffic = measured_traffic(args.storage, kind, tile, overlap)
+    copy_gbs = copy_rate_gbs()
+    roofline = {
+        "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+        "kernel": f"k_interior<{args.storage}, {info['tile_lanes']} lanes, {KIND_NAMES[kind]}>",
+        "avg_launch_us": round(per * 1e6, 2),
+        "algorithmic_bytes_per_launch": own * bpu,
+        "bytes_per_node_pass": bpu, "nodes_per_launch": own, "lups_per_launch": lups,
+        "effective_GBs": round(lups * bpu / per / 1e9, 1),
+        "effective_frac": round(lups * bpu / per / 1e9 / HBM_PEAK_GBS, 4),
+        "measured_GBs": round(traffic / per / 1e9, 1) if traffic else None,
+        "measured_frac": round(traffic / per / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
+        "copy_GBs": round(copy_gbs, 1),
+        "frac_of_copy": round(achieved / copy_gbs, 4),
+        "step_effective_GBs": round(nodes * bpu / (dt / K) / 1e9, 1),
+        "step_effective_frac": round(nodes * bpu / (dt / K) / 1e9 / HBM_PEAK_GBS, 4),
+    }
+    for k in ("interior", "two_step", "boundary", "sync", "deep"):
+        ms, n = prof[k]
+        if n:
+            roofline[f"{k}_launch_avg_us"] = round(ms / n * 1e3, 2)
+
+    # ---- untimed leg: on to step 2000, the fields the errors are taken on
+    done = info["steps_done"]
+    fields = {}
+    if not args.no_precision and done <= PRECISION_STEPS:
+        ctx.step(PRECISION_STEPS - done)
+        fields[args.storage] = ctx.fields(0, want=("e", "omega", "u"))
     ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
 
     variants = {}
     if not args.no_variants:
-        ref_u = f64_fields["u"]
-        for st in ("f32", "f32dev", "f16dev", "bf16dev"):
-            c2, d2 = timed_run(st)
-            fl = c2.fields(0)
-            pr = c2.profile(min(args.profile_steps, 100))
-            i2 = c2.info()
-            bpu2 = i2["bytes_per_update"]
-            if pr["deep"][1] > 0:
-                i_ms, i_n = pr["deep"]
-                lups2 = 2 * i2["nodes_deep"]
-            elif pr["two_step"][1] > 0:
-                i_ms, i_n = pr["two_step"]
-                lups2 = nodes + i2["nodes_two_step"]
-            else:
-                i_ms, i_n = pr["interior"]
-                lups2 = nodes
-            ach2 = lups2 * bpu2 / (i_ms / i_n / 1e3) / 1e9
+        for st in VARIANTS:
+            if st == args.storage:
+                continue
+            c2, d2, w2 = timed_run(st)
+            i2, p2, k2, per2, own2, lups2, bpu2 = roofline_of(c2, st, args.profile_steps)
+            ach2 = own2 * bpu2 / per2 / 1e9
+            v = {"glups": round(nodes * K / d2 / 1e9, 3), "ms_per_step": round(d2 / K * 1e3, 4),
+                 "speedup_vs_" + args.storage: round(dt / d2, 3), "bytes_per_lup": bpu2,
+                 "kernel_avg_launch_us": round(per2 * 1e6, 2),
+                 "kernel_GBs": round(ach2, 1), "kernel_frac": round(ach2 / HBM_PEAK_GBS, 4),
+                 "kernel_effective_frac": round(lups2 * bpu2 / per2 / 1e9 / HBM_PEAK_GBS, 4),
+                 "step_effective_frac": round(nodes * bpu2 / (d2 / K) / 1e9 / HBM_PEAK_GBS, 4),
+                 "graph_steps": w2["graph_steps"],
+                 "tile": [i2["tile_lanes"], i2["tile_rows"], i2["tile_order"],
+                          i2["tile_edge_rows"], i2["tile_align"], i2["tile_steps"],
+                          i2["tile_edge_cols"]]}
+            t2 = measured_traffic(st, k2, v["tile"], bool(i2["overlap"]))
+            if t2:
+                v["kernel_measured_frac"] = round(t2 / per2 / 1e9 / HBM_PEAK_GBS, 4)
+            if not args.no_precision and i2["steps_done"] <= PRECISION_STEPS:
+                c2.step(PRECISION_STEPS - i2["steps_done"])
+                fields[st] = c2.fields(0, want=("e", "omega", "u"))
             c2.close()
-            variants[st] = {
-                "glups": round(nodes * K / d2 / 1e9, 3),
-                "ms_per_step": round(d2 / K * 1e3, 4),
-                "speedup_vs_f64": round(dt / d2, 3),
-                "interior_GBs": round(ach2, 1), "interior_frac": round(ach2 / HBM_PEAK_GBS, 4),
-                "bytes_per_lup": bpu2,
-                "rel_l2_vs_f64": {"e": rel_l2(fl["e"], f64_fields["e"]),
-                                  "omega": rel_l2(fl["omega"], f64_fields["omega"]),
-                                  "u": rel_l2(fl["u"], ref_u)},
-            }
-        del ref_u
+            del c2
+            torch.cuda.empty_cache()
+            variants[st] = v
+        if args.storage in fields:
+            ref = fields[args.storage]
+            for st, v in variants.items():
+                if st in fields:
+                    v["rel_l2_vs_" + args.storage + f"_at_step_{PRECISION_STEPS}"] = {
+                        k: rel_l2(fields[st][k], ref[k]) for k in ("e", "omega", "u")}
+                    v["within_1e-3"] = all(
+                        x <= 1e-3 for x in v["rel_l2_vs_" + args.storage + f"_at_step_{PRECISION_STEPS}"].values())
+                    log(f"{st}: rel L2 at step {PRECISION_STEPS}: "
+                        f"{v['rel_l2_vs_' + args.storage + f'_at_step_{PRECISION_STEPS}']}")
+    fields.clear()
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(case)
-        if args.cpu_workloads:
-            cpu["workload_samples"] = cpu_workload_samples()
+        log("oracle CPU baseline")
+        cpu, orc = cpu_baseline(case, args.cpu_budget)
+        # the FP64 GPU path on the same plate, to the oracle's step count
+        n_orc = orc.steps_done
+        ref = orc.fields()
+        del orc
+        with lbm.context_for(case, "f64") as c3:
+            c3.set_tiling(*TUNED["f64"][0])
+            c3.use_overlap(TUNED["f64"][1])
+            c3.step(n_orc)
+            got = c3.fields(0)
+        cpu["fp64_gpu_vs_oracle_rel_max"] = {
+            k: float(np.abs(got[k] - ref[k]).max() / max(np.abs(ref[k]).max(), 1e-300))
+            for k in ("e", "omega", "u", "v")}
+        cpu["fp64_gpu_vs_oracle_step"] = n_orc
+        del ref, got
 
     line = {
         "metric": METRIC, "value": round(glups, 4), "unit": "GLUPS", "n_gpus": 1, "steps": K,
         "warmup": W, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": {"f64": "f64", "f32": "f32"}.get(args.storage, "f32+f64"), "data": "synthetic",
-        "config": {"workload": "clamped plate 1024x1024 (left edge u*=0, other edges traction "
-                               "free), nu 0.3, a0_phi 0.9999, Gaussian pulse sigma 16 amp 1e-3, "
-                               "sync every 50, FP64 populations and u",
-                   "nodes": nodes, "storage": args.storage, "tile": tile,
-                   "overlap": bool(info["overlap"]), "graphs": True},
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": {"f64": "f64", "f32": "f32"}.get(args.storage, "f32+f64"), "data": "synthetic",
+        "config": {"workload": "plate 8192x8192 with a central circular hole of radius 1024 "
+                               "(traction-free rim), outer edges clamped u*=0, nu 0.3, a0_phi "
+                               "0.9999, Gaussian pulse sigma 16 amp 1e-3 on the annulus, sync "
+                               f"every 50; {args.storage} storage",
+                   "nodes": nodes, "storage": args.storage, "tile": tile, "overlap": overlap,
+                   "graphs": window["graph_steps"] == K,
+                   "timed_window": {"steps": [window["first_step"], window["first_step"] + K - 1],
+                                    "steps_in_graphs": window["graph_steps"],
+                                    "sync_steps": window["sync_steps"]}},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "variants": variants,

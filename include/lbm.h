@@ -259,7 +259,9 @@ typedef struct {
   int32_t tile_edge_cols;     /* width of the first and last column strip (0: no such strip) */
   int64_t nodes_deep;         /* body nodes in deep two-step tiles (see lbm_use_overlap)    */
   int32_t overlap;            /* 1: pairs of steps overlapped on two streams                */
-  int32_t pad;
+  int32_t graphs_cached;      /* captured step graphs held (see lbm_step)                   */
+  int64_t steps_in_graphs;    /* steps run so far by replaying captured graphs              */
+  int64_t syncs_done;         /* synchronization steps (Sec. 3.2) enqueued so far           */
 } lbm_info_t;
 lbm_status lbm_info(const lbm_ctx *ctx, lbm_info_t *info);
 
@@ -333,7 +335,20 @@ lbm_status lbm_autotune(lbm_ctx *ctx, int32_t steps, double *best_ms);
  * the sum over kinds can exceed the wall time.  Synchronizes the stream. */
 lbm_status lbm_profile(lbm_ctx *ctx, int64_t n_steps, double *ms, int64_t *launches);
 
-/* Use (nonzero) or bypass (0) captured HIP graphs in lbm_step.  Default on. */
+/* Capture, without running them, the HIP graphs that lbm_step(ctx,
+ * n_steps) would replay from the current state, so that the lbm_step call
+ * that follows launches only cached graphs (e.g. before a timed or
+ * latency-critical call).  Starts the context like the first lbm_step (the
+ * boundary accelerations of step 0 are enqueued) but takes no step.  No-op
+ * with graphs off.  Errors as lbm_step. */
+lbm_status lbm_prepare_steps(lbm_ctx *ctx, int64_t n_steps);
+
+/* Use (nonzero) or bypass (0) captured HIP graphs in lbm_step.  Default on.
+ * With graphs on, lbm_step runs whole synchronization periods (from a step
+ * that is a multiple of the period) as one cached graph each and any other
+ * run of steps as a graph captured for that run's length and starting
+ * phase; up to 8 graphs are kept (least recently used dropped).  Changing
+ * the tiling or the overlap setting drops them. */
 lbm_status lbm_use_graphs(lbm_ctx *ctx, int32_t enable);
 
 /* Overlapped pairs (nonzero, the default) or one stream (0), for two-step

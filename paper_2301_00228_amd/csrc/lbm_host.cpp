@@ -169,10 +169,22 @@ struct lbm_ctx {
   bool bnd_dirty = true;
 
   bool use_graphs = true;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
-  int64_t gsteps = 0;
-  int gcur = 0, gprev = 0;  // buffers at the start (and end) of the captured steps
+  // Captured step graphs, keyed by what the launch sequence of k steps from
+  // step s depends on: k, s modulo lcm(l, 2) (synchronization points, step
+  // parity), s == 0 (the first step of a run differs) and the buffers (cur,
+  // prev) at s.  Least recently used ones are dropped beyond kMaxGraphs.
+  struct GraphEntry {
+    int64_t k = 0, phase = 0;
+    bool first = false;
+    int cur = 0, prev = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t used = 0;
+  };
+  std::vector<GraphEntry> graphs;
+  uint64_t graph_clock = 0;
+  int64_t steps_in_graphs = 0;  // steps run by graph replays so far
+  int64_t syncs_done = 0;       // synchronization steps enqueued so far
 
   int *h_flag = nullptr;
   hipEvent_t flag_ev = nullptr;
@@ -255,11 +267,11 @@ void dev_free_all(lbm_ctx *c) {
 }
 
 void drop_graph(lbm_ctx *c) {
-  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
-  if (c->graph) (void)hipGraphDestroy(c->graph);
-  c->gexec = nullptr;
-  c->graph = nullptr;
-  c->gsteps = 0;
+  for (auto &g : c->graphs) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+  }
+  c->graphs.clear();
 }
 
 // Equilibrium weights and wave speeds (Sec. 2; Sec. 3, eqs. feq_req,
@@ -1260,8 +1272,8 @@ void advance_buffers(const lbm_ctx *c, int64_t s, int64_t n, int &cur, int &prev
   }
 }
 
-// Steps per captured graph: a multiple of l that starts and ends on the same
-// buffers.
+// Steps per captured graph of whole periods: a multiple of l that starts
+// and ends on the same buffers.
 int64_t graph_period(const lbm_ctx *c) {
   int64_t g = c->sync_every > 0 ? c->sync_every : 64;
   while (g < 32) g *= 2;
@@ -1270,23 +1282,47 @@ int64_t graph_period(const lbm_ctx *c) {
     advance_buffers(c, 0, g, cur, prev);
     if (cur == c->cur && prev == c->prev) return g;
   }
-  return 0;  // no period found: eager stepping
+  return 0;  // no period found: graphs of at most kMaxGraphSteps steps
 }
 
-lbm_status ensure_graph(lbm_ctx *c, int64_t G) {
-  if (c->gexec && c->gsteps == G && c->gcur == c->cur && c->gprev == c->prev) return LBM_OK;
-  drop_graph(c);
+constexpr size_t kMaxGraphs = 8;
+constexpr int64_t kMaxGraphSteps = 256;
+
+// Period of the launch sequence's dependence on the starting step.
+int64_t phase_period(const lbm_ctx *c) {
+  if (c->sync_every <= 0) return 2;
+  return c->sync_every % 2 == 0 ? c->sync_every : 2 * (int64_t)c->sync_every;
+}
+
+// Steps of the next graph of a run of n steps from step s.
+int64_t graph_chunk(const lbm_ctx *c, int64_t s, int64_t n) {
+  const int64_t G = graph_period(c);
+  if (G <= 0) return std::min(n, kMaxGraphSteps);
+  if (s % G == 0 && n >= G) return G;
+  return std::min(n, G - s % G);
+}
+
+// The captured graph of steps [s, s + k) from buffers (cur, prev), from the
+// cache or captured now.
+lbm_status graph_for(lbm_ctx *c, int64_t s, int64_t k, int cur, int prev, hipGraphExec_t *out) {
+  const int64_t phase = s % phase_period(c);
+  const bool first = s == 0;
+  const int cur0 = cur, prev0 = prev;
+  for (auto &g : c->graphs)
+    if (g.k == k && g.phase == phase && g.first == first && g.cur == cur && g.prev == prev) {
+      g.used = ++c->graph_clock;
+      *out = g.exec;
+      return LBM_OK;
+    }
   if (!c->cap_stream)
     HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "capture stream");
-
   HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal),
           "begin capture");
   hipError_t e = hipSuccess;
-  int cur = c->cur, prev = c->prev;
-  for (int64_t s = 0; s < G && e == hipSuccess;) {
-    const int64_t k = segment_limit(c, s, G - s);
-    e = enqueue_segment(c, s, k, cur, prev, c->cap_stream, nullptr);
-    s += k;
+  for (int64_t m = s; m < s + k && e == hipSuccess;) {
+    const int64_t q = segment_limit(c, m, s + k - m);
+    e = enqueue_segment(c, m, q, cur, prev, c->cap_stream, nullptr);
+    m += q;
   }
   hipGraph_t g = nullptr;
   hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
@@ -1301,12 +1337,34 @@ lbm_status ensure_graph(lbm_ctx *c, int64_t G) {
     (void)hipGraphDestroy(g);
     return hip_fail(c, e, "graph instantiate");
   }
-  c->graph = g;
-  c->gexec = ge;
-  c->gsteps = G;
-  c->gcur = c->cur;
-  c->gprev = c->prev;
+  if (c->graphs.size() >= kMaxGraphs) {
+    auto lru = std::min_element(c->graphs.begin(), c->graphs.end(),
+                                [](const lbm_ctx::GraphEntry &a, const lbm_ctx::GraphEntry &b) {
+                                  return a.used < b.used;
+                                });
+    (void)hipGraphExecDestroy(lru->exec);
+    (void)hipGraphDestroy(lru->graph);
+    c->graphs.erase(lru);
+  }
+  lbm_ctx::GraphEntry ent;
+  ent.k = k;
+  ent.phase = phase;
+  ent.first = first;
+  ent.cur = cur0;
+  ent.prev = prev0;
+  ent.graph = g;
+  ent.exec = ge;
+  ent.used = ++c->graph_clock;
+  c->graphs.push_back(ent);
+  *out = ge;
   return LBM_OK;
+}
+
+// Synchronization steps among [s, s + n).
+int64_t syncs_in(const lbm_ctx *c, int64_t s, int64_t n) {
+  if (c->sync_every <= 0 || n <= 0) return 0;
+  const int64_t l = c->sync_every;
+  return (s + n) / l - s / l;
 }
 
 lbm_status check_flag(lbm_ctx *c, bool wait) {
@@ -1778,19 +1836,22 @@ lbm_status lbm_step(lbm_ctx *c, int64_t n) {
   if (st) return st;
   while (n > 0) {
     if (c->use_graphs) {
-      const int64_t G = graph_period(c);
-      if (G > 0 && n >= G && c->step % G == 0) {
-        st = ensure_graph(c, G);
-        if (st) return st;
-        HIP_TRY(c, hipGraphLaunch(c->gexec, c->stream), "graph launch");
-        c->step += G;
-        n -= G;
-        continue;
-      }
+      const int64_t k = graph_chunk(c, c->step, n);
+      hipGraphExec_t ge = nullptr;
+      st = graph_for(c, c->step, k, c->cur, c->prev, &ge);
+      if (st) return st;
+      HIP_TRY(c, hipGraphLaunch(ge, c->stream), "graph launch");
+      advance_buffers(c, c->step, k, c->cur, c->prev);
+      c->syncs_done += syncs_in(c, c->step, k);
+      c->steps_in_graphs += k;
+      c->step += k;
+      n -= k;
+      continue;
     }
     const int64_t k = segment_limit(c, c->step, n);
     HIP_TRY(c, enqueue_segment(c, c->step, k, c->cur, c->prev, c->stream, nullptr),
             "step launch");
+    c->syncs_done += syncs_in(c, c->step, k);
     c->step += k;
     n -= k;
   }
@@ -1798,6 +1859,27 @@ lbm_status lbm_step(lbm_ctx *c, int64_t n) {
           "flag copy");
   HIP_TRY(c, hipEventRecord(c->flag_ev, c->stream), "flag event");
   c->flag_pending = true;
+  return LBM_OK;
+}
+
+lbm_status lbm_prepare_steps(lbm_ctx *c, int64_t n) {
+  if (!c || n < 0) return LBM_E_INVAL;
+  lbm_status st = check_flag(c, false);
+  if (st) return st;
+  if (!c->use_graphs) return LBM_OK;
+  st = start(c);
+  if (st) return st;
+  int64_t s = c->step;
+  int cur = c->cur, prev = c->prev;
+  while (n > 0) {
+    const int64_t k = graph_chunk(c, s, n);
+    hipGraphExec_t ge = nullptr;
+    st = graph_for(c, s, k, cur, prev, &ge);
+    if (st) return st;
+    advance_buffers(c, s, k, cur, prev);
+    s += k;
+    n -= k;
+  }
   return LBM_OK;
 }
 
@@ -1923,6 +2005,9 @@ lbm_status lbm_info(const lbm_ctx *c, lbm_info_t *info) {
   info->tile_edge_cols = c->edge_cols;
   info->nodes_deep = c->two ? c->n_deep : 0;
   info->overlap = (c->two && c->overlap) ? 1 : 0;
+  info->steps_in_graphs = c->steps_in_graphs;
+  info->syncs_done = c->syncs_done;
+  info->graphs_cached = (int32_t)c->graphs.size();
   return LBM_OK;
 }
 
@@ -2000,6 +2085,7 @@ lbm_status lbm_profile(lbm_ctx *c, int64_t n, double *ms, int64_t *launches) {
     const int64_t k = segment_limit(c, c->step, n);
     e = enqueue_segment(c, c->step, k, c->cur, c->prev, c->stream, &rec);
     if (e == hipSuccess) {
+      c->syncs_done += syncs_in(c, c->step, k);
       c->step += k;
       n -= k;
     }
@@ -2043,6 +2129,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
   if (c->step == 0 || (syncs_now && c->sync_every > 1) || c->prev == 2) {
     HIP_TRY(c, enqueue_segment(c, c->step, 1, c->cur, c->prev, c->stream, nullptr),
             "step launch");
+    c->syncs_done += syncs_in(c, c->step, 1);
     c->step += 1;
   }
   const bool with_prologue = !(c->sync_every > 0 && c->step % c->sync_every == 0);

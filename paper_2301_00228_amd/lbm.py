@@ -26,7 +26,7 @@ BC_NEUMANN, BC_DIRICHLET = 0, 1
 EXPORTS = ["lbm_create", "lbm_set_bc", "lbm_step", "lbm_fields", "lbm_fields_device", "lbm_info",
            "lbm_set_tiling", "lbm_autotune", "lbm_profile", "lbm_use_graphs", "lbm_use_overlap", "lbm_destroy",
            "lbm_last_error", "lbm_version", "lbm_exact_cells", "lbm_consistency_error",
-           "lbm_fields_noalloc"]
+           "lbm_fields_noalloc", "lbm_prepare_steps"]
 SHAPE_HOLE, SHAPE_BOUND = 0, 1
 
 
@@ -64,7 +64,8 @@ class lbm_info_t(C.Structure):
                 ("tile_order", C.c_int32), ("tile_edge_rows", C.c_int32),
                 ("tile_align", C.c_int32), ("tile_steps", C.c_int32), ("n_tiles", C.c_int32),
                 ("tile_edge_cols", C.c_int32), ("nodes_deep", C.c_int64), ("overlap", C.c_int32),
-                ("pad", C.c_int32)]
+                ("graphs_cached", C.c_int32), ("steps_in_graphs", C.c_int64),
+                ("syncs_done", C.c_int64)]
 
 
 class lbm_tiling(C.Structure):
@@ -98,6 +99,8 @@ def library():
     L.lbm_set_bc.argtypes = [vp, C.c_int32, C.c_int32, ip, up, dp, dp, C.c_int32, dp]
     L.lbm_step.restype = C.c_int
     L.lbm_step.argtypes = [vp, C.c_int64]
+    L.lbm_prepare_steps.restype = C.c_int
+    L.lbm_prepare_steps.argtypes = [vp, C.c_int64]
     L.lbm_fields.restype = C.c_int
     L.lbm_fields.argtypes = [vp, C.c_int32, dp, dp, dp, dp]
     L.lbm_fields_noalloc.restype = C.c_int
@@ -278,6 +281,11 @@ class Context:
 
     def step(self, n=1):
         self._check(library().lbm_step(self._h, int(n)))
+
+    def prepare_steps(self, n):
+        """lbm_prepare_steps: capture the graphs step(n) would replay from the
+        current state, without running them."""
+        self._check(library().lbm_prepare_steps(self._h, int(n)))
 
     def fields(self, plate=0, want=("e", "omega", "u", "v")):
         nx, ny = self.shapes[plate]

@@ -437,3 +437,43 @@ def test_set_bc_after_step_is_rejected():
         with pytest.raises(lbm.LbmError) as ei:
             lbm.Context([lbm.plate_dict(case)]).set_bc(0, [[5, 5]], [1], [[0.0, 0.0]])
         assert ei.value.code == lbm.E_INVAL
+
+
+@pytest.mark.parametrize("tiling,overlap", [((64, 8, 0, 4, 0, 2, 4), True),
+                                            ((128, 16, 0, 4, 16, 2, 16), False),
+                                            ((128, 8, 0, 2, 0, 1, 0), False)])
+def test_graphs_of_any_step_count_are_bitwise_and_counted(tiling, overlap):
+    """lbm_step replays a captured graph for runs of any length and starting
+    phase (whole synchronization periods from aligned steps, any other run
+    as a graph of its own, cached); the trajectory is bitwise that of eager
+    launches, every step runs in a graph, the synchronizations are counted,
+    and graphs prepared ahead are replayed without a new capture."""
+    case = I.clamped_plate(n=150, ny=118, sigma=5.0, steps=0, sync_every=50)
+    calls = (2, 7, 13, 50, 3, 77, 31, 50, 50, 7, 13)
+    total = sum(calls)
+    with lbm.context_for(case) as ctx:
+        ctx.set_tiling(*tiling)
+        ctx.use_overlap(overlap)
+        ctx.use_graphs(False)
+        ctx.step(total)
+        ref = ctx.fields(0)
+        assert ctx.info()["steps_in_graphs"] == 0
+    with lbm.context_for(case) as ctx:
+        ctx.set_tiling(*tiling)
+        ctx.use_overlap(overlap)
+        for m, n in enumerate(calls):
+            if m % 3 == 1:
+                ctx.prepare_steps(n)
+                cached = ctx.info()["graphs_cached"]
+                ctx.step(n)
+                assert ctx.info()["graphs_cached"] == cached
+            else:
+                ctx.step(n)
+            if m % 4 == 0:
+                ctx.fields(0)  # eager work and a synchronization between replays
+        got = ctx.fields(0)
+        info = ctx.info()
+    assert info["steps_in_graphs"] == total
+    assert info["syncs_done"] == total // 50
+    for k in FIELDS:
+        assert np.array_equal(got[k], ref[k]), (tiling, k)
