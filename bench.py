@@ -130,22 +130,10 @@ def cpu_baseline(case, budget_s):
 
 
 def copy_rate_gbs(gib=2.0, reps=10):
-    """A plain device-to-device copy (torch) as the practical HBM ceiling."""
-    import torch
-    n = int(gib * 2**30) // 8
-    a = torch.ones(n, dtype=torch.float64, device="cuda")
-    b = torch.empty_like(a)
-    for _ in range(3):
-        b.copy_(a)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        b.copy_(a)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    del a, b
-    torch.cuda.empty_cache()
-    return 2 * n * 8 * reps / dt / 1e9
+    """A plain device-to-device copy (the library's copy probe) as the
+    practical HBM ceiling."""
+    from paper_2301_00228_amd import lbm
+    return lbm.copy_rate(int(gib * 2**30), reps)
 
 
 def main():

@@ -373,6 +373,16 @@ void lbm_destroy(lbm_ctx *ctx);
  * NULL).  The pointer stays valid until the next call on ctx. */
 const char *lbm_last_error(const lbm_ctx *ctx);
 
+/* Measurement aid: the rate (GB/s, bytes read + written per second) of a
+ * plain device-to-device copy of `bytes` bytes on the current device (a
+ * grid-stride copy of 16-byte vectors, nontemporal, 1024-lane workgroups),
+ * averaged over reps launches after three untimed ones -- the HBM rate a
+ * pure stream reaches, to set the kernels' measured rates against.
+ * Allocates and frees two device buffers of `bytes` bytes; synchronizes
+ * the device.  Errors (text via lbm_last_error(NULL)): LBM_E_INVAL (bytes <
+ * 16, reps < 1, NULL gbs), LBM_E_NOMEM, LBM_E_DEVICE. */
+lbm_status lbm_copy_rate(size_t bytes, int32_t reps, double *gbs);
+
 /* Library version string. */
 const char *lbm_version(void);
 

@@ -8,7 +8,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
 SOURCES = [os.path.join(CSRC, "lbm_kernels.hip"), os.path.join(CSRC, "lbm_host.cpp"),
-           os.path.join(CSRC, "lbm_geom.cpp")]
+           os.path.join(CSRC, "lbm_geom.cpp"), os.path.join(CSRC, "lbm_probe.hip")]
 HEADERS = [os.path.join(CSRC, "lbm_types.h"), os.path.join(CSRC, "lbm_kernels.h"),
            os.path.join(ROOT, "include", "lbm.h")]
 

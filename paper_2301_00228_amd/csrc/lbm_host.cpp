@@ -1437,6 +1437,16 @@ double field_magnitude(const lbm_plate &p, const PlateHost &h, int fl) {
 
 extern "C" {
 
+lbm_status lbm_copy_rate(size_t bytes, int32_t reps, double *gbs) {
+  if (!gbs || bytes < 16 || reps < 1) return fail(nullptr, LBM_E_INVAL, "bad copy-rate arguments");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
+    return fail(nullptr, LBM_E_DEVICE, "no HIP device available");
+  const hipError_t e = copy_rate(bytes, reps, gbs);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "copy probe");
+  return LBM_OK;
+}
+
 const char *lbm_version(void) { return "paper_2301_00228_amd lbm 0.1 (gfx950)"; }
 
 const char *lbm_last_error(const lbm_ctx *c) {

@@ -37,6 +37,11 @@ hipError_t launch_fields(int storage, const DevState &s, int plate, int64_t node
 hipError_t launch_cons_err(int storage, const DevState &s, int plate, int64_t nodes, int b,
                            double *err, hipStream_t stream);
 
+// Rate in GB/s (read + write) of a plain device copy of `bytes` bytes,
+// averaged over reps launches after 3 untimed ones; allocates and frees
+// its two buffers.
+hipError_t copy_rate(size_t bytes, int reps, double *gbs);
+
 // Size of the fixed device staging area of lbm_fields_noalloc (per GPU).
 constexpr size_t kNoAllocBytes = (size_t)48 << 20;
 // Device address of that area on `device`, which must be the current

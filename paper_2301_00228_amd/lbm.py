@@ -26,7 +26,7 @@ BC_NEUMANN, BC_DIRICHLET = 0, 1
 EXPORTS = ["lbm_create", "lbm_set_bc", "lbm_step", "lbm_fields", "lbm_fields_device", "lbm_info",
            "lbm_set_tiling", "lbm_autotune", "lbm_profile", "lbm_use_graphs", "lbm_use_overlap", "lbm_destroy",
            "lbm_last_error", "lbm_version", "lbm_exact_cells", "lbm_consistency_error",
-           "lbm_fields_noalloc", "lbm_prepare_steps"]
+           "lbm_fields_noalloc", "lbm_prepare_steps", "lbm_copy_rate"]
 SHAPE_HOLE, SHAPE_BOUND = 0, 1
 
 
@@ -99,6 +99,8 @@ def library():
     L.lbm_set_bc.argtypes = [vp, C.c_int32, C.c_int32, ip, up, dp, dp, C.c_int32, dp]
     L.lbm_step.restype = C.c_int
     L.lbm_step.argtypes = [vp, C.c_int64]
+    L.lbm_copy_rate.restype = C.c_int
+    L.lbm_copy_rate.argtypes = [C.c_size_t, C.c_int32, dp]
     L.lbm_prepare_steps.restype = C.c_int
     L.lbm_prepare_steps.argtypes = [vp, C.c_int64]
     L.lbm_fields.restype = C.c_int
@@ -164,6 +166,15 @@ def exact_cells(nx, ny, shapes, xy, dh=1.0, periodic=(False, False)):
     if st != OK:
         raise LbmError(st, "lbm_exact_cells rejected its arguments")
     return cell, ext
+
+
+def copy_rate(nbytes=2 << 30, reps=10):
+    """lbm_copy_rate: GB/s of a plain device copy of nbytes bytes."""
+    out = C.c_double(0)
+    rc = library().lbm_copy_rate(int(nbytes), int(reps), C.byref(out))
+    if rc != OK:
+        raise LbmError(rc, library().lbm_last_error(None).decode())
+    return out.value
 
 
 def default_stream():

@@ -42,6 +42,10 @@ hipError_t launch_fields(int, const DevState &, int, int64_t, int, double *, dou
 hipError_t launch_cons_err(int, const DevState &, int, int64_t, int, double *, hipStream_t) {
   return hipErrorInvalidValue;
 }
+hipError_t copy_rate(size_t, int, double *gbs) {
+  *gbs = 0;
+  return hipErrorInvalidValue;
+}
 hipError_t noalloc_staging(int, void **ptr) {
   *ptr = nullptr;
   return hipErrorInvalidValue;
