@@ -96,7 +96,22 @@ typedef struct {
                                 order): v is kept, and reported by lbm_fields, at t - dt/2
                                 (v0 is the velocity at t = 0); u is the same after the
                                 first step.  Other values: LBM_E_INVAL.                    */
+  int32_t readings;          /* readings of two points Sec. 3.1 leaves open, bits (other
+                                bits: LBM_E_INVAL).  0 (default) = R1 and M1.
+                                LBM_READ_FLUX_STREAMED (R2): the flux J(x_k, t) of eq.
+                                correction-f is that of the post-collision populations
+                                streaming into the boundary node from its body neighbours
+                                (a missing one adds 0), not that of its own populations.
+                                LBM_READ_EQ_OLD (M2): the equilibrium of eq. LBE_mod is that
+                                of the boundary node's populations at t, not that of the
+                                time-averaged populations.  With either bit on any plate
+                                the context runs each step's boundary work in a launch of
+                                its own after the interior launch (no two-step pairs;
+                                slower, the same update) and lbm_autotune returns
+                                LBM_E_STATE.                                              */
 } lbm_plate;
+
+enum { LBM_READ_FLUX_STREAMED = 1, LBM_READ_EQ_OLD = 2 };
 
 /* Optional device allocator (e.g. a framework's caching allocator).  alloc
  * returns device memory of at least `bytes` bytes or NULL; free releases it.
@@ -314,9 +329,9 @@ lbm_status lbm_set_tiling(lbm_ctx *ctx, const lbm_tiling *tiling);
  * allowed (lbm_use_overlap on, the default) the best two-step tiling is then
  * timed overlapped (also with frame tiles of 2 and 4 rows) against one
  * stream, both captured in HIP graphs as lbm_step runs them, and overlap is
- * kept on only if that is at least 3 % faster, else turned off.  Results are
- * cached per (storage, single/multiple plates, size bucket) for the life of
- * the process and picked up by later contexts.  best_ms (nullable) receives
+ * kept on only if that is at least 3 % faster, else turned off.  The result
+ * applies to this context only (every context starts from the same default
+ * tiling, whatever ran before in the process).  best_ms (nullable) receives
  * the fastest interior time per step (for two-step tilings half the time of
  * a pair's launches). */
 lbm_status lbm_autotune(lbm_ctx *ctx, int32_t steps, double *best_ms);

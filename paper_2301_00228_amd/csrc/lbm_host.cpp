@@ -37,6 +37,7 @@ struct PlateHost {
   int64_t b0 = 0, b1 = 0;    // range in the boundary list
   int nloads = 0;
   int64_t body = 0;
+  double field_mag[2] = {0, 0};  // magnitude of the initial fields (16-bit storage scale)
   int ns = 0;          // interior tiles: column strips
   std::vector<int> sx;  // first column of each strip, then nx (ns + 1 entries)
   // per strip: (first row, tile index) of its tiles, by increasing row
@@ -76,12 +77,6 @@ size_t slot_bytes(int st) {
 }
 size_t uv_bytes(int st) { return st == LBM_STORE_F32 ? 4 : 8; }
 
-std::mutex g_tune_mu;
-struct TuneEntry {
-  lbm_tiling t;
-  bool overlap;
-};
-std::map<std::tuple<int, int, int>, TuneEntry> g_tune_cache;
 
 }  // namespace
 
@@ -100,6 +95,10 @@ struct lbm_ctx {
   int64_t n_two = 0;  // body nodes in two-step tiles
   int64_t n_body = 0;
   int sync_every = 0;
+  // some plate uses readings other than R1 + M1: every step's boundary work
+  // runs in the boundary kernel (the interior kernel's prologues carry only
+  // the default readings), so every step is a segment of its own
+  bool variant_readings = false;
 
   std::vector<BndNode> bnd;
   std::vector<SecNode> sec;
@@ -302,6 +301,8 @@ lbm_status plate_params(const lbm_plate &p, PlateDev &d) {
   d.mu = p.mu;
   if (p.integrator != 0 && p.integrator != 1) return LBM_E_INVAL;
   d.integ = p.integrator;
+  if (p.readings < 0 || p.readings > (RD_FLUX_STREAMED | RD_EQ_OLD)) return LBM_E_INVAL;
+  d.readings = p.readings;
   return LBM_OK;
 }
 
@@ -1246,8 +1247,10 @@ hipError_t enqueue_segment(lbm_ctx *c, int64_t s, int64_t k, int &cur, int &prev
   return e;
 }
 
-// Length of the segment starting at step s (ends at the next synchronization).
+// Length of the segment starting at step s (ends at the next synchronization;
+// one step with readings other than R1 + M1).
 int64_t segment_limit(const lbm_ctx *c, int64_t s, int64_t n) {
+  if (c->variant_readings) return std::min<int64_t>(n, 1);
   if (c->sync_every <= 0) return n;
   return std::min<int64_t>(n, c->sync_every - s % c->sync_every);
 }
@@ -1382,6 +1385,40 @@ lbm_status check_flag(lbm_ctx *c, bool wait) {
   return LBM_OK;
 }
 
+// 16-bit storage scale of one field for fields of magnitude about m: a
+// power of two that puts m near 2^12 (the deviation moments are a small
+// fraction of the fields, far from the FP16 limit of 65504; BF16 has FP32's
+// exponent range), 2^14 when m is 0.
+void set_scale(PlateDev &d, int fl, double m) {
+  const int e = m > 0 ? 12 - (int)std::ceil(std::log2(m)) : 14;
+  const int ec = std::max(-100, std::min(100, e));
+  d.scale[fl] = std::ldexp(1.0f, ec);
+  d.iscale[fl] = std::ldexp(1.0f, -ec);
+}
+
+// Rough magnitude of the strains the boundary data of plate p impose: a
+// Neumann force F on a cell of side dh is a traction of about |F|/dh, a
+// strain of about |F|/((lambda + 2 mu) dh); a prescribed displacement u*
+// next to nodes at rest is a gradient of about |u*|/dh (each times the
+// largest amplitude of its load table).
+double load_magnitude(const lbm_ctx *c, int p) {
+  const PlateHost &h = c->ph[(size_t)p];
+  const PlateDev &d = c->pd[(size_t)p];
+  double m = 0;
+  for (int64_t b = h.b0; b < h.b1; b++) {
+    const BndNode &B = c->bnd[(size_t)b];
+    double g = 1.0;
+    if (B.load >= 0) {
+      const LoadTable &L = c->loads[(size_t)B.load];
+      g = 0;
+      for (int k = 0; k < L.n; k++) g = std::max(g, std::fabs(L.g[k]));
+    }
+    const double v = g * std::max(std::fabs(B.val[0]), std::fabs(B.val[1]));
+    m = std::max(m, B.kind == LBM_BC_DIRICHLET ? v / d.dh : v / ((d.lam + 2.0 * d.mu) * d.dh));
+  }
+  return m;
+}
+
 lbm_status start(lbm_ctx *c) {
   if (c->started) return LBM_OK;
   // side stream and events of overlapped pairs (default priority)
@@ -1395,6 +1432,25 @@ lbm_status start(lbm_ctx *c) {
   if (c->bnd_dirty) {
     lbm_status st = upload_boundary(c);
     if (st) return st;
+  }
+  if (c->storage == LBM_STORE_F16DEV || c->storage == LBM_STORE_BF16DEV) {
+    // 16-bit scale from the initial fields and the boundary data: a plate
+    // that starts at rest is driven to strains its loads set.  The stored
+    // deviation moments are all 0 before the first step (f = f_eq), so the
+    // scale can change here without re-encoding.
+    bool changed = false;
+    for (size_t p = 0; p < c->pd.size(); p++) {
+      const double ml = load_magnitude(c, (int)p);
+      for (int fl = 0; fl < 2; fl++) {
+        const float before = c->pd[p].scale[fl];
+        set_scale(c->pd[p], fl, std::max(c->ph[p].field_mag[fl], ml));
+        changed |= c->pd[p].scale[fl] != before;
+      }
+    }
+    if (changed)
+      HIP_TRY(c, hipMemcpy(c->d_plates, c->pd.data(), c->pd.size() * sizeof(PlateDev),
+                           hipMemcpyHostToDevice),
+              "plate upload");
   }
   // boundary accelerations of step 0: u(t_1) of the boundary nodes, into
   // both buffers the first step may write
@@ -1514,6 +1570,7 @@ lbm_status lbm_create(const lbm_plate *plates, int32_t n_plates, lbm_storage sto
                       ? "plate " + std::to_string(p) + ": dt gives a0_phi < 0 (dt > dh/(sqrt(2) c_d))"
                       : "plate " + std::to_string(p) + ": bad material or lattice parameters");
     }
+    if (pl.readings != 0) c->variant_readings = true;
     PlateHost &h = c->ph[p];
     h.nx = pl.nx;
     h.ny = pl.ny;
@@ -1536,11 +1593,8 @@ lbm_status lbm_create(const lbm_plate *plates, int32_t n_plates, lbm_storage sto
     d.pitch = h.pitch;
     d.periodic = (h.px ? 1 : 0) | (h.py ? 2 : 0);
     for (int fl = 0; fl < 2; fl++) {
-      const double m = field_magnitude(pl, h, fl);
-      const int e = m > 0 ? 12 - (int)std::ceil(std::log2(m)) : 14;
-      const int ec = std::max(-100, std::min(100, e));
-      d.scale[fl] = std::ldexp(1.0f, ec);
-      d.iscale[fl] = std::ldexp(1.0f, -ec);
+      h.field_mag[fl] = field_magnitude(pl, h, fl);
+      set_scale(d, fl, h.field_mag[fl]);
     }
     // boundary and second-row lists (row-major order)
     h.b0 = (int64_t)c->bnd.size();
@@ -1738,31 +1792,13 @@ lbm_status lbm_create(const lbm_plate *plates, int32_t n_plates, lbm_storage sto
   (void)hipFree(stage);
   if (e != hipSuccess) return bail(LBM_E_DEVICE, std::string("initial state: ") + hipGetErrorString(e));
 
-  // tiles (cached tuning if any)
-  {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto key = std::make_tuple(c->storage, n_plates > 1 ? 1 : 0,
-                               (int)std::lround(std::log2((double)std::max<int64_t>(1, c->n_body))));
-    auto it = g_tune_cache.find(key);
-    if (it != g_tune_cache.end()) {
-      const lbm_tiling &t = it->second.t;
-      c->lanes = t.lanes;
-      c->rows = t.rows;
-      c->order = t.order;
-      c->edge_rows = t.edge_rows;
-      c->edge_cols = t.edge_cols;
-      c->align = t.align;
-      c->two = t.steps == 2 ? 1 : 0;
-      c->overlap = it->second.overlap;
-      if (c->two && ensure_third(c) != LBM_OK) c->two = 0;
-    } else {
-      // what the autotuner picks on 1024^2 (unaligned) and 4096^2 plates
-      c->lanes = 128;
-      c->rows = 8;
-      c->edge_rows = 2;
-      c->align = c->n_body < ((int64_t)4 << 20) ? 0 : 16;
-    }
-  }
+  // default tiling (what the autotuner picks on 1024^2 plates unaligned and
+  // on 4096^2 plates aligned); every context starts from it, whatever ran
+  // before in the process, so that timings do not depend on history
+  c->lanes = 128;
+  c->rows = 8;
+  c->edge_rows = 2;
+  c->align = c->n_body < ((int64_t)4 << 20) ? 0 : 16;
   build_tiles(c);
   build_tile_tables(c);
   if (upload_tiles(c) != LBM_OK || upload_tile_tables(c) != LBM_OK)
@@ -2121,6 +2157,10 @@ lbm_status lbm_profile(lbm_ctx *c, int64_t n, double *ms, int64_t *launches) {
 
 lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
   if (!c || steps < 1) return LBM_E_INVAL;
+  if (c->variant_readings)
+    return fail(c, LBM_E_STATE,
+                "lbm_autotune times the interior launches with their boundary prologues, which "
+                "carry only the default readings (R1, M1)");
   lbm_status st = check_flag(c, false);
   if (st) return st;
   st = start(c);
@@ -2396,12 +2436,6 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
   st = upload_tile_tables(c);
   if (st) return st;
   drop_graph(c);
-  {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto key = std::make_tuple(c->storage, c->ph.size() > 1 ? 1 : 0,
-                               (int)std::lround(std::log2((double)std::max<int64_t>(1, c->n_body))));
-    g_tune_cache[key] = TuneEntry{bt, best_ov};
-  }
   if (best_ms) *best_ms = best;
   return LBM_OK;
 }

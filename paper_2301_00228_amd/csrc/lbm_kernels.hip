@@ -143,6 +143,7 @@ struct PopCodec {
     jx = r[1] - r[3];
     jy = r[2] - r[4];
   }
+  __device__ static C raw_rho(const Slot r[5]) { return r[0] + ((r[1] + r[3]) + (r[2] + r[4])); }
   __device__ static C aw(const PlateDev &P, int fl) { return (C)P.a[fl]; }
   __device__ static C a0w(const PlateDev &P, int fl) { return (C)P.a0[fl]; }
   __device__ static void load(const DevState &s, int b, int fl, int64_t k, const PlateDev &,
@@ -253,6 +254,7 @@ struct DevCodec {
     jx = __uint_as_float(r[1]);
     jy = __uint_as_float(r[2]);
   }
+  __device__ static C raw_rho(const Slot r[5]) { return __uint_as_float(r[0]); }
   __device__ static void raw_to_pops(const PlateDev &P, int fl, const Slot r[5], C f[5]) {
     float m[5];
     m[0] = __uint_as_float(r[0]);
@@ -521,6 +523,40 @@ __device__ __forceinline__ void hooke(const PlateDev &P, const U *g, U &sxx, U &
   sxy = U(2.0) * mu * exy;
 }
 
+// Flux of eq. correction-f under reading R2 at boundary node (i, j) with
+// class byte cl, field fl: the first moment (lattice units) of the
+// post-collision populations (eq. LBE, dt/tau = 2) that the LBE would
+// stream into the node at t from its body neighbours x - c^alpha, their
+// populations at t - dt being in buffer po (those neighbours are boundary
+// or second-row nodes, whose populations the march never overwrites); a
+// missing neighbour contributes 0.
+template <class CD>
+__device__ void streamed_in_flux(const DevState &s, const PlateDev &P, int i, int j, uint8_t cl,
+                                 int fl, int po, typename CD::C &jx, typename CD::C &jy) {
+  using C = typename CD::C;
+  using Slot = typename CD::Slot;
+  // population alpha arrives from x - c^alpha: 1 from W, 2 from S, 3 from E,
+  // 4 from N (one neighbour at a time)
+  C sx = C(0), sy = C(0);
+#pragma unroll 1
+  for (int al = 1; al < 5; al++) {
+    const int di = (al == 1) - (al == 3), dj = (al == 2) - (al == 4);
+    const uint8_t from = al == 1 ? NB_W : al == 2 ? NB_S : al == 3 ? NB_E : NB_N;
+    if (!(cl & from)) continue;
+    const int64_t ky = node_of(P, wrapc(i - di, P.nx), wrapc(j - dj, P.ny));
+    Slot r[5];
+    CD::load_raw(s, po, fl, ky, r);
+    C rho, fs[5];
+    CD::collide_raw(P, fl, r, rho, fs);
+    // fs[al] (a select, not a dynamic index into a local array)
+    const C g = al == 1 ? fs[1] : al == 2 ? fs[2] : al == 3 ? fs[3] : fs[4];
+    if (di != 0) sx += C(di) * g;
+    if (dj != 0) sy += C(dj) * g;
+  }
+  jx = sx;
+  jy = sy;
+}
+
 // One boundary node.  grad: rows of 4 gradient values (d_x u_x, d_y u_x,
 // d_x u_y, d_y u_y) of u at time t, indexed by the task's g[].
 //  reset (eqs. psi_phi_at_bound, correction-f): populations at t from the
@@ -529,7 +565,7 @@ __device__ __forceinline__ void hooke(const PlateDev &P, const U *g, U &sxx, U &
 //  accel (eq. acc_dirichlet or eq. acc_neumann, step n with loads at n dt /
 //    (n+1) dt): u, du/dt at t from buffer ua, Newmark update (eq.
 //    integration) into buffer ub (and ub2 if >= 0).
-template <class CD>
+template <class CD, bool VAR>
 __device__ void boundary_task(const DevState &s, const PlateDev &P, const BTask &T,
                               const typename CD::U *grad, int po, int pn, bool reset, bool accel,
                               int ua, int ub, int ub2, unsigned long long n) {
@@ -542,10 +578,18 @@ __device__ void boundary_task(const DevState &s, const PlateDev &P, const BTask 
     const U dv = gs[0] + gs[3];
     const U cu = gs[2] - gs[1];
     C jx, jy;
-    CD::flux(s, po, 0, k, P, jx, jy);
-    CD::store_eq(s, pn, 0, k, P, (C)dv, jx, jy);
-    CD::flux(s, po, 1, k, P, jx, jy);
-    CD::store_eq(s, pn, 1, k, P, (C)cu, jx, jy);
+    if (VAR && (P.readings & RD_FLUX_STREAMED)) {
+      const uint8_t cl = s.cls[k];
+      streamed_in_flux<CD>(s, P, B.i, B.j, cl, 0, po, jx, jy);
+      CD::store_eq(s, pn, 0, k, P, (C)dv, jx, jy);
+      streamed_in_flux<CD>(s, P, B.i, B.j, cl, 1, po, jx, jy);
+      CD::store_eq(s, pn, 1, k, P, (C)cu, jx, jy);
+    } else {
+      CD::flux(s, po, 0, k, P, jx, jy);
+      CD::store_eq(s, pn, 0, k, P, (C)dv, jx, jy);
+      CD::flux(s, po, 1, k, P, jx, jy);
+      CD::store_eq(s, pn, 1, k, P, (C)cu, jx, jy);
+    }
   }
   if (!accel) return;
   const U ux0 = ldg<U>(s.u[ua][0], k), uy0 = ldg<U>(s.u[ua][1], k);
@@ -611,14 +655,56 @@ __device__ void boundary_task(const DevState &s, const PlateDev &P, const BTask 
   if (!(fabs((double)nux) < 1e30) || !(fabs((double)nuy) < 1e30)) s.flag[0] = 1;
 }
 
+// Population AL that second-row node Q pulls from its upwind boundary node
+// y = x - c^AL by eq. LBE_mod under the plate's readings (used when they are
+// not R1 + M1): the average of y's populations at t - dt (buffer po) and of
+// their reset values at t (field from grad, flux of eq. correction-f by
+// reading R1 or R2), collided towards the equilibrium of its own moments (M1)
+// or of y's populations at t - dt (M2).
+template <class CD, int AL>
+__device__ typename CD::C pull_from_boundary(const DevState &s, const PlateDev &P, const STask &Q,
+                                             int fl, const typename CD::U *grad, int po) {
+  using C = typename CD::C;
+  using U = typename CD::U;
+  using Slot = typename CD::Slot;
+  constexpr int di = (AL == 1) - (AL == 3), dj = (AL == 2) - (AL == 4);
+  const int yi = wrapc(Q.i - di, P.nx), yj = wrapc(Q.j - dj, P.ny);
+  const int64_t ky = node_of(P, yi, yj);
+  Slot raw[5];
+  CD::load_raw(s, po, fl, ky, raw);
+  const U *gy = grad + 4 * Q.g[AL];
+  const C fld = fl == 0 ? (C)(gy[0] + gy[3]) : (C)(gy[2] - gy[1]);
+  C jx, jy, f[5], fnew[5];
+  if (P.readings & RD_FLUX_STREAMED)
+    streamed_in_flux<CD>(s, P, yi, yj, s.cls[ky], fl, po, jx, jy);
+  else
+    CD::raw_flux(raw, jx, jy);
+  CD::eq_pops(P, fl, fld, jx, jy, fnew);
+  CD::raw_to_pops(P, fl, raw, f);
+#pragma unroll
+  for (int q = 0; q < 5; q++) f[q] = C(0.5) * (fnew[q] + f[q]);
+  if (P.readings & RD_EQ_OLD) {
+    // f~ - 2 (f~ - f_eq(rho, J of the populations at t - dt))
+    C jox, joy, e[5];
+    CD::raw_flux(raw, jox, joy);
+    CD::eq_pops(P, fl, CD::raw_rho(raw), jox, joy, e);
+    return f[AL] - C(2.0) * (f[AL] - e[AL]);
+  }
+  C r, fs[5];
+  collide_pops<CD>(P, fl, f, r, fs);
+  return fs[AL];
+}
+
 // One field of one second-row node: its populations at t, pulled from the
 // upwind nodes at t - dt.  Those pulled from non-boundary upwind nodes were
 // left in side buffer sr by the march of the previous step; one leaving a
 // boundary node follows eq. LBE_mod: the average of the boundary node's
 // populations at t - dt (buffer po) and of their reset values at t (field
-// from grad, flux of the populations at t - dt), collided with the
-// equilibrium of their own moments.  Written to buffer pn.
-template <class CD>
+// from grad, flux by eq. correction-f as the plate's reading says: R1 that
+// of the populations at t - dt, R2 the streamed-in flux), collided with the
+// equilibrium of their own moments (M1) or of the boundary node's
+// populations at t - dt (M2).  Written to buffer pn.
+template <class CD, bool VAR>
 __device__ void second_row_task(const DevState &s, const PlateDev &P, const STask &Q, int fl,
                                 const typename CD::U *grad, int po, int pn, int sr) {
   using C = typename CD::C;
@@ -628,6 +714,16 @@ __device__ void second_row_task(const DevState &s, const PlateDev &P, const STas
   const int dj[5] = {0, 0, 1, 0, -1};
   const C *side = static_cast<const C *>(s.side[sr]);
   C fo[5];
+  if (VAR && P.readings != 0) {
+#pragma unroll
+    for (int al = 0; al < 5; al++) fo[al] = side[(int64_t)(fl * 5 + al) * s.nsec + Q.si];
+    if (Q.g[1] >= 0) fo[1] = pull_from_boundary<CD, 1>(s, P, Q, fl, grad, po);
+    if (Q.g[2] >= 0) fo[2] = pull_from_boundary<CD, 2>(s, P, Q, fl, grad, po);
+    if (Q.g[3] >= 0) fo[3] = pull_from_boundary<CD, 3>(s, P, Q, fl, grad, po);
+    if (Q.g[4] >= 0) fo[4] = pull_from_boundary<CD, 4>(s, P, Q, fl, grad, po);
+    CD::store(s, pn, fl, Q.node, P, fo);
+    return;
+  }
   Slot raw[5][5];
 #pragma unroll
   for (int al = 0; al < 5; al++) {
@@ -657,7 +753,9 @@ __device__ void second_row_task(const DevState &s, const PlateDev &P, const STas
 }
 
 // Prologue of an interior tile at step n (buffers sb): the boundary work
-// of step n - 1 for the boundary and second-row nodes of the tile and its
+// (readings R1 and M1 only: contexts with other readings run every step's
+// boundary work in k_boundary) of step n - 1 for the boundary and
+// second-row nodes of the tile and its
 // halo ring (resets and pulls into buffer sb.in, which the march then reads,
 // from the populations of t_{n-1} in buffer sb.prev and the side buffer
 // sb.sp) and the next boundary accelerations of the tile's own boundary
@@ -687,12 +785,13 @@ __device__ void prologue(const DevState &s, const Prologue &pro, int chunk, cons
   const unsigned long long n = s.counter[sb.in];
   for (int t = ch.b0 + tid; t < ch.b1; t += nthreads) {
     const BTask T = pro.bt[t];
-    boundary_task<CD>(s, P, T, grad, sb.prev, sb.in, true, T.accel != 0, sb.in, sb.out, -1, n);
+    boundary_task<CD, false>(s, P, T, grad, sb.prev, sb.in, true, T.accel != 0, sb.in, sb.out, -1,
+                             n);
   }
   const int nst = 2 * (ch.s1 - ch.s0);
   for (int t = tid; t < nst; t += nthreads) {
     const STask Q = pro.st[ch.s0 + (t >> 1)];
-    second_row_task<CD>(s, P, Q, t & 1, grad, sb.prev, sb.in, sb.sp);
+    second_row_task<CD, false>(s, P, Q, t & 1, grad, sb.prev, sb.in, sb.sp);
   }
   __syncthreads();
 }
@@ -740,11 +839,11 @@ __global__ void __launch_bounds__(kBoundaryThreads)
   const int nb = ch.b1 - ch.b0;
   if (tid < nb) {
     const BTask T = btask[ch.b0 + tid];
-    boundary_task<CD>(s, P, T, &grad[0][0], bp, bc, do_reset != 0, true, bc, ub, ub2, n);
+    boundary_task<CD, true>(s, P, T, &grad[0][0], bp, bc, do_reset != 0, true, bc, ub, ub2, n);
   } else if (do_reset) {
     const int t = tid - nb;
     if (ch.s0 + (t >> 1) < ch.s1)
-      second_row_task<CD>(s, P, stask[ch.s0 + (t >> 1)], t & 1, &grad[0][0], bp, bc, sr);
+      second_row_task<CD, true>(s, P, stask[ch.s0 + (t >> 1)], t & 1, &grad[0][0], bp, bc, sr);
   }
 }
 

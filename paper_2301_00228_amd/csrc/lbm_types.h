@@ -39,8 +39,16 @@ struct PlateDev {
   float scale[2];        // 16-bit storage scale of the deviation moments
   float iscale[2];
   int32_t integ;         // 0: v += dt a(t) (the paper's update); 1: central difference
-  int32_t pad;
+  int32_t readings;      // RD_* bits: readings of eqs. correction-f and LBE_mod
 };
+
+// Readings of two points Sec. 3.1 leaves open.  RD_FLUX_STREAMED (R2): the
+// flux J(x_k, t) of eq. correction-f is that of the post-collision
+// populations streaming into the boundary node from its body neighbours (a
+// missing one adds 0) instead of that of its own populations (R1).
+// RD_EQ_OLD (M2): the equilibrium of eq. LBE_mod is that of the boundary
+// node's populations at t instead of that of the averaged populations (M1).
+enum { RD_FLUX_STREAMED = 1, RD_EQ_OLD = 2 };
 
 // Interior-kernel tile: owned columns [x0, x1) and rows [y0, y1) of a plate;
 // chunk: index of its prologue work list (-1 = none).

@@ -21,6 +21,7 @@ STATUS = {0: "OK", -1: "INVAL", -2: "UNSTABLE_DT", -3: "NOMEM", -4: "DEVICE", -5
 STORE_F64, STORE_F32, STORE_F32DEV, STORE_F16DEV, STORE_BF16DEV = 0, 1, 2, 3, 4
 STORAGES = {"f64": 0, "f32": 1, "f32dev": 2, "f16dev": 3, "bf16dev": 4}
 BC_NEUMANN, BC_DIRICHLET = 0, 1
+READ_FLUX_STREAMED, READ_EQ_OLD = 1, 2
 
 # Every entry point declared in include/lbm.h.
 EXPORTS = ["lbm_create", "lbm_set_bc", "lbm_step", "lbm_fields", "lbm_fields_device", "lbm_info",
@@ -43,7 +44,7 @@ class lbm_plate(C.Structure):
                 ("dh", C.c_double), ("dt", C.c_double), ("sync_every", C.c_int32),
                 ("u0", C.POINTER(C.c_double)), ("v0", C.POINTER(C.c_double)),
                 ("e0", C.POINTER(C.c_double)), ("w0", C.POINTER(C.c_double)),
-                ("integrator", C.c_int32)]
+                ("integrator", C.c_int32), ("readings", C.c_int32)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -240,6 +241,10 @@ class Context:
             d.dh, d.dt = float(p["dh"]), float(p["dt"])
             d.sync_every = int(p.get("sync_every", 0))
             d.integrator = int(p.get("integrator", 0))
+            rd = p.get("readings", (0, 0))
+            # (flux reading of eq. correction-f: 0 R1 / 1 R2; equilibrium of
+            # eq. LBE_mod: 0 M1 / 1 M2) -> LBM_READ_* bits
+            d.readings = int(rd[0]) * READ_FLUX_STREAMED + int(rd[1]) * READ_EQ_OLD
             for name, shape in (("u0", (2, ny, nx)), ("v0", (2, ny, nx)), ("e0", (ny, nx)),
                                 ("w0", (ny, nx))):
                 a = _f64(p.get(name), shape, name)
@@ -378,7 +383,8 @@ def plate_dict(case):
     return {"nx": case.nx, "ny": case.ny, "mask": case.mask, "periodic": case.periodic,
             "lam": case.lam, "mu": case.mu, "rho": case.rho, "dh": case.dh, "dt": case.dt,
             "sync_every": case.sync_every, "u0": case.u0, "v0": case.v0, "e0": case.e0,
-            "w0": case.w0, "integrator": getattr(case, "integrator", 0)}
+            "w0": case.w0, "integrator": getattr(case, "integrator", 0),
+            "readings": getattr(case, "readings", (0, 0))}
 
 
 def context_for(cases, storage="f64", **kw):

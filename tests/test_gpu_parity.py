@@ -477,3 +477,55 @@ def test_graphs_of_any_step_count_are_bitwise_and_counted(tiling, overlap):
     assert info["syncs_done"] == total // 50
     for k in FIELDS:
         assert np.array_equal(got[k], ref[k]), (tiling, k)
+
+
+def _moving_boundary_cases(readings):
+    """A plate with a hole and ramped loads on both edge kinds, and a
+    clamped plate, with the given readings of eqs. correction-f / LBE_mod."""
+    hole = I.plate_with_hole(n=72, radius=10, sigma=3.0, steps=140, sync_every=50, a0_phi=0.99)
+    dt = hole.dt
+    rim = I.boundary_nodes(hole.mask)
+    rim = rim[(rim[:, 0] > 0) & (rim[:, 0] < hole.nx - 1) & (rim[:, 1] > 0) & (rim[:, 1] < hole.ny - 1)]
+    rng = np.random.default_rng(11)
+    hole.bcs.append(I.BoundaryData(rim, np.zeros(len(rim), np.uint8),
+                                   rng.uniform(-2e-4, 2e-4, (len(rim), 2)),
+                                   knots=np.array([[0.0, 0.0], [60 * dt, 1.0]])))
+    clamped = I.clamped_plate(n=80, ny=66, sigma=4.0, steps=131, sync_every=50, a0_phi=0.99)
+    for c in (hole, clamped):
+        c.readings = readings
+    return [hole, clamped]
+
+
+@pytest.mark.parametrize("readings", [(1, 0), (0, 1), (1, 1)])
+@pytest.mark.parametrize("tiling", [None, (64, 8, 0, 4, 0, 2, 4)])
+def test_reading_switches_r2_m2_match_the_oracle(readings, tiling):
+    """The R2 (streamed-in flux in eq. correction-f) and M2 (old state's
+    equilibrium in eq. LBE_mod) readings against the oracle's, which its pins
+    fix in closed form; each plate alone and both in one batch."""
+    cases = _moving_boundary_cases(readings)
+    refs = [run_case(c)[0] for c in cases]
+    for c, ref in zip(cases, refs):
+        print("case", c.name, "readings", readings, tiling, flush=True)
+        assert_parity(gpu_run(c, tiling=tiling), ref, what=f"{c.name} {readings}")
+    # in one batch with a default-reading plate (which then steps the same way)
+    plain = I.clamped_plate(n=40, ny=36, sigma=3.0, steps=140, sync_every=50, a0_phi=0.99)
+    ref_plain, _ = run_case(plain)
+    cases[1].steps = cases[0].steps
+    refs[1], _ = run_case(cases[1])
+    outs = gpu_run(cases + [plain], tiling=tiling)
+    for got, ref, c in zip(outs, refs + [ref_plain], cases + [plain]):
+        assert_parity(got, ref, what=f"batch {c.name}")
+
+
+def test_reading_switches_change_the_result_and_reject_autotune():
+    cases = _moving_boundary_cases((1, 1))
+    base = I.plate_with_hole(n=72, radius=10, sigma=3.0, steps=140, sync_every=50, a0_phi=0.99)
+    base.bcs = cases[0].bcs
+    a = gpu_run(cases[0])
+    b = gpu_run(base)
+    assert np.abs(a["e"] - b["e"]).max() > 1e-9 * np.abs(b["e"]).max()
+    with lbm.context_for(cases[0], "f64") as ctx:
+        ctx.step(3)
+        with pytest.raises(lbm.LbmError) as ei:
+            ctx.autotune(2)
+        assert ei.value.code == lbm.E_STATE
