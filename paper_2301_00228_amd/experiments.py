@@ -273,13 +273,15 @@ def _orders(sizes, a0s, storage, integ):
 
 
 def stability_sweep(L=64, a0s=(0.9999, 0.999, 0.99, 0.9), syncs=(0, 10, 50, 200), t_end=2.0,
-                    storage="f64"):
+                    storage="f64", readings=(0, 0)):
     """Blow-up time (units of L / c_s; None = stable to t_end) of the
-    tension example for each (a0_phi, synchronization period)."""
+    tension example for each (a0_phi, synchronization period), with the
+    given readings of eqs. correction-f / LBE_mod ((0, 0) = R1, M1)."""
     out = []
     for a0 in a0s:
         for l in syncs:
             case = paper_case("tension", L, l, t_end=t_end)
+            case.readings = tuple(readings)
             nu = case.nu
             case.dt = I.time_step(nu, a0)
             case.a0_phi = a0
@@ -300,6 +302,7 @@ def stability_sweep(L=64, a0s=(0.9999, 0.999, 0.99, 0.9), syncs=(0, 10, 50, 200)
                 except lbm.LbmError:
                     blew = done * case.dt / L
             out.append({"experiment": "stability_tension", "L": L, "a0_phi": a0, "sync_every": l,
+                        "readings": "R%dM%d" % (readings[0] + 1, readings[1] + 1),
                         "dt": case.dt, "steps": done, "blew_up_at": blew})
             print(json.dumps(out[-1]), file=sys.stderr, flush=True)
     return out
@@ -313,6 +316,9 @@ def main():
     ap.add_argument("--radii", type=int, nargs="+", default=[8, 12, 16, 24, 32])
     ap.add_argument("--periods", type=float, default=1.0)
     ap.add_argument("--storage", default="f64")
+    ap.add_argument("--readings", default="R1M1", choices=["R1M1", "R2M1", "R1M2", "R2M2", "all"],
+                    help="stability: readings of eqs. correction-f (R1 own flux, R2 streamed-in "
+                         "flux) and LBE_mod (M1 own moments, M2 old state's equilibrium)")
     args = ap.parse_args()
     import torch
     assert torch.cuda.is_available()
@@ -322,8 +328,11 @@ def main():
             print(json.dumps(r), flush=True)
         return
     if args.experiment == "stability":
-        for r in stability_sweep(L=args.L, storage=args.storage, t_end=args.t_end):
-            print(json.dumps(r), flush=True)
+        names = ["R1M1", "R2M1", "R1M2", "R2M2"] if args.readings == "all" else [args.readings]
+        for name in names:
+            rd = (int(name[1]) - 1, int(name[3]) - 1)
+            for r in stability_sweep(L=args.L, storage=args.storage, t_end=args.t_end, readings=rd):
+                print(json.dumps(r), flush=True)
         return
     if args.experiment == "disc":
         for R in args.radii:

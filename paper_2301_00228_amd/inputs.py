@@ -375,3 +375,18 @@ def large_batch(count=64, side=4096, strip=(65536, 2048), steps=2000, seed_index
         st.v0 = None
         cases.append(st)
     return cases
+
+
+def mixed_batch(steps=2000, seed_index=6):
+    """A small mixed batch for precision checks of the batched path against
+    the oracle: five rectangular plates of the 256-plate recipe (sides
+    U{128..320}, random clamped / free edges, one pulse each), a plate with
+    one elliptic hole and a strip with seeded elliptic holes (5 % of its
+    area, three pulses); a0_phi = 0.9999, synchronization every 50 steps."""
+    cases = plate_batch(count=5, side_lo=128, side_hi=320, steps=steps, seed_index=seed_index)
+    cases.append(plate_with_ellipse_hole(nx=200, ny=160, hole=(97.3, 81.6, 31.0, 17.5, 0.7),
+                                         a0_phi=0.9999, steps=steps, sync_every=50, sigma=6.0,
+                                         seed_index=seed_index))
+    cases.append(strip_with_holes(nx=480, ny=120, sigma=8.0, pulses=3, steps=steps,
+                                  seed_index=seed_index, a_lo=6.0, a_hi=20.0))
+    return cases
