@@ -126,7 +126,9 @@ struct lbm_ctx {
   BTask *d_btasks = nullptr;
   STask *d_stasks = nullptr;
   std::vector<LoadTable> loads;
-  std::vector<Tile> tiles;
+  std::vector<Tile> tiles;    // every tile (host lookups), with merged-away ones
+  std::vector<int> partner;   // per tile: the tile paired in as its second segment (-1: none)
+  std::vector<Tile> ltiles;   // the tiles launched: all but the merged-away ones
   std::vector<Tile> etiles;  // the single-step tiles (second launch of a two-step pair)
   std::vector<Tile> ftiles;  // single-step and frame tiles (first launch of an overlapped pair)
   std::vector<Tile> dtiles;  // deep two-step tiles (the side stream's launch)
@@ -707,6 +709,40 @@ void classify_two_step(lbm_ctx *c) {
   }
 }
 
+// Paired edge strips: on a plate with narrow first and last column strips
+// (edge_cols), each single-step tile of the last strip becomes the second
+// column segment of the single-step tile of the first strip with the same
+// rows and march direction, when both segments and their halo columns fit
+// the workgroup, so that the edge strips run with about twice the live
+// lanes and half the tiles.  The last-strip tile stays in the list
+// (TF_MERGED) for the host's lookups; the first-strip tile carries both
+// prologue work lists (build_tile_tables).
+void pair_edge_tiles(lbm_ctx *c) {
+  c->partner.assign(c->tiles.size(), -1);
+  if (c->edge_cols <= 0) return;
+  for (size_t p = 0; p < c->ph.size(); p++) {
+    const PlateHost &h = c->ph[p];
+    const int ec = c->edge_cols;
+    if (h.px || h.ns < 3 || h.sx[1] != ec || h.sx[(size_t)h.ns - 1] != h.nx - ec) continue;
+    const auto &L = h.strips[0];
+    const auto &R = h.strips[(size_t)h.ns - 1];
+    size_t ir = 0;
+    for (const auto &l : L) {
+      while (ir < R.size() && R[ir].first < l.first) ir++;
+      if (ir >= R.size()) break;
+      if (R[ir].first != l.first) continue;
+      Tile &A = c->tiles[(size_t)l.second];
+      Tile &B = c->tiles[(size_t)R[ir].second];
+      if (A.y1 != B.y1 || A.dir != B.dir || (A.flags & TF_TWO) || (B.flags & TF_TWO)) continue;
+      if ((A.x1 - A.x0) + (B.x1 - B.x0) + 4 > c->lanes) continue;
+      A.bx0 = B.x0;
+      A.bx1 = B.x1;
+      B.flags |= TF_MERGED;
+      c->partner[(size_t)l.second] = R[ir].second;
+    }
+  }
+}
+
 // Interior tiles: per plate, column strips of at most lanes-2 columns (of
 // equal width, or of a multiple of align columns but the last; with
 // edge_cols the first and last strip of a plate whose x axis is not periodic
@@ -845,6 +881,7 @@ void build_tiles(lbm_ctx *c) {
     }
   }
   classify_two_step(c);
+  pair_edge_tiles(c);
 }
 
 // Prologue work lists.  A boundary or second-row node belongs to every tile
@@ -875,9 +912,29 @@ void build_tile_tables(lbm_ctx *c) {
     const SecNode &S = c->sec[si];
     visit(S.plate, S.i, S.j, [&](int ti, bool) { ts[ti].push_back((int)si); });
   }
+  // a paired tile carries its second segment's lists too (a node in the
+  // rings of both segments is listed once, owned if either segment owns it)
+  for (size_t ti = 0; ti < c->tiles.size(); ti++) {
+    const int pb = ti < c->partner.size() ? c->partner[ti] : -1;
+    if (pb < 0) continue;
+    for (auto &e : tb[(size_t)pb]) tb[ti].push_back(e);
+    for (int si : ts[(size_t)pb]) ts[ti].push_back(si);
+    std::sort(tb[ti].begin(), tb[ti].end(), [](const std::pair<int64_t, int> &a,
+                                               const std::pair<int64_t, int> &b) {
+      return a.first != b.first ? a.first < b.first : a.second > b.second;
+    });
+    tb[ti].erase(std::unique(tb[ti].begin(), tb[ti].end(),
+                             [](const std::pair<int64_t, int> &a, const std::pair<int64_t, int> &b) {
+                               return a.first == b.first;
+                             }),
+                 tb[ti].end());
+    std::sort(ts[ti].begin(), ts[ti].end());
+    ts[ti].erase(std::unique(ts[ti].begin(), ts[ti].end()), ts[ti].end());
+  }
   typedef std::pair<int64_t, std::pair<int, int>> Key;
   std::vector<Key> g;
   for (size_t ti = 0; ti < c->tiles.size(); ti++) {
+    if (c->tiles[ti].flags & TF_MERGED) continue;
     if (tb[ti].empty() && ts[ti].empty()) continue;
     Tile &t = c->tiles[ti];
     const PlateHost &h = c->ph[t.plate];
@@ -1002,14 +1059,17 @@ lbm_status upload_tiles(lbm_ctx *c) {
   c->etiles.clear();
   c->ftiles.clear();
   c->dtiles.clear();
+  c->ltiles.clear();
   for (const Tile &t : c->tiles) {
+    if (t.flags & TF_MERGED) continue;
+    c->ltiles.push_back(t);
     if (!(t.flags & TF_TWO)) c->etiles.push_back(t);
     if ((t.flags & TF_TWO) && !(t.flags & TF_FRAME))
       c->dtiles.push_back(t);
     else
       c->ftiles.push_back(t);
   }
-  lbm_status st = upload_tile_list(c, c->tiles, c->d_tiles, c->tiles_cap);
+  lbm_status st = upload_tile_list(c, c->ltiles, c->d_tiles, c->tiles_cap);
   if (st) return st;
   st = upload_tile_list(c, c->ftiles, c->d_ftiles, c->ftiles_cap);
   if (st) return st;
@@ -1198,7 +1258,7 @@ hipError_t enqueue_segment(lbm_ctx *c, int64_t s, int64_t k, int &cur, int &prev
         e = join();
         if (e == hipSuccess)
           e = timed(3, st, [&] {
-            return launch_interior(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), c->lanes,
+            return launch_interior(c->storage, c->ds, c->d_tiles, (int)c->ltiles.size(), c->lanes,
                                    b1, p1, st);
           });
         if (e == hipSuccess)
@@ -1217,7 +1277,7 @@ hipError_t enqueue_segment(lbm_ctx *c, int64_t s, int64_t k, int &cur, int &prev
       e = join();
       if (e == hipSuccess)
         e = timed(0, st, [&] {
-          return launch_interior(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), c->lanes,
+          return launch_interior(c->storage, c->ds, c->d_tiles, (int)c->ltiles.size(), c->lanes,
                                  b1, p1, st);
         });
       have_f = false;
@@ -1240,7 +1300,7 @@ hipError_t enqueue_segment(lbm_ctx *c, int64_t s, int64_t k, int &cur, int &prev
   if (e != hipSuccess) return e;
   if (c->sync_every > 0 && (s + k) % c->sync_every == 0) {
     e = timed(2, st, [&] {
-      return launch_sync(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), c->lanes, c_now,
+      return launch_sync(c->storage, c->ds, c->d_tiles, (int)c->ltiles.size(), c->lanes, c_now,
                          st);
     });
   }
@@ -2047,7 +2107,7 @@ lbm_status lbm_info(const lbm_ctx *c, lbm_info_t *info) {
   info->tile_edge_rows = (c->edge_rows > 0 && c->edge_rows < c->rows) ? c->edge_rows : c->rows;
   info->tile_align = c->align;
   info->tile_steps = c->two ? 2 : 1;
-  info->n_tiles = (int32_t)c->tiles.size();
+  info->n_tiles = (int32_t)c->ltiles.size();
   info->tile_edge_cols = c->edge_cols;
   info->nodes_deep = c->two ? c->n_deep : 0;
   info->overlap = (c->two && c->overlap) ? 1 : 0;
@@ -2256,7 +2316,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
       return time_body([&](hipStream_t st, int k) {
         hipError_t e = hipSuccess;
         for (int i = 0; i < k && e == hipSuccess; i++)
-          e = launch_interior(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), T.lanes, sb,
+          e = launch_interior(c->storage, c->ds, c->d_tiles, (int)c->ltiles.size(), T.lanes, sb,
                               pro, st);
         return e;
       }, graph);
@@ -2297,7 +2357,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
     return 0.5 * time_body([&](hipStream_t st, int k) {
       hipError_t e = hipSuccess;
       for (int i = 0; i < k && e == hipSuccess; i++) {
-        e = launch_interior(c->storage, c->ds, c->d_tiles, (int)c->tiles.size(), T.lanes, b1, pro,
+        e = launch_interior(c->storage, c->ds, c->d_tiles, (int)c->ltiles.size(), T.lanes, b1, pro,
                             st);
         if (e == hipSuccess)
           e = launch_interior(c->storage, ds_b, c->d_etiles, (int)c->etiles.size(), T.lanes, b2,

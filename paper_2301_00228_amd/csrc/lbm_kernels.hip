@@ -1181,16 +1181,23 @@ __global__ void __launch_bounds__(TWL)
   const PlateDev P = s.plates[t.plate];
   const Kick<U> kick = kick_of<U>(P, s.counter[sb.in] == 0ull);
   const int lane = threadIdx.x;
-  const int w = t.x1 - t.x0;
-  int x = t.x0 - 1 + lane;
-  bool xok = lane <= w + 1;
+  // this lane's column segment: lanes 0 .. w+1 the first (a halo column on
+  // each side), the next wb+2 lanes the second of a paired tile; a lane
+  // reads its x-neighbours' values from lanes lane -+ 1, which for an owned
+  // column are its own segment's
+  const int wa = t.x1 - t.x0, wb = t.bx1 > t.bx0 ? t.bx1 - t.bx0 : 0;
+  const bool segb = wb > 0 && lane >= wa + 2;
+  const int sl = segb ? lane - (wa + 2) : lane;  // lane within the segment
+  const int w = segb ? wb : wa;
+  int x = (segb ? t.bx0 : t.x0) - 1 + sl;
+  bool xok = sl <= w + 1;
   if (x < 0 || x >= P.nx) {
     if (P.periodic & 1)
       x = wrapc(x, P.nx);
     else
       xok = false;
   }
-  const bool owned = xok && lane >= 1 && lane <= w;
+  const bool owned = xok && sl >= 1 && sl <= w;
   const bool py = (P.periodic & 2) != 0;
 
   // Node of row y in this lane's column; false if there is none.
@@ -1391,8 +1398,10 @@ __global__ void __launch_bounds__(TWL)
   if (tix >= ntiles) return;
   const Tile t = tiles[tix];
   const PlateDev P = s.plates[t.plate];
-  const int x = t.x0 + (int)threadIdx.x;
-  if (x >= t.x1) return;
+  // owned columns of the tile's first segment, then of its second
+  const int wa = t.x1 - t.x0, lane = (int)threadIdx.x;
+  const int x = lane < wa ? t.x0 + lane : t.bx0 + (lane - wa);
+  if (lane >= wa && x >= t.bx1) return;
   for (int y = t.y0; y < t.y1; y++) {
     const int64_t k = node_of(P, x, y);
     if (!(s.cls[k] & CL_IN)) continue;

@@ -51,7 +51,12 @@ struct PlateDev {
 enum { RD_FLUX_STREAMED = 1, RD_EQ_OLD = 2 };
 
 // Interior-kernel tile: owned columns [x0, x1) and rows [y0, y1) of a plate;
-// chunk: index of its prologue work list (-1 = none).
+// chunk: index of its prologue work list (-1 = none).  A single-step tile
+// may own a second column segment [bx0, bx1) of the same rows (bx1 > bx0):
+// the last strip of a plate paired with its first one, so that the narrow
+// edge strips of both sides share one workgroup (lanes 0 .. x1-x0+1 march
+// the first segment with its two halo columns, the next bx1-bx0+2 lanes the
+// second).
 struct Tile {
   int32_t plate, x0, x1, y0, y1;
   int32_t chunk;  // prologue work list (-1: none)
@@ -59,10 +64,15 @@ struct Tile {
   // bits 0-3: export the t_{n+1} populations of the first/last owned column
   // and row (W, E, S, N) of a two-step tile; bit 4: two-step tile; bit 5:
   // frame tile (a two-step tile with a node of a single-step tile in its
-  // two-node ring)
+  // two-node ring); bit 6: a tile whose area a paired tile owns as its
+  // second segment (kept for the host's lookups, never launched)
   int32_t flags;
+  int32_t bx0, bx1;  // second column segment (single-step tiles; bx1 <= bx0: none)
 };
-enum { TF_EXP_W = 1, TF_EXP_E = 2, TF_EXP_S = 4, TF_EXP_N = 8, TF_TWO = 16, TF_FRAME = 32 };
+enum {
+  TF_EXP_W = 1, TF_EXP_E = 2, TF_EXP_S = 4, TF_EXP_N = 8, TF_TWO = 16, TF_FRAME = 32,
+  TF_MERGED = 64
+};
 
 // Boundary node record (one per node with a missing neighbour).
 struct BndNode {

@@ -1,5 +1,10 @@
 """The interior tiling's invariants, checked on the host (no GPU).
 
+The launched tiles (a paired tile owning the last edge strip's rows as its
+second column segment) partition every plate, and each launched tile's
+prologue lists hold exactly the boundary and second-row nodes of its
+segments' areas and one-node rings.
+
 Two-step tiles take two steps per pass from their two-node ring, which must
 hold no boundary or second-row node; with overlapped pairs the deep two-step
 tiles run beside the single-step launches, which is race-free only if no
@@ -76,6 +81,8 @@ def test_plate_with_hole(harness, tiling, overlap):
     got = check(harness, [(case.mask, case.periodic)], tiling, overlap)
     if tiling == TILINGS[0]:
         assert got["single"] > 0 and got["frame"] > 0 and got["deep"] > 0
+    if tiling[6] > 0:  # edge strips: their tiles are paired
+        assert got["paired"] > 0
 
 
 @pytest.mark.parametrize("tiling", TILINGS[:4])
