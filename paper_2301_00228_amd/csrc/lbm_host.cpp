@@ -716,10 +716,14 @@ void classify_two_step(lbm_ctx *c) {
 // the workgroup, so that the edge strips run with about twice the live
 // lanes and half the tiles.  The last-strip tile stays in the list
 // (TF_MERGED) for the host's lookups; the first-strip tile carries both
-// prologue work lists (build_tile_tables).
+// prologue work lists (build_tile_tables).  Only with one-wave (64-lane)
+// tiles: in wider workgroups the pair still leaves most lanes idle, and
+// measured on the 8192^2 plate the longer joint prologue cost more than the
+// fewer tiles saved (256-lane F16DEV: -14 us on the second launch of a
+// pair, +62 us on the first).
 void pair_edge_tiles(lbm_ctx *c) {
   c->partner.assign(c->tiles.size(), -1);
-  if (c->edge_cols <= 0) return;
+  if (c->edge_cols <= 0 || c->lanes != 64) return;
   for (size_t p = 0; p < c->ph.size(); p++) {
     const PlateHost &h = c->ph[p];
     const int ec = c->edge_cols;
