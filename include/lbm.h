@@ -287,7 +287,10 @@ lbm_status lbm_info(const lbm_ctx *ctx, lbm_info_t *info);
  *  rows       rows per tile (>= 1);
  *  order      packing order of the tile list (0: plate by plate, row band by
  *             row band; 1: plate by plate, column strip by column strip; 2:
- *             as 0 with the largest plates first);
+ *             as 0 with the largest plates first; 3: plate by plate in
+ *             groups of 4 row bands, strip by strip within a group with the
+ *             group's bands of a strip consecutive, so that tiles sharing
+ *             halo rows or columns run at about the same time on one XCD);
  *  edge_rows  rows of the tiles whose area or one-node halo ring holds
  *             boundary or second-row nodes (those tiles finish the previous
  *             step's boundary work before their march; 0 or >= rows: no

@@ -758,10 +758,20 @@ void pair_edge_tiles(lbm_ctx *c) {
 // tiles march in opposite directions (dir).  order 0: plate by
 // plate, band by band (strips of a band adjacent); 1: plate by plate, strip
 // by strip (bands of a strip adjacent); 2: as 0 with the plates by decreasing
-// size.  Consecutive tiles land on the same XCD (see k_interior), so the
-// order decides which halo rows / columns share an L2.  With overlapped
+// size; 3: plate by plate in groups of kBandGroup row bands, within a group
+// strip by strip with the group's bands of one strip consecutive.
+// Consecutive tiles land on the same XCD (see k_interior) and start at about
+// the same time, so the order decides which halo rows / columns share an L2:
+// with order 0 a tile's x-neighbours are its list neighbours but its
+// y-neighbours a whole band of strips away (on an 8192^2 plate long gone from
+// the L2 when they read the shared halo rows); order 3 keeps both close, the
+// bands of a group marching in alternating directions so that each shared
+// pair of halo rows is read by its two tiles at the same end of their
+// marches.  With overlapped
 // two-step pairs the band pieces around those with boundary work are cut to
 // edge_rows as well (they hold the frame tiles, see classify_two_step).
+constexpr int kBandGroup = 4;
+
 void build_tiles(lbm_ctx *c) {
   c->tiles.clear();
   const int own = c->lanes - (c->two ? 4 : 2);
@@ -879,6 +889,12 @@ void build_tiles(lbm_ctx *c) {
     if (c->order == 1) {
       for (int s = 0; s < ns; s++)
         for (int b = 0; b < nb; b++) add(s, b);
+    } else if (c->order == 3) {
+      // groups of kBandGroup bands; in a group, strip by strip, the group's
+      // bands of a strip one after the other
+      for (int g = 0; g < nb; g += kBandGroup)
+        for (int s = 0; s < ns; s++)
+          for (int b = g; b < std::min(nb, g + kBandGroup); b++) add(s, b);
     } else {
       for (int b = 0; b < nb; b++)
         for (int s = 0; s < ns; s++) add(s, b);
@@ -2126,7 +2142,7 @@ lbm_status lbm_set_tiling(lbm_ctx *c, const lbm_tiling *t) {
   const int32_t lanes = t->lanes, rows = t->rows, order = t->order, edge_rows = t->edge_rows,
                 align = t->align, steps = t->steps, edge_cols = t->edge_cols;
   if ((lanes != 64 && lanes != 128 && lanes != 256) || rows < 1 || rows > 65536 || order < 0 ||
-      order > 2 || edge_rows < 0 || align < 0 || align > 4096 || steps < 0 || steps > 2 ||
+      order > 3 || edge_rows < 0 || align < 0 || align > 4096 || steps < 0 || steps > 2 ||
       edge_cols < 0 || edge_cols > lanes - 4)
     return fail(c, LBM_E_INVAL,
                 "lanes must be 64, 128 or 256, rows >= 1, order 0..2, edge_rows >= 0, "

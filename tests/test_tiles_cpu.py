@@ -67,7 +67,7 @@ def check(exe, plates, tiling, overlap=True):
 
 TILINGS = [(64, 8, 0, 4, 0, 2, 4), (64, 8, 0, 2, 16, 2, 8), (128, 16, 1, 4, 16, 2, 16),
            (256, 5, 2, 0, 0, 2, 0), (64, 3, 0, 1, 0, 2, 5), (128, 9, 0, 3, 0, 2, 4),
-           (64, 8, 0, 4, 0, 1, 0)]
+           (64, 8, 0, 4, 0, 1, 0), (128, 16, 3, 4, 16, 2, 16), (64, 8, 3, 4, 16, 2, 16)]
 
 
 def full(nx, ny):
