@@ -35,11 +35,11 @@ PRECISION_STEPS = 2000
 # autotuner picks for this workload on MI355X, pinned so that runs and the
 # committed rocprofv3 summaries use the same launches (--autotune tunes
 # again instead).
-TUNED = {"f64": ((128, 16, 0, 4, 16, 2, 16), False),
-         "f32": ((256, 16, 0, 8, 16, 2, 16), False),
-         "f32dev": ((256, 16, 0, 8, 16, 2, 16), False),
-         "f16dev": ((256, 16, 0, 8, 16, 2, 16), False),
-         "bf16dev": ((256, 16, 0, 8, 16, 2, 16), False)}
+TUNED = {"f64": ((128, 16, 3, 4, 16, 2, 16), False),
+         "f32": ((256, 16, 3, 8, 16, 2, 16), False),
+         "f32dev": ((256, 16, 3, 8, 16, 2, 16), False),
+         "f16dev": ((256, 16, 3, 8, 16, 2, 16), False),
+         "bf16dev": ((256, 16, 3, 8, 16, 2, 16), False)}
 VARIANTS = ("f32", "f32dev", "f16dev", "bf16dev")
 METRIC = "GLUPS + % HBM roofline, FP64 vs FP16/FP32-storage at ≤1e-3 rel L2"
 KIND_NAMES = {"deep": "deep tiles of overlapped pairs", "two_step": "first launch of a two-step pair",

@@ -2450,6 +2450,12 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
         consider(T);
       }
   }
+  {
+    // band groups (order 3): tiles sharing halo rows run together
+    lbm_tiling T = bt;
+    T.order = 3;
+    if (T.order != bt.order) consider(T);
+  }
   if (c->ph.size() > 1) {
     const lbm_tiling b0 = bt;
     for (int O : {1, 2}) {
