@@ -149,9 +149,10 @@ def main():
                     help="skip the untimed leg to step 2000 and the rel L2 errors")
     ap.add_argument("--profile-steps", type=int, default=8)
     ap.add_argument("--storage", default="f64", help="storage of the headline run")
-    ap.add_argument("--tiling", default="", metavar="L,R,O,E,A,S[,W]",
+    ap.add_argument("--tiling", default="", metavar="L,R,O,E,A,S[,W[,N]]",
                     help="interior tiling of the headline storage (lanes, rows, order, edge "
-                         "rows, alignment, steps, edge columns) instead of the pinned one")
+                         "rows, alignment, steps, edge columns, stream stores) instead of the "
+                         "pinned one")
     ap.add_argument("--overlap", type=int, default=-1, choices=(-1, 0, 1),
                     help="overlapped pairs of the headline storage (-1: the pinned choice)")
     ap.add_argument("--autotune", action="store_true",
@@ -242,7 +243,8 @@ def main():
     glups = nodes * K / dt / 1e9
     info, prof, kind, per, own, lups, bpu = roofline_of(ctx, args.storage, args.profile_steps)
     tile = [info["tile_lanes"], info["tile_rows"], info["tile_order"], info["tile_edge_rows"],
-            info["tile_align"], info["tile_steps"], info["tile_edge_cols"]]
+            info["tile_align"], info["tile_steps"], info["tile_edge_cols"],
+            info["tile_stream_stores"]]
     overlap = bool(info["overlap"])
     achieved = own * bpu / per / 1e9
     traffic = measured_traffic(args.storage, kind, tile, overlap)
@@ -295,7 +297,7 @@ def main():
                  "graph_steps": w2["graph_steps"],
                  "tile": [i2["tile_lanes"], i2["tile_rows"], i2["tile_order"],
                           i2["tile_edge_rows"], i2["tile_align"], i2["tile_steps"],
-                          i2["tile_edge_cols"]]}
+                          i2["tile_edge_cols"], i2["tile_stream_stores"]]}
             t2 = measured_traffic(st, k2, v["tile"], bool(i2["overlap"]))
             if t2:
                 v["kernel_measured_frac"] = round(t2 / per2 / 1e9 / HBM_PEAK_GBS, 4)

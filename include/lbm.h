@@ -277,6 +277,8 @@ typedef struct {
   int32_t graphs_cached;      /* captured step graphs held (see lbm_step)                   */
   int64_t steps_in_graphs;    /* steps run so far by replaying captured graphs              */
   int64_t syncs_done;         /* synchronization steps (Sec. 3.2) enqueued so far           */
+  int32_t tile_stream_stores; /* two-step passes store with nontemporal stores (lbm_tiling) */
+  int32_t pad;
 } lbm_info_t;
 lbm_status lbm_info(const lbm_ctx *ctx, lbm_info_t *info);
 
@@ -309,13 +311,21 @@ lbm_status lbm_info(const lbm_ctx *ctx, lbm_info_t *info);
  *             2 edge_cols + 2, the first and the last strip are edge_cols
  *             columns wide (the others as `align` says, between them), so
  *             that with steps = 2 the strips next to a boundary column are
- *             narrow and the rest of the plate takes two steps per pass.
+ *             narrow and the rest of the plate takes two steps per pass;
+ *  stream_stores  0 or 1: with steps = 2, the two-step tiles write the
+ *             state at the end of their pass with nontemporal stores (it is
+ *             not read again in that launch; the caches stay free for the
+ *             halo rows the neighbouring tiles read).  Faster where the
+ *             state streams through HBM with a large halo share (the
+ *             256-plate batch), slower where it stays in the Infinity Cache
+ *             (a 1024^2 FP64 plate); the autotuner decides.
  * Any tiling gives bitwise the same results.  May be changed between steps;
  * invalidates captured step graphs.  LBM_E_INVAL on values out of range
- * (align: 0..4096, edge_cols: 0..lanes-4). */
+ * (order: 0..3, align: 0..4096, edge_cols: 0..lanes-4, stream_stores: 0..1). */
 typedef struct {
   int32_t lanes, rows, order, edge_rows, align, steps;
   int32_t edge_cols;
+  int32_t stream_stores;
 } lbm_tiling;
 lbm_status lbm_set_tiling(lbm_ctx *ctx, const lbm_tiling *tiling);
 

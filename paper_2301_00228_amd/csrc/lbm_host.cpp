@@ -133,6 +133,7 @@ struct lbm_ctx {
   std::vector<Tile> ftiles;  // single-step and frame tiles (first launch of an overlapped pair)
   std::vector<Tile> dtiles;  // deep two-step tiles (the side stream's launch)
   int lanes = 128, rows = 32, order = 0, edge_rows = 0, align = 0, two = 0, edge_cols = 0;
+  int nt = 0;  // two-step passes store their final state with nontemporal stores
 
   std::vector<Buffer> bufs;
   DevState ds{};
@@ -1245,7 +1246,7 @@ hipError_t enqueue_segment(lbm_ctx *c, int64_t s, int64_t k, int &cur, int &prev
   };
   for (int64_t n = s; n < s + k && e == hipSuccess;) {
     if (c->two && s + k - n >= 2) {
-      const StepBufs b1{cur, T, prev, (int)(n & 1), cur ^ 1};
+      const StepBufs b1{cur, T, prev, (int)(n & 1), cur ^ 1, c->nt};
       const Prologue p1 = make_prologue(c, n > s);
       const StepBufs b2{T, cur ^ 1, cur, (int)((n + 1) & 1), -1};
       const Prologue p2 = make_prologue(c, true);
@@ -2124,6 +2125,7 @@ lbm_status lbm_info(const lbm_ctx *c, lbm_info_t *info) {
   info->tile_lanes = c->lanes;
   info->tile_rows = c->rows;
   info->tile_order = c->order;
+  info->tile_stream_stores = c->nt;
   info->tile_edge_rows = (c->edge_rows > 0 && c->edge_rows < c->rows) ? c->edge_rows : c->rows;
   info->tile_align = c->align;
   info->tile_steps = c->two ? 2 : 1;
@@ -2140,13 +2142,14 @@ lbm_status lbm_info(const lbm_ctx *c, lbm_info_t *info) {
 lbm_status lbm_set_tiling(lbm_ctx *c, const lbm_tiling *t) {
   if (!c || !t) return LBM_E_INVAL;
   const int32_t lanes = t->lanes, rows = t->rows, order = t->order, edge_rows = t->edge_rows,
-                align = t->align, steps = t->steps, edge_cols = t->edge_cols;
+                align = t->align, steps = t->steps, edge_cols = t->edge_cols,
+                stream = t->stream_stores;
   if ((lanes != 64 && lanes != 128 && lanes != 256) || rows < 1 || rows > 65536 || order < 0 ||
       order > 3 || edge_rows < 0 || align < 0 || align > 4096 || steps < 0 || steps > 2 ||
-      edge_cols < 0 || edge_cols > lanes - 4)
+      edge_cols < 0 || edge_cols > lanes - 4 || stream < 0 || stream > 1)
     return fail(c, LBM_E_INVAL,
-                "lanes must be 64, 128 or 256, rows >= 1, order 0..2, edge_rows >= 0, "
-                "align 0..4096, steps 0..2, edge_cols 0..lanes-4");
+                "lanes must be 64, 128 or 256, rows >= 1, order 0..3, edge_rows >= 0, "
+                "align 0..4096, steps 0..2, edge_cols 0..lanes-4, stream_stores 0..1");
   HIP_TRY(c, hipStreamSynchronize(c->stream), "synchronize");
   c->lanes = lanes;
   c->rows = rows;
@@ -2154,6 +2157,7 @@ lbm_status lbm_set_tiling(lbm_ctx *c, const lbm_tiling *t) {
   c->edge_rows = edge_rows;
   c->edge_cols = edge_cols;
   c->align = align;
+  c->nt = stream;
   c->two = steps == 2 ? 1 : 0;
   if (c->two) {
     lbm_status st3 = ensure_third(c);
@@ -2325,6 +2329,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
     c->edge_rows = T.edge_rows;
     c->edge_cols = T.edge_cols;
     c->align = T.align;
+    c->nt = T.stream_stores;
     c->two = T.steps == 2 ? 1 : 0;
     c->overlap = ov;
     build_tiles(c);
@@ -2343,7 +2348,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
     }
     // (two-step launches use buffer 2, in both state copies)
     if (!have_third(c) || !ds_b.pop[2][0][0] || !ds_b.u[2][0]) return 1e300;
-    const StepBufs b1{cur, 2, prev, (int)(n & 1), cur ^ 1};
+    const StepBufs b1{cur, 2, prev, (int)(n & 1), cur ^ 1, c->nt};
     const StepBufs b2{2, cur ^ 1, cur, (int)((n + 1) & 1), -1};
     const Prologue pro2 = make_prologue(c, true);
     if (ov && !c->dtiles.empty() && c->side) {
@@ -2387,7 +2392,8 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
     }, graph);
   };
   double best = 1e300;
-  lbm_tiling bt{c->lanes, c->rows, c->order, c->edge_rows, c->align, c->two ? 2 : 1, c->edge_cols};
+  lbm_tiling bt{c->lanes, c->rows, c->order, c->edge_rows, c->align, c->two ? 2 : 1, c->edge_cols,
+                c->nt};
   const bool ov_user = c->overlap;  // the search runs on one stream; the end may turn it on
   bool best_ov = false;
   auto consider = [&](lbm_tiling T) {
@@ -2416,7 +2422,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
   const int a0 = c->n_body >= ((int64_t)4 << 20) ? 16 : 0;
   for (int S = max_steps; S >= 1; S--)
     for (int L : {64, 128, 256})
-      for (int R : {8, 16, 32}) consider(lbm_tiling{L, R, 0, std::min(4, R / 2), a0, S});
+      for (int R : {8, 16, 32}) consider(lbm_tiling{L, R, 0, std::min(4, R / 2), a0, S, 0, 0});
   // Stage 2: one dimension at a time around the best.
   {
     const lbm_tiling b0 = bt;
@@ -2463,6 +2469,14 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
       T.order = O;
       consider(T);
     }
+  }
+  if (bt.steps == 2) {
+    // nontemporal stores of the two-step passes' final state: they leave the
+    // L2 to the halo rows where the state streams through HBM (8-row tiles
+    // of small plates), and lose where the state stays in the Infinity Cache
+    lbm_tiling T = bt;
+    T.stream_stores = bt.stream_stores ? 0 : 1;
+    consider(T);
   }
   // Overlapped pairs pay off where the single-step launches are short
   // beside the deep tiles' work: tried with the best tiling and frame tiles
@@ -2512,6 +2526,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
   c->edge_rows = bt.edge_rows;
   c->edge_cols = bt.edge_cols;
   c->align = bt.align;
+  c->nt = bt.stream_stores;
   c->two = bt.steps == 2 ? 1 : 0;
   c->overlap = best_ov;
   if (!c->two && !had_third) release_third(c);

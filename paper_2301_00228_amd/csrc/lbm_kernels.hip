@@ -97,9 +97,14 @@ template <class T>
 __device__ __forceinline__ T ldg(const void *p, int64_t k) {
   return static_cast<const T *>(p)[k];
 }
-template <class T>
+// Store; NT: a nontemporal store (data written once and not read again in
+// the launch: the final state of a two-step pass).
+template <class T, bool NT = false>
 __device__ __forceinline__ void stg(void *p, int64_t k, T v) {
-  static_cast<T *>(p)[k] = v;
+  if constexpr (NT)
+    __builtin_nontemporal_store(v, static_cast<T *>(p) + k);
+  else
+    static_cast<T *>(p)[k] = v;
 }
 
 template <class C>
@@ -151,10 +156,11 @@ struct PopCodec {
 #pragma unroll
     for (int q = 0; q < 5; q++) f[q] = ldg<T>(s.pop[b][fl][q], k);
   }
+  template <bool NT = false>
   __device__ static void store(const DevState &s, int b, int fl, int64_t k, const PlateDev &,
                                const C f[5]) {
 #pragma unroll
-    for (int q = 0; q < 5; q++) stg<T>(s.pop[b][fl][q], k, f[q]);
+    for (int q = 0; q < 5; q++) stg<T, NT>(s.pop[b][fl][q], k, f[q]);
   }
   __device__ static void flux(const DevState &s, int b, int fl, int64_t k, const PlateDev &,
                               C &jx, C &jy) {
@@ -284,18 +290,20 @@ struct DevCodec {
     load_moments(s, b, fl, k, P, m);
     moments_to_pops(P, fl, m, f);
   }
+  template <bool NT = false>
   __device__ static void store_moments(const DevState &s, int b, int fl, int64_t k,
                                        const PlateDev &P, const float m[5]) {
-    stg<float>(s.pop[b][fl][0], k, m[0]);
-    stg<float>(s.pop[b][fl][1], k, m[1]);
-    stg<float>(s.pop[b][fl][2], k, m[2]);
+    stg<float, NT>(s.pop[b][fl][0], k, m[0]);
+    stg<float, NT>(s.pop[b][fl][1], k, m[1]);
+    stg<float, NT>(s.pop[b][fl][2], k, m[2]);
     if (H == 0) {
-      stg<float>(s.pop[b][fl][3], k, m[3]);
-      stg<float>(s.pop[b][fl][4], k, m[4]);
+      stg<float, NT>(s.pop[b][fl][3], k, m[3]);
+      stg<float, NT>(s.pop[b][fl][4], k, m[4]);
     } else {
-      stg<uint32_t>(s.pop[b][fl][3], k, pack(m, P, fl));
+      stg<uint32_t, NT>(s.pop[b][fl][3], k, pack(m, P, fl));
     }
   }
+  template <bool NT = false>
   __device__ static void store(const DevState &s, int b, int fl, int64_t k, const PlateDev &P,
                                const C f[5]) {
     const float s13 = f[1] + f[3], s24 = f[2] + f[4];
@@ -306,7 +314,7 @@ struct DevCodec {
     m[2] = f[2] - f[4];
     m[3] = s13 - s24;
     m[4] = q - 4.0f * aw(P, fl) * m[0];
-    store_moments(s, b, fl, k, P, m);
+    store_moments<NT>(s, b, fl, k, P, m);
   }
   __device__ static void flux(const DevState &s, int b, int fl, int64_t k, const PlateDev &,
                               C &jx, C &jy) {
@@ -926,7 +934,7 @@ __device__ __forceinline__ int tile_index(int b, int q) { return (b & 7) * q + (
 // triple-buffered LDS slots (exA: t_n, exB: t_{n+1}).  deep: a launch of
 // deep tiles, never the run's first step (it does not read the step
 // counters, which the launches beside it may be writing).
-template <class CD, int TWL>
+template <class CD, int TWL, bool NT>
 __device__ void march2(const DevState &s, const Tile &t, const StepBufs &sb,
                        typename CD::C (*exA)[X_N][TWL], typename CD::C (*exB)[X_N][TWL],
                        bool deep) {
@@ -1111,13 +1119,15 @@ __device__ void march2(const DevState &s, const Tile &t, const StepBufs &sb,
       U nu2[4];
       finalize(exB, a - 2, b2_f0, b3_fb, fa1, b3_rho, rho1, uvB, g2, nu2, kickB);
       if (stepB) {
+        // NT: the pass's final state is not read again in this launch;
+        // nontemporal stores leave the caches to the halo rows
         const int64_t k = node_of(P, x, row_y(a - 2));
-        stg<U>(s.u[sb.out2][0], k, nu2[0]);
-        stg<U>(s.u[sb.out2][1], k, nu2[1]);
-        stg<U>(s.v[sb.out2][0], k, nu2[2]);
-        stg<U>(s.v[sb.out2][1], k, nu2[3]);
-        CD::store(s, sb.out2, 0, k, P, g2[0]);
-        CD::store(s, sb.out2, 1, k, P, g2[1]);
+        stg<U, NT>(s.u[sb.out2][0], k, nu2[0]);
+        stg<U, NT>(s.u[sb.out2][1], k, nu2[1]);
+        stg<U, NT>(s.v[sb.out2][0], k, nu2[2]);
+        stg<U, NT>(s.v[sb.out2][1], k, nu2[3]);
+        CD::template store<NT>(s, sb.out2, 0, k, P, g2[0]);
+        CD::template store<NT>(s, sb.out2, 1, k, P, g2[1]);
       }
     }
     // shift the stages by one row
@@ -1144,7 +1154,7 @@ __device__ void march2(const DevState &s, const Tile &t, const StepBufs &sb,
 // DEEP: a launch of deep two-step tiles (no boundary or single-step tile
 // within two nodes), which runs beside the launches that own the step
 // counters and so leaves them alone.
-template <int ST, int TWL, bool TWO, bool DEEP>
+template <int ST, int TWL, bool TWO, bool DEEP, bool NT>
 __global__ void __launch_bounds__(TWL)
     __attribute__((amdgpu_waves_per_eu((TWO && ST == LBM_STORE_F64 && TWL == 64) ? 3 : 1)))
     k_interior(DevState s, const Tile *__restrict__ tiles, int ntiles, int q, StepBufs sb,
@@ -1169,11 +1179,11 @@ __global__ void __launch_bounds__(TWL)
   if (tix >= ntiles) return;
   const Tile t = tiles[tix];
   if constexpr (DEEP) {
-    march2<CD, TWL>(s, t, sb, exs, exs + NS, true);
+    march2<CD, TWL, NT>(s, t, sb, exs, exs + NS, true);
     return;
   }
   if (TWO && sb.out2 >= 0 && (t.flags & TF_TWO)) {
-    march2<CD, TWL>(s, t, sb, exs, exs + NS, false);
+    march2<CD, TWL, NT>(s, t, sb, exs, exs + NS, false);
     return;
   }
   if (pro.enabled && t.chunk >= 0)
@@ -1518,7 +1528,7 @@ __global__ void k_cons_err(DevState s, int plate, int b, double *err) {
 
 // --------------------------------------------------------------- launchers
 
-template <int ST, bool TWO, bool DEEP>
+template <int ST, bool TWO, bool DEEP, bool NT>
 static hipError_t launch_interior_t(const DevState &s, const Tile *tiles, int ntiles, int lanes,
                                     const StepBufs &b, const Prologue &pro, hipStream_t st) {
   // at least one block: block 0 advances the step counter
@@ -1526,15 +1536,15 @@ static hipError_t launch_interior_t(const DevState &s, const Tile *tiles, int nt
   const dim3 grid(8 * q);
   switch (lanes) {
     case 64:
-      hipLaunchKernelGGL((k_interior<ST, 64, TWO, DEEP>), grid, dim3(64), 0, st, s, tiles, ntiles,
+      hipLaunchKernelGGL((k_interior<ST, 64, TWO, DEEP, NT>), grid, dim3(64), 0, st, s, tiles, ntiles,
                          q, b, pro);
       break;
     case 128:
-      hipLaunchKernelGGL((k_interior<ST, 128, TWO, DEEP>), grid, dim3(128), 0, st, s, tiles,
+      hipLaunchKernelGGL((k_interior<ST, 128, TWO, DEEP, NT>), grid, dim3(128), 0, st, s, tiles,
                          ntiles, q, b, pro);
       break;
     case 256:
-      hipLaunchKernelGGL((k_interior<ST, 256, TWO, DEEP>), grid, dim3(256), 0, st, s, tiles,
+      hipLaunchKernelGGL((k_interior<ST, 256, TWO, DEEP, NT>), grid, dim3(256), 0, st, s, tiles,
                          ntiles, q, b, pro);
       break;
     default:
@@ -1576,12 +1586,15 @@ static hipError_t launch_sync_t(const DevState &s, const Tile *tiles, int ntiles
 
 hipError_t launch_interior(int st, const DevState &s, const Tile *tiles, int ntiles, int lanes,
                            const StepBufs &b, const Prologue &pro, hipStream_t stream) {
-  if (b.out2 >= 0) {
-    LBM_DISPATCH(st, return (launch_interior_t<ST, true, false>(s, tiles, ntiles, lanes, b, pro,
-                                                                stream)));
+  if (b.out2 >= 0 && b.nt) {
+    LBM_DISPATCH(st, return (launch_interior_t<ST, true, false, true>(s, tiles, ntiles, lanes, b,
+                                                                      pro, stream)));
+  } else if (b.out2 >= 0) {
+    LBM_DISPATCH(st, return (launch_interior_t<ST, true, false, false>(s, tiles, ntiles, lanes, b,
+                                                                       pro, stream)));
   } else {
-    LBM_DISPATCH(st, return (launch_interior_t<ST, false, false>(s, tiles, ntiles, lanes, b, pro,
-                                                                 stream)));
+    LBM_DISPATCH(st, return (launch_interior_t<ST, false, false, false>(s, tiles, ntiles, lanes, b,
+                                                                        pro, stream)));
   }
   return hipSuccess;
 }
@@ -1591,8 +1604,13 @@ hipError_t launch_deep(int st, const DevState &s, const Tile *tiles, int ntiles,
   if (ntiles <= 0) return hipSuccess;
   if (b.out2 < 0) return hipErrorInvalidValue;
   const Prologue none{};
-  LBM_DISPATCH(st, return (launch_interior_t<ST, true, true>(s, tiles, ntiles, lanes, b, none,
-                                                             stream)));
+  if (b.nt) {
+    LBM_DISPATCH(st, return (launch_interior_t<ST, true, true, true>(s, tiles, ntiles, lanes, b,
+                                                                     none, stream)));
+  } else {
+    LBM_DISPATCH(st, return (launch_interior_t<ST, true, true, false>(s, tiles, ntiles, lanes, b,
+                                                                      none, stream)));
+  }
   return hipSuccess;
 }
 

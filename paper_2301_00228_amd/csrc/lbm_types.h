@@ -211,9 +211,11 @@ struct DevState {
 // `in`, t_{n+1} written to `out`; the boundary nodes' populations of t_{n-1}
 // in `prev` (read by the prologue); sp = n & 1 (the prologue reads side[sp],
 // the march writes side[sp ^ 1]).  A two-step tile (kind 1) writes t_{n+2}
-// to out2 and the t_{n+1} populations of its export bands to `out`.
+// to out2 (with nontemporal stores if nt) and the t_{n+1} populations of its
+// export bands to `out`.
 struct StepBufs {
   int in, out, prev, sp, out2;
+  int nt;  // two-step tiles write t_{n+2} with nontemporal stores
 };
 
 // Prologue work lists of the interior kernel (see k_interior); grad:

@@ -66,13 +66,13 @@ class lbm_info_t(C.Structure):
                 ("tile_align", C.c_int32), ("tile_steps", C.c_int32), ("n_tiles", C.c_int32),
                 ("tile_edge_cols", C.c_int32), ("nodes_deep", C.c_int64), ("overlap", C.c_int32),
                 ("graphs_cached", C.c_int32), ("steps_in_graphs", C.c_int64),
-                ("syncs_done", C.c_int64)]
+                ("syncs_done", C.c_int64), ("tile_stream_stores", C.c_int32), ("pad", C.c_int32)]
 
 
 class lbm_tiling(C.Structure):
     _fields_ = [("lanes", C.c_int32), ("rows", C.c_int32), ("order", C.c_int32),
                 ("edge_rows", C.c_int32), ("align", C.c_int32), ("steps", C.c_int32),
-                ("edge_cols", C.c_int32)]
+                ("edge_cols", C.c_int32), ("stream_stores", C.c_int32)]
 
 
 class lbm_shape(C.Structure):
@@ -348,9 +348,10 @@ class Context:
         self._check(library().lbm_info(self._h, C.byref(i)))
         return {f: getattr(i, f) for f, _ in lbm_info_t._fields_}
 
-    def set_tiling(self, lanes, rows, order=0, edge_rows=0, align=0, steps=1, edge_cols=0):
+    def set_tiling(self, lanes, rows, order=0, edge_rows=0, align=0, steps=1, edge_cols=0,
+                   stream_stores=0):
         t = lbm_tiling(int(lanes), int(rows), int(order), int(edge_rows), int(align), int(steps),
-                       int(edge_cols))
+                       int(edge_cols), int(stream_stores))
         self._check(library().lbm_set_tiling(self._h, C.byref(t)))
 
     def autotune(self, steps=5):

@@ -59,7 +59,8 @@ def timed(cases, storage, steps, warmup, tune=True, tiling=None, overlap=None):
             ctx.autotune(3)
         i = ctx.info()
         print("tuned", [i["tile_lanes"], i["tile_rows"], i["tile_order"], i["tile_edge_rows"],
-                        i["tile_align"], i["tile_steps"], i["tile_edge_cols"]],
+                        i["tile_align"], i["tile_steps"], i["tile_edge_cols"],
+                        i["tile_stream_stores"]],
               f"in {time.perf_counter() - t1:.1f} s", file=sys.stderr, flush=True)
     ctx.step(warmup)
     torch.cuda.synchronize()
@@ -95,7 +96,7 @@ def timed(cases, storage, steps, warmup, tune=True, tiling=None, overlap=None):
            "bytes_per_lup": info["bytes_per_update"], "boundary_nodes": info["boundary_nodes"],
            "tile": [info["tile_lanes"], info["tile_rows"], info["tile_order"],
                     info["tile_edge_rows"], info["tile_align"], info["tile_steps"],
-                    info["tile_edge_cols"]],
+                    info["tile_edge_cols"], info["tile_stream_stores"]],
            "device_GB": info["device_bytes"] / 1e9, "setup_s": setup}
     return ctx, res
 
@@ -108,7 +109,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--ref", default="f64",
                     help="storage of the reference run for the error ('' = no error)")
-    ap.add_argument("--tiling", default="", metavar="L,R,O,E,A,S,W",
+    ap.add_argument("--tiling", default="", metavar="L,R,O,E,A,S,W[,N]",
                     help="interior tiling instead of the autotuner's pick")
     ap.add_argument("--overlap", type=int, choices=(0, 1), default=None,
                     help="with --tiling: overlapped pairs on (1) or off (0); default on")

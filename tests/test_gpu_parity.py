@@ -214,7 +214,8 @@ def test_tilings_graphs_and_eager_are_bitwise_identical():
                            ((256, 5, 0, 0, 0, 2), True), ((64, 3, 0, 1, 0, 2), False),
                            ((64, 8, 0, 2, 16, 2, 8), True), ((128, 7, 1, 3, 0, 2, 5), False),
                            ((64, 8, 0, 4, 0, 1, 16), True), ((128, 16, 3, 4, 16, 2, 16), True),
-                           ((64, 8, 3, 4, 16, 2, 16), False), ((256, 7, 3, 2), True)]:
+                           ((64, 8, 3, 4, 16, 2, 16), False), ((256, 7, 3, 2), True),
+                           ((64, 8, 3, 4, 16, 2, 16, 1), True), ((128, 16, 0, 4, 0, 2, 4, 1), False)]:
         other = gpu_run(case, tiling=tiling, graphs=graphs)
         for k in FIELDS:
             assert np.array_equal(base[k], other[k]), (tiling, graphs, k)
