@@ -149,8 +149,10 @@ struct PopCodec {
     jy = r[2] - r[4];
   }
   __device__ static C raw_rho(const Slot r[5]) { return r[0] + ((r[1] + r[3]) + (r[2] + r[4])); }
-  __device__ static C aw(const PlateDev &P, int fl) { return (C)P.a[fl]; }
-  __device__ static C a0w(const PlateDev &P, int fl) { return (C)P.a0[fl]; }
+  // (a select of the two fields' values, not an index: fl may differ between
+  // lanes, and an indexed plate record would have to live in scratch memory)
+  __device__ static C aw(const PlateDev &P, int fl) { return (C)(fl ? P.a[1] : P.a[0]); }
+  __device__ static C a0w(const PlateDev &P, int fl) { return (C)(fl ? P.a0[1] : P.a0[0]); }
   __device__ static void load(const DevState &s, int b, int fl, int64_t k, const PlateDev &,
                               C f[5]) {
 #pragma unroll
@@ -203,16 +205,20 @@ struct DevCodec {
   using C = float;
   using U = double;
   using Slot = uint32_t;  // raw stored word of one slot
-  __device__ static C aw(const PlateDev &P, int fl) { return P.af[fl]; }
-  __device__ static C a0w(const PlateDev &P, int fl) { return P.a0f[fl]; }
+  __device__ static C aw(const PlateDev &P, int fl) { return fl ? P.af[1] : P.af[0]; }
+  __device__ static C a0w(const PlateDev &P, int fl) { return fl ? P.a0f[1] : P.a0f[0]; }
+  __device__ static float scale(const PlateDev &P, int fl) { return fl ? P.scale[1] : P.scale[0]; }
+  __device__ static float iscale(const PlateDev &P, int fl) {
+    return fl ? P.iscale[1] : P.iscale[0];
+  }
   __device__ static void unpack(uint32_t w, const PlateDev &P, int fl, float &n, float &d) {
     const uint16_t lo = (uint16_t)(w & 0xffffu), hi = (uint16_t)(w >> 16);
     if (H == 1) {
-      n = f16_to_f32(lo) * P.iscale[fl];
-      d = f16_to_f32(hi) * P.iscale[fl];
+      n = f16_to_f32(lo) * iscale(P, fl);
+      d = f16_to_f32(hi) * iscale(P, fl);
     } else {
-      n = bf16_to_f32(lo) * P.iscale[fl];
-      d = bf16_to_f32(hi) * P.iscale[fl];
+      n = bf16_to_f32(lo) * iscale(P, fl);
+      d = bf16_to_f32(hi) * iscale(P, fl);
     }
   }
   // N = m[3] and D = m[4] in the 16-bit type, rounded stochastically:
@@ -224,7 +230,7 @@ struct DevCodec {
   // from step to step, so the stored state stays a function of the state
   // it comes from (every tiling and launch shape gives the same bits).
   __device__ static uint32_t pack(const float m[5], const PlateDev &P, int fl) {
-    const float sn = m[3] * P.scale[fl], sd = m[4] * P.scale[fl];
+    const float sn = m[3] * scale(P, fl), sd = m[4] * scale(P, fl);
     uint16_t lo, hi;
     const uint32_t r = rand_bits(__float_as_uint(m[0]), __float_as_uint(m[1]),
                                  __float_as_uint(m[2]), (uint32_t)fl);
@@ -497,14 +503,15 @@ __device__ __forceinline__ U fd_vals(int code, U q0, U qa, U qb, const PlateDev 
   return ((c0 * q0 + ca * qa) + cb * qb) * sc;
 }
 
-// The same finite difference read straight from q at node (i, j).  Every
-// index touched lies in the body (the code was built from the mask).
-template <class U>
-__device__ __forceinline__ U fd_code(const U *q, const PlateDev &P, int i, int j, int ax,
-                                     int code) {
+// Further stencil nodes a and b of a finite difference with code `code`
+// along axis ax at node (i, j) (the node k0 itself where the stencil has no
+// such node).  Every index touched lies in the body (the code was built from
+// the mask).
+__device__ __forceinline__ void fd_nodes(const PlateDev &P, int i, int j, int ax, int code,
+                                         int64_t k0, int64_t &ka, int64_t &kb) {
   const int di = ax == 0 ? 1 : 0, dj = ax == 0 ? 0 : 1;
-  const int64_t k0 = node_of(P, i, j);
-  int64_t ka = k0, kb = k0;
+  ka = k0;
+  kb = k0;
   if (code == FD_CENTRAL || code == FD_FWD3 || code == FD_FWD2) {
     const int ip = wrapc(i + di, P.nx), jp = wrapc(j + dj, P.ny);
     ka = node_of(P, ip, jp);
@@ -515,7 +522,33 @@ __device__ __forceinline__ U fd_code(const U *q, const PlateDev &P, int i, int j
     ka = node_of(P, im, jm);
     if (code == FD_BWD3) kb = node_of(P, wrapc(im - di, P.nx), wrapc(jm - dj, P.ny));
   }
+}
+
+// The same finite difference read straight from q at node (i, j).
+template <class U>
+__device__ __forceinline__ U fd_code(const U *q, const PlateDev &P, int i, int j, int ax,
+                                     int code) {
+  const int64_t k0 = node_of(P, i, j);
+  int64_t ka, kb;
+  fd_nodes(P, i, j, ax, code, k0, ka, kb);
   return fd_vals<U>(code, q[k0], q[ka], q[kb], P);
+}
+
+// The values of q that the finite differences along x (code cx) and y
+// (code cy) at node (i, j) combine: v[0] at the node, v[1], v[2] the x
+// stencil's nodes a, b, v[3], v[4] the y stencil's.
+template <class U>
+__device__ __forceinline__ void fd_stencil_values(const U *q, const PlateDev &P, int i, int j,
+                                                  int cx, int cy, U v[5]) {
+  const int64_t k0 = node_of(P, i, j);
+  int64_t xa, xb, ya, yb;
+  fd_nodes(P, i, j, 0, cx, k0, xa, xb);
+  fd_nodes(P, i, j, 1, cy, k0, ya, yb);
+  v[0] = q[k0];
+  v[1] = q[xa];
+  v[2] = q[xb];
+  v[3] = q[ya];
+  v[4] = q[yb];
 }
 
 // Hooke's law (Sec. 2, eq. hooke) from a displacement gradient
@@ -565,18 +598,54 @@ __device__ void streamed_in_flux(const DevState &s, const PlateDev &P, int i, in
   jy = sy;
 }
 
+// Inputs of one boundary task read from memory: the flux of eq.
+// correction-f of both fields and u, du/dt at t.
+template <class CD>
+struct BoundaryIn {
+  typename CD::C jx[2], jy[2];
+  typename CD::U ux, uy, vx, vy;
+};
+
+// The reads of one boundary task (see boundary_task): the flux from the
+// populations at t - dt in buffer po (reading R1, or R2 for variant
+// contexts) if reset, u and du/dt from buffer ua if accel.  Kept apart from
+// the arithmetic so that a caller can issue them early.
+template <class CD, bool VAR>
+__device__ __forceinline__ void boundary_load(const DevState &s, const PlateDev &P, const BTask &T,
+                                              int po, bool reset, bool accel, int ua,
+                                              BoundaryIn<CD> &in) {
+  using U = typename CD::U;
+  const BndNode &B = T.b;
+  const int64_t k = B.node;
+  if (reset) {
+    if (VAR && (P.readings & RD_FLUX_STREAMED)) {
+      const uint8_t cl = s.cls[k];
+      streamed_in_flux<CD>(s, P, B.i, B.j, cl, 0, po, in.jx[0], in.jy[0]);
+      streamed_in_flux<CD>(s, P, B.i, B.j, cl, 1, po, in.jx[1], in.jy[1]);
+    } else {
+      CD::flux(s, po, 0, k, P, in.jx[0], in.jy[0]);
+      CD::flux(s, po, 1, k, P, in.jx[1], in.jy[1]);
+    }
+  }
+  if (accel) {
+    in.ux = ldg<U>(s.u[ua][0], k);
+    in.uy = ldg<U>(s.u[ua][1], k);
+    in.vx = ldg<U>(s.v[ua][0], k);
+    in.vy = ldg<U>(s.v[ua][1], k);
+  }
+}
+
 // One boundary node.  grad: rows of 4 gradient values (d_x u_x, d_y u_x,
 // d_x u_y, d_y u_y) of u at time t, indexed by the task's g[].
 //  reset (eqs. psi_phi_at_bound, correction-f): populations at t from the
-//    field div u / (curl u).e_z and the flux of the populations at t - dt
-//    (buffer po), written to buffer pn;
+//    field div u / (curl u).e_z and the flux in `in`, written to buffer pn;
 //  accel (eq. acc_dirichlet or eq. acc_neumann, step n with loads at n dt /
-//    (n+1) dt): u, du/dt at t from buffer ua, Newmark update (eq.
+//    (n+1) dt): from u, du/dt at t in `in`, Newmark update (eq.
 //    integration) into buffer ub (and ub2 if >= 0).
-template <class CD, bool VAR>
-__device__ void boundary_task(const DevState &s, const PlateDev &P, const BTask &T,
-                              const typename CD::U *grad, int po, int pn, bool reset, bool accel,
-                              int ua, int ub, int ub2, unsigned long long n) {
+template <class CD>
+__device__ __forceinline__ void boundary_finish(const DevState &s, const PlateDev &P, const BTask &T,
+                                const typename CD::U *grad, const BoundaryIn<CD> &in, int pn,
+                                bool reset, bool accel, int ub, int ub2, unsigned long long n) {
   using C = typename CD::C;
   using U = typename CD::U;
   const BndNode &B = T.b;
@@ -585,23 +654,11 @@ __device__ void boundary_task(const DevState &s, const PlateDev &P, const BTask 
   if (reset) {
     const U dv = gs[0] + gs[3];
     const U cu = gs[2] - gs[1];
-    C jx, jy;
-    if (VAR && (P.readings & RD_FLUX_STREAMED)) {
-      const uint8_t cl = s.cls[k];
-      streamed_in_flux<CD>(s, P, B.i, B.j, cl, 0, po, jx, jy);
-      CD::store_eq(s, pn, 0, k, P, (C)dv, jx, jy);
-      streamed_in_flux<CD>(s, P, B.i, B.j, cl, 1, po, jx, jy);
-      CD::store_eq(s, pn, 1, k, P, (C)cu, jx, jy);
-    } else {
-      CD::flux(s, po, 0, k, P, jx, jy);
-      CD::store_eq(s, pn, 0, k, P, (C)dv, jx, jy);
-      CD::flux(s, po, 1, k, P, jx, jy);
-      CD::store_eq(s, pn, 1, k, P, (C)cu, jx, jy);
-    }
+    CD::store_eq(s, pn, 0, k, P, (C)dv, in.jx[0], in.jy[0]);
+    CD::store_eq(s, pn, 1, k, P, (C)cu, in.jx[1], in.jy[1]);
   }
   if (!accel) return;
-  const U ux0 = ldg<U>(s.u[ua][0], k), uy0 = ldg<U>(s.u[ua][1], k);
-  const U vx0 = ldg<U>(s.v[ua][0], k), vy0 = ldg<U>(s.v[ua][1], k);
+  const U ux0 = in.ux, uy0 = in.uy, vx0 = in.vx, vy0 = in.vy;
   const U dt = (U)P.dt;
   U ax, ay;
   if (B.kind == LBM_BC_DIRICHLET) {
@@ -663,6 +720,17 @@ __device__ void boundary_task(const DevState &s, const PlateDev &P, const BTask 
   if (!(fabs((double)nux) < 1e30) || !(fabs((double)nuy) < 1e30)) s.flag[0] = 1;
 }
 
+// One boundary node's reset and acceleration (reads from buffers po and ua,
+// writes to pn, ub, ub2; see boundary_load and boundary_finish).
+template <class CD, bool VAR>
+__device__ void boundary_task(const DevState &s, const PlateDev &P, const BTask &T,
+                              const typename CD::U *grad, int po, int pn, bool reset, bool accel,
+                              int ua, int ub, int ub2, unsigned long long n) {
+  BoundaryIn<CD> in;
+  boundary_load<CD, VAR>(s, P, T, po, reset, accel, ua, in);
+  boundary_finish<CD>(s, P, T, grad, in, pn, reset, accel, ub, ub2, n);
+}
+
 // Population AL that second-row node Q pulls from its upwind boundary node
 // y = x - c^AL by eq. LBE_mod under the plate's readings (used when they are
 // not R1 + M1): the average of y's populations at t - dt (buffer po) and of
@@ -703,26 +771,88 @@ __device__ typename CD::C pull_from_boundary(const DevState &s, const PlateDev &
   return fs[AL];
 }
 
+// Inputs of one field of one second-row task read from memory (readings
+// R1 and M1): the side buffer's pulls and the stored state at t - dt of its
+// first upwind boundary node (direction a1, 0 if none).
+template <class CD>
+struct SecondRowIn {
+  typename CD::C fo[5];
+  typename CD::Slot raw[5];
+  int a1;
+};
+
+template <class CD>
+__device__ __forceinline__ void second_row_load(const DevState &s, const PlateDev &P,
+                                                const STask &Q, int fl, int po, int sr,
+                                                SecondRowIn<CD> &in) {
+  using C = typename CD::C;
+  const C *side = static_cast<const C *>(s.side[sr]);
+#pragma unroll
+  for (int al = 0; al < 5; al++) in.fo[al] = side[(int64_t)(fl * 5 + al) * s.nsec + Q.si];
+  in.a1 = Q.g[1] >= 0 ? 1 : Q.g[2] >= 0 ? 2 : Q.g[3] >= 0 ? 3 : Q.g[4] >= 0 ? 4 : 0;
+  if (in.a1 != 0) {
+    const int di = (in.a1 == 1) - (in.a1 == 3), dj = (in.a1 == 2) - (in.a1 == 4);
+    const int64_t ky = node_of(P, wrapc(Q.i - di, P.nx), wrapc(Q.j - dj, P.ny));
+    CD::load_raw(s, po, fl, ky, in.raw);
+  }
+}
+
 // One field of one second-row node: its populations at t, pulled from the
 // upwind nodes at t - dt.  Those pulled from non-boundary upwind nodes were
-// left in side buffer sr by the march of the previous step; one leaving a
-// boundary node follows eq. LBE_mod: the average of the boundary node's
-// populations at t - dt (buffer po) and of their reset values at t (field
-// from grad, flux by eq. correction-f as the plate's reading says: R1 that
-// of the populations at t - dt, R2 the streamed-in flux), collided with the
-// equilibrium of their own moments (M1) or of the boundary node's
-// populations at t - dt (M2).  Written to buffer pn.
+// left in the side buffer by the march of the previous step (in.fo); one
+// leaving a boundary node follows eq. LBE_mod: the average of the boundary
+// node's populations at t - dt (buffer po; in.raw for the first such node)
+// and of their reset values at t (field from grad, flux of eq. correction-f
+// by reading R1: that of the populations at t - dt), collided with the
+// equilibrium of their own moments (reading M1).  Written to buffer pn.
+template <class CD>
+__device__ __forceinline__ void second_row_finish(const DevState &s, const PlateDev &P, const STask &Q, int fl,
+                                  const typename CD::U *grad, int po, int pn,
+                                  const SecondRowIn<CD> &in) {
+  using C = typename CD::C;
+  using U = typename CD::U;
+  using Slot = typename CD::Slot;
+  C fo[5];
+#pragma unroll
+  for (int al = 0; al < 5; al++) fo[al] = in.fo[al];
+#pragma unroll
+  for (int al = 1; al < 5; al++) {
+    if (Q.g[al] < 0) continue;
+    Slot raw[5];
+    if (al == in.a1) {
+#pragma unroll
+      for (int q = 0; q < 5; q++) raw[q] = in.raw[q];
+    } else {
+      // a further upwind boundary node (a corner)
+      const int di = (al == 1) - (al == 3), dj = (al == 2) - (al == 4);
+      const int64_t ky = node_of(P, wrapc(Q.i - di, P.nx), wrapc(Q.j - dj, P.ny));
+      CD::load_raw(s, po, fl, ky, raw);
+    }
+    C f[5], r, fs[5];
+    CD::raw_to_pops(P, fl, raw, f);
+    const U *gy = grad + 4 * Q.g[al];
+    const C fld = fl == 0 ? (C)(gy[0] + gy[3]) : (C)(gy[2] - gy[1]);
+    C fnew[5], jx, jy;
+    CD::raw_flux(raw, jx, jy);
+    CD::eq_pops(P, fl, fld, jx, jy, fnew);
+#pragma unroll
+    for (int qq = 0; qq < 5; qq++) f[qq] = C(0.5) * (fnew[qq] + f[qq]);
+    collide_pops<CD>(P, fl, f, r, fs);
+    fo[al] = fs[al];
+  }
+  CD::store(s, pn, fl, Q.node, P, fo);
+}
+
+// One field of one second-row node under the plate's readings (buffers po,
+// pn, side buffer sr): R1 and M1 by second_row_load and second_row_finish;
+// the variant readings (VAR contexts only) through pull_from_boundary.
 template <class CD, bool VAR>
 __device__ void second_row_task(const DevState &s, const PlateDev &P, const STask &Q, int fl,
                                 const typename CD::U *grad, int po, int pn, int sr) {
   using C = typename CD::C;
-  using U = typename CD::U;
-  using Slot = typename CD::Slot;
-  const int di[5] = {0, 1, 0, -1, 0};
-  const int dj[5] = {0, 0, 1, 0, -1};
-  const C *side = static_cast<const C *>(s.side[sr]);
-  C fo[5];
   if (VAR && P.readings != 0) {
+    const C *side = static_cast<const C *>(s.side[sr]);
+    C fo[5];
 #pragma unroll
     for (int al = 0; al < 5; al++) fo[al] = side[(int64_t)(fl * 5 + al) * s.nsec + Q.si];
     if (Q.g[1] >= 0) fo[1] = pull_from_boundary<CD, 1>(s, P, Q, fl, grad, po);
@@ -732,32 +862,9 @@ __device__ void second_row_task(const DevState &s, const PlateDev &P, const STas
     CD::store(s, pn, fl, Q.node, P, fo);
     return;
   }
-  Slot raw[5][5];
-#pragma unroll
-  for (int al = 0; al < 5; al++) {
-    fo[al] = side[(int64_t)(fl * 5 + al) * s.nsec + Q.si];
-    if (Q.g[al] >= 0) {
-      // upwind boundary node x - c^alpha dt
-      const int64_t ky = node_of(P, wrapc(Q.i - di[al], P.nx), wrapc(Q.j - dj[al], P.ny));
-      CD::load_raw(s, po, fl, ky, raw[al]);
-    }
-  }
-#pragma unroll
-  for (int al = 0; al < 5; al++) {
-    if (Q.g[al] < 0) continue;
-    C f[5], r, fs[5];
-    CD::raw_to_pops(P, fl, raw[al], f);
-    const U *gy = grad + 4 * Q.g[al];
-    const C fld = fl == 0 ? (C)(gy[0] + gy[3]) : (C)(gy[2] - gy[1]);
-    C fnew[5], jx, jy;
-    CD::raw_flux(raw[al], jx, jy);
-    CD::eq_pops(P, fl, fld, jx, jy, fnew);
-#pragma unroll
-    for (int qq = 0; qq < 5; qq++) f[qq] = C(0.5) * (fnew[qq] + f[qq]);
-    collide_pops<CD>(P, fl, f, r, fs);
-    fo[al] = fs[al];
-  }
-  CD::store(s, pn, fl, Q.node, P, fo);
+  SecondRowIn<CD> in;
+  second_row_load<CD>(s, P, Q, fl, po, sr, in);
+  second_row_finish<CD>(s, P, Q, fl, grad, po, pn, in);
 }
 
 // Prologue of an interior tile at step n (buffers sb): the boundary work
@@ -769,37 +876,74 @@ __device__ void second_row_task(const DevState &s, const PlateDev &P, const STas
 // sb.sp) and the next boundary accelerations of the tile's own boundary
 // nodes (u buffer sb.in to sb.out).  Gradients of u(t_n) go to LDS (lds,
 // lds_bytes: the march's exchange buffer, unused until the march starts) if
-// they fit, else to a per-tile scratch area in global memory.
+// they fit, else to a per-tile scratch area in global memory.  `plate` is
+// the tile's plate (the chunk's).
+//
+// The prologue is a chain of dependent memory reads on a tile's critical
+// path.  Each lane's first gradient node, boundary task and second-row task
+// therefore read their records first and then all their inputs (stencil
+// values of u, the flux and u, du/dt of the boundary node, the side-buffer
+// pulls and the first upwind boundary node's state) before any of them is
+// used, so that the chain is records -> inputs -> barrier -> arithmetic and
+// stores; further items (lists longer than the workgroup) follow one by one.
 template <class CD>
-__device__ void prologue(const DevState &s, const Prologue &pro, int chunk, const StepBufs &sb,
-                         int tid, int nthreads, void *lds, int lds_bytes) {
+__device__ void prologue(const DevState &s, const Prologue &pro, int chunk, int plate,
+                         const StepBufs &sb, int tid, int nthreads, void *lds, int lds_bytes) {
   using U = typename CD::U;
   const TileChunk ch = pro.chunks[chunk];
-  const PlateDev P = s.plates[ch.plate];
+  const PlateDev P = s.plates[plate];
   const bool in_lds = (int64_t)(ch.g1 - ch.g0) * 4 * (int64_t)sizeof(U) <= (int64_t)lds_bytes;
   U *grad = in_lds ? static_cast<U *>(lds) : static_cast<U *>(pro.grad) + (int64_t)4 * ch.g0;
   const U *ux = static_cast<const U *>(s.u[sb.in][0]);
   const U *uy = static_cast<const U *>(s.u[sb.in][1]);
-  for (int g = ch.g0 + tid; g < ch.g1; g += nthreads) {
-    const TGradNode G = pro.gn[g];
+  const unsigned long long n = s.counter[sb.in];
+  const int nst = 2 * (ch.s1 - ch.s0);
+  const int g = ch.g0 + tid, b = ch.b0 + tid;
+  const bool hg = g < ch.g1, hb = b < ch.b1, hs = tid < nst;
+  TGradNode G{};
+  BTask T{};
+  STask Q{};
+  if (hg) G = pro.gn[g];
+  if (hb) T = pro.bt[b];
+  if (hs) Q = pro.st[ch.s0 + (tid >> 1)];
+  U gu[2][5];
+  if (hg) {
     const int cx = G.code & 7, cy = (G.code >> 3) & 7;
-    U *d = grad + 4 * (g - ch.g0);
-    d[0] = fd_code<U>(ux, P, G.i, G.j, 0, cx);
-    d[1] = fd_code<U>(ux, P, G.i, G.j, 1, cy);
-    d[2] = fd_code<U>(uy, P, G.i, G.j, 0, cx);
-    d[3] = fd_code<U>(uy, P, G.i, G.j, 1, cy);
+    fd_stencil_values<U>(ux, P, G.i, G.j, cx, cy, gu[0]);
+    fd_stencil_values<U>(uy, P, G.i, G.j, cx, cy, gu[1]);
+  }
+  BoundaryIn<CD> bin;
+  if (hb) boundary_load<CD, false>(s, P, T, sb.prev, true, T.accel != 0, sb.in, bin);
+  SecondRowIn<CD> sin;
+  if (hs) second_row_load<CD>(s, P, Q, tid & 1, sb.prev, sb.sp, sin);
+  for (int g2 = g; g2 < ch.g1; g2 += nthreads) {
+    if (g2 != g) {
+      G = pro.gn[g2];
+      const int cx = G.code & 7, cy = (G.code >> 3) & 7;
+      fd_stencil_values<U>(ux, P, G.i, G.j, cx, cy, gu[0]);
+      fd_stencil_values<U>(uy, P, G.i, G.j, cx, cy, gu[1]);
+    }
+    const int cx = G.code & 7, cy = (G.code >> 3) & 7;
+    U *d = grad + 4 * (g2 - ch.g0);
+    d[0] = fd_vals<U>(cx, gu[0][0], gu[0][1], gu[0][2], P);
+    d[1] = fd_vals<U>(cy, gu[0][0], gu[0][3], gu[0][4], P);
+    d[2] = fd_vals<U>(cx, gu[1][0], gu[1][1], gu[1][2], P);
+    d[3] = fd_vals<U>(cy, gu[1][0], gu[1][3], gu[1][4], P);
   }
   __syncthreads();
-  const unsigned long long n = s.counter[sb.in];
-  for (int t = ch.b0 + tid; t < ch.b1; t += nthreads) {
-    const BTask T = pro.bt[t];
-    boundary_task<CD, false>(s, P, T, grad, sb.prev, sb.in, true, T.accel != 0, sb.in, sb.out, -1,
-                             n);
+  for (int b2 = b; b2 < ch.b1; b2 += nthreads) {
+    if (b2 != b) {
+      T = pro.bt[b2];
+      boundary_load<CD, false>(s, P, T, sb.prev, true, T.accel != 0, sb.in, bin);
+    }
+    boundary_finish<CD>(s, P, T, grad, bin, sb.in, true, T.accel != 0, sb.out, -1, n);
   }
-  const int nst = 2 * (ch.s1 - ch.s0);
   for (int t = tid; t < nst; t += nthreads) {
-    const STask Q = pro.st[ch.s0 + (t >> 1)];
-    second_row_task<CD, false>(s, P, Q, t & 1, grad, sb.prev, sb.in, sb.sp);
+    if (t != tid) {
+      Q = pro.st[ch.s0 + (t >> 1)];
+      second_row_load<CD>(s, P, Q, t & 1, sb.prev, sb.sp, sin);
+    }
+    second_row_finish<CD>(s, P, Q, t & 1, grad, sb.prev, sb.in, sin);
   }
   __syncthreads();
 }
@@ -1187,7 +1331,7 @@ __global__ void __launch_bounds__(TWL)
     return;
   }
   if (pro.enabled && t.chunk >= 0)
-    prologue<CD>(s, pro, t.chunk, sb, (int)threadIdx.x, TWL, exs, (int)sizeof(exs));
+    prologue<CD>(s, pro, t.chunk, t.plate, sb, (int)threadIdx.x, TWL, exs, (int)sizeof(exs));
   const PlateDev P = s.plates[t.plate];
   const Kick<U> kick = kick_of<U>(P, s.counter[sb.in] == 0ull);
   const int lane = threadIdx.x;
