@@ -332,8 +332,9 @@ lbm_status lbm_set_tiling(lbm_ctx *ctx, const lbm_tiling *tiling);
 /* Autotuner: time one step's interior launches (with the boundary work they
  * carry) on this context's plates for the tilings of a two-stage search
  * (steps x lanes x rows, then edge rows, edge columns, alignment, rows, the
- * band-group order 3 and -- with several plates -- orders 1 and 2 one at a
- * time around the best, about 30 tilings),
+ * band-group order 3, -- with several plates -- orders 1 and 2, nontemporal
+ * stores, and rows with edge rows once more, one at a time around the best,
+ * about 35 tilings),
  * `steps` launches each, and keep the fastest.  Repeating those launches
  * leaves the state unchanged, except at step 0, at a synchronization step
  * and right after a two-step pair, where the autotuner first takes one real

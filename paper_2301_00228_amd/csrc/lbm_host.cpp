@@ -2478,6 +2478,20 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t steps, double *best_ms) {
     T.stream_stores = bt.stream_stores ? 0 : 1;
     consider(T);
   }
+  {
+    // rows and edge rows once more, with the packing order and stores now
+    // chosen: on the 256-plate batch 16-row tiles with 8-row edge tiles win
+    // only with band groups and nontemporal stores (+3 % over 8 / 4)
+    const lbm_tiling b0 = bt;
+    for (int R : {b0.rows / 2, b0.rows, b0.rows * 2})
+      for (int E : {b0.edge_rows, R / 2})
+        if (R >= 4 && R <= 64 && !(R == b0.rows && E == b0.edge_rows)) {
+          lbm_tiling T = b0;
+          T.rows = R;
+          T.edge_rows = E;
+          consider(T);
+        }
+  }
   // Overlapped pairs pay off where the single-step launches are short
   // beside the deep tiles' work: tried with the best tiling and frame tiles
   // of 2 and 4 rows, and kept if at least 3 % faster (the timed pairs lack
