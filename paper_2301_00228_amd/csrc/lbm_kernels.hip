@@ -524,19 +524,10 @@ __device__ __forceinline__ void fd_nodes(const PlateDev &P, int i, int j, int ax
   }
 }
 
-// The same finite difference read straight from q at node (i, j).
-template <class U>
-__device__ __forceinline__ U fd_code(const U *q, const PlateDev &P, int i, int j, int ax,
-                                     int code) {
-  const int64_t k0 = node_of(P, i, j);
-  int64_t ka, kb;
-  fd_nodes(P, i, j, ax, code, k0, ka, kb);
-  return fd_vals<U>(code, q[k0], q[ka], q[kb], P);
-}
-
 // The values of q that the finite differences along x (code cx) and y
-// (code cy) at node (i, j) combine: v[0] at the node, v[1], v[2] the x
-// stencil's nodes a, b, v[3], v[4] the y stencil's.
+// (code cy) at node (i, j) combine, read straight from q: v[0] at the node,
+// v[1], v[2] the x stencil's nodes a, b, v[3], v[4] the y stencil's (fd_vals
+// of (v[0], v[1], v[2]) is d/dx, of (v[0], v[3], v[4]) d/dy).
 template <class U>
 __device__ __forceinline__ void fd_stencil_values(const U *q, const PlateDev &P, int i, int j,
                                                   int cx, int cy, U v[5]) {
