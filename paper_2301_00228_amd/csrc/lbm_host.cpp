@@ -717,14 +717,13 @@ void classify_two_step(lbm_ctx *c) {
 // the workgroup, so that the edge strips run with about twice the live
 // lanes and half the tiles.  The last-strip tile stays in the list
 // (TF_MERGED) for the host's lookups; the first-strip tile carries both
-// prologue work lists (build_tile_tables).  Only with one-wave (64-lane)
-// tiles: in wider workgroups the pair still leaves most lanes idle, and
-// measured on the 8192^2 plate the longer joint prologue cost more than the
-// fewer tiles saved (256-lane F16DEV: -14 us on the second launch of a
-// pair, +62 us on the first).
+// prologue work lists (build_tile_tables).  Any workgroup size: since the
+// prologue issues its reads together, the joint prologue of a pair costs
+// little more than one, and on the 8192^2 plate pairs take 15-35 us off
+// the second launch of 128- and 256-lane tilings at no cost to the first.
 void pair_edge_tiles(lbm_ctx *c) {
   c->partner.assign(c->tiles.size(), -1);
-  if (c->edge_cols <= 0 || c->lanes != 64) return;
+  if (c->edge_cols <= 0) return;
   for (size_t p = 0; p < c->ph.size(); p++) {
     const PlateHost &h = c->ph[p];
     const int ec = c->edge_cols;
