@@ -334,16 +334,17 @@ lbm_status lbm_set_tiling(lbm_ctx *ctx, const lbm_tiling *tiling);
  * (steps x lanes x rows, then edge rows, edge columns, alignment, rows, the
  * band-group order 3, -- with several plates -- orders 1 and 2, nontemporal
  * stores, and rows with edge rows once more, one at a time around the best,
- * about 35 tilings),
- * `steps` launches each, and keep the fastest.  Repeating those launches
- * leaves the state unchanged, except at step 0, at a synchronization step
- * and right after a two-step pair, where the autotuner first takes one real
- * step (steps_done grows by one; the trajectory is the same as without the
- * autotuner).  The search times one-stream pairs; with overlapped pairs
- * allowed (lbm_use_overlap on, the default) the best two-step tiling is then
- * timed overlapped (also with frame tiles of 2 and 4 rows) against one
- * stream, both captured in HIP graphs as lbm_step runs them, and overlap is
- * kept on only if that is at least 3 % faster, else turned off.  The result
+ * about 35 tilings), `steps` launches and at least 10 ms each, eager, on one
+ * stream.  Repeating those launches leaves the state unchanged, except at
+ * step 0, at a synchronization step and right after a two-step pair, where
+ * the autotuner first takes one real step (steps_done grows by one; the
+ * trajectory is the same as without the autotuner).  The three fastest are
+ * then timed again captured in HIP graphs as lbm_step runs them, on one
+ * stream and -- with overlapped pairs allowed (lbm_use_overlap on, the
+ * default) -- overlapped (frame tiles of their own edge rows, 2 and 4 rows);
+ * the fastest one-stream tiling is kept unless an overlapped one is at least
+ * 3 % faster (then overlap is turned on, else off).  Nontemporal stores are
+ * not tried when the state fits in the 256 MB Infinity Cache.  The result
  * applies to this context only (every context starts from the same default
  * tiling, whatever ran before in the process).  best_ms (nullable) receives
  * the fastest interior time per step (for two-step tilings half the time of
