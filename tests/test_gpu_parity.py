@@ -215,7 +215,9 @@ def test_tilings_graphs_and_eager_are_bitwise_identical():
                            ((64, 8, 0, 2, 16, 2, 8), True), ((128, 7, 1, 3, 0, 2, 5), False),
                            ((64, 8, 0, 4, 0, 1, 16), True), ((128, 16, 3, 4, 16, 2, 16), True),
                            ((64, 8, 3, 4, 16, 2, 16), False), ((256, 7, 3, 2), True),
-                           ((64, 8, 3, 4, 16, 2, 16, 1), True), ((128, 16, 0, 4, 0, 2, 4, 1), False)]:
+                           ((64, 8, 3, 4, 16, 2, 16, 1), True), ((128, 16, 0, 4, 0, 2, 4, 1), False),
+                           ((256, 16, 3, 8, 16, 2, 16), True), ((64, 16, 3, 8, 16, 2, 16, 1), False),
+                           ((256, 8, 0, 4, 8, 2, 8, 1), True)]:
         other = gpu_run(case, tiling=tiling, graphs=graphs)
         for k in FIELDS:
             assert np.array_equal(base[k], other[k]), (tiling, graphs, k)
@@ -247,7 +249,11 @@ def test_autotune_keeps_the_trajectory(first):
 
 
 TWO_STEP = [(64, 8, 0, 2, 0, 2), (128, 16, 0, 4, 16, 2), (256, 5, 1, 0, 0, 2), (64, 8, 0, 4, 16, 2, 8),
-            (128, 9, 2, 2, 0, 2, 4)]
+            (128, 9, 2, 2, 0, 2, 4),
+            # the 8192^2 bench plate's FP64 tiling (256-lane tiles, paired edge strips)
+            (256, 16, 3, 8, 16, 2, 16),
+            # the 256-plate batch's (16-row tiles, 8-row edge tiles, stream stores)
+            (64, 16, 3, 8, 16, 2, 16, 1)]
 
 
 @pytest.mark.parametrize("tiling", TWO_STEP)
