@@ -130,6 +130,31 @@ def cpu_baseline(case, budget_s):
     return rec, p
 
 
+def cpu_workloads():
+    """The FP64 oracle on samples of the batched workloads (all its OpenMP
+    threads): the first four plates of the 256-plate batch over 100 steps and
+    the first 4096^2 plate of the 1.2 G-node batch over 20 steps, each plate
+    from t = 0 after one untimed step."""
+    from paper_2301_00228_amd import inputs
+
+    out = {}
+    for name, cases, steps in (("batch256", inputs.plate_batch(count=4, steps=0), 100),
+                               ("large", inputs.large_batch(count=1, strip=None, steps=0), 20)):
+        nodes = sum(c.in_body_nodes() for c in cases)
+        plates = [oracle_plate(c) for c in cases]
+        for p in plates:
+            p.step(1)
+        t0 = time.perf_counter()
+        for p in plates:
+            p.step(steps)
+        dt = time.perf_counter() - t0
+        out[name] = {"value": nodes * steps / dt / 1e6, "unit": "MLUPS",
+                     "plates": [f"{c.nx}x{c.ny}" for c in cases], "steps": steps,
+                     "wall_s": round(dt, 2)}
+        del plates
+    return out
+
+
 def copy_rate_gbs(gib=2.0, reps=10):
     """A plain device-to-device copy (the library's copy probe) as the
     practical HBM ceiling."""
@@ -145,6 +170,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of timed oracle steps in the CPU baseline")
+    ap.add_argument("--cpu-workloads", action="store_true",
+                    help="also time the oracle on samples of the batched workloads")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the untimed leg to step 2000 and the rel L2 errors")
@@ -339,6 +366,9 @@ def main():
             for k in ("e", "omega", "u", "v")}
         cpu["fp64_gpu_vs_oracle_step"] = n_orc
         del ref, got
+        if args.cpu_workloads:
+            log("oracle on samples of the batched workloads")
+            cpu["workloads"] = cpu_workloads()
 
     line = {
         "metric": METRIC, "value": round(glups, 4), "unit": "GLUPS", "n_gpus": 1, "steps": K,
