@@ -102,3 +102,30 @@ def test_switches_need_a_context():
     L = lbm.library()
     assert L.lbm_use_overlap(None, 1) == lbm.E_INVAL
     assert L.lbm_use_graphs(None, 1) == lbm.E_INVAL
+
+
+def test_unknown_reading_bits_rejected():
+    with pytest.raises(lbm.LbmError) as ei:
+        lbm.Context([_plate(readings=(4, 0))])
+    assert ei.value.code == lbm.E_INVAL
+
+
+def test_step_entry_points_need_a_context():
+    L = lbm.library()
+    assert L.lbm_prepare_steps(None, 10) == lbm.E_INVAL
+    assert L.lbm_fields_noalloc(None, 0, None, None, None, None) == lbm.E_INVAL
+
+
+def test_copy_rate_rejects_bad_arguments():
+    for nbytes, reps in ((8, 1), (1 << 20, 0)):
+        with pytest.raises(lbm.LbmError) as ei:
+            lbm.copy_rate(nbytes, reps)
+        assert ei.value.code == lbm.E_INVAL
+    assert lbm.library().lbm_copy_rate(1 << 20, 1, None) == lbm.E_INVAL
+
+
+@pytest.mark.skipif(_gpu_present(), reason="checks the no-GPU error path")
+def test_copy_rate_reports_missing_device():
+    with pytest.raises(lbm.LbmError) as ei:
+        lbm.copy_rate(1 << 20, 1)
+    assert ei.value.code == lbm.E_DEVICE
