@@ -277,6 +277,7 @@ def main():
     achieved = own * bpu / per / 1e9
     traffic = measured_traffic(args.storage, kind, tile, overlap)
     copy_gbs = copy_rate_gbs()
+    layout_gbs = lbm.layout_copy_rate(args.storage, info["nodes_allocated"], 10)
     roofline = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -290,6 +291,9 @@ def main():
         "measured_frac": round(traffic / per / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
         "copy_GBs": round(copy_gbs, 1),
         "frac_of_copy": round(achieved / copy_gbs, 4),
+        "layout_copy_GBs": round(layout_gbs, 1),
+        "measured_frac_of_layout_copy": (round(traffic / per / 1e9 / layout_gbs, 4)
+                                         if traffic else None),
         "step_effective_GBs": round(nodes * bpu / (dt / K) / 1e9, 1),
         "step_effective_frac": round(nodes * bpu / (dt / K) / 1e9 / HBM_PEAK_GBS, 4),
     }
@@ -327,8 +331,11 @@ def main():
                           i2["tile_edge_rows"], i2["tile_align"], i2["tile_steps"],
                           i2["tile_edge_cols"], i2["tile_stream_stores"]]}
             t2 = measured_traffic(st, k2, v["tile"], bool(i2["overlap"]))
+            lc2 = lbm.layout_copy_rate(st, i2["nodes_allocated"], 10)
+            v["layout_copy_GBs"] = round(lc2, 1)
             if t2:
                 v["kernel_measured_frac"] = round(t2 / per2 / 1e9 / HBM_PEAK_GBS, 4)
+                v["kernel_measured_frac_of_layout_copy"] = round(t2 / per2 / 1e9 / lc2, 4)
             if not args.no_precision and i2["steps_done"] <= PRECISION_STEPS:
                 c2.step(PRECISION_STEPS - i2["steps_done"])
                 fields[st] = c2.fields(0, want=("e", "omega", "u"))

@@ -413,6 +413,21 @@ const char *lbm_last_error(const lbm_ctx *ctx);
  * 16, reps < 1, NULL gbs), LBM_E_NOMEM, LBM_E_DEVICE. */
 lbm_status lbm_copy_rate(size_t bytes, int32_t reps, double *gbs);
 
+/* Measurement aid: the rate (GB/s, bytes read + written per second) of a
+ * plain copy with the array structure of `storage`'s state (LBM_STORE_*):
+ * each of its arrays over `nodes` nodes (rounded up to a multiple of
+ * 8192 x 16) -- the two fields' population slots and the four arrays of u
+ * and du/dt, at their storage widths -- copied to an array of its own by
+ * 256-lane workgroups marching 256 x 16 blocks of 8192-node rows, as the
+ * interior tiles march, without their arithmetic or halo.  Many arrays
+ * streamed at once reach less than lbm_copy_rate's single stream; this is
+ * the ceiling the layout sets for one pass over the state.  Averaged over
+ * reps launches after two untimed ones; allocates and frees 2 x (number of
+ * arrays) device arrays; synchronizes the device.  Errors (text via
+ * lbm_last_error(NULL)): LBM_E_INVAL (unknown storage, nodes outside
+ * 1 .. 2^32, reps < 1, NULL gbs), LBM_E_NOMEM, LBM_E_DEVICE. */
+lbm_status lbm_layout_copy_rate(int32_t storage, int64_t nodes, int32_t reps, double *gbs);
+
 /* Library version string. */
 const char *lbm_version(void);
 

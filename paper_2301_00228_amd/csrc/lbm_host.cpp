@@ -1585,6 +1585,18 @@ lbm_status lbm_copy_rate(size_t bytes, int32_t reps, double *gbs) {
   return LBM_OK;
 }
 
+lbm_status lbm_layout_copy_rate(int32_t storage, int64_t nodes, int32_t reps, double *gbs) {
+  if (!gbs || storage < LBM_STORE_F64 || storage > LBM_STORE_BF16DEV || nodes < 1 ||
+      nodes > ((int64_t)1 << 32) || reps < 1)
+    return fail(nullptr, LBM_E_INVAL, "bad layout-copy arguments");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
+    return fail(nullptr, LBM_E_DEVICE, "no HIP device available");
+  const hipError_t e = layout_copy_rate(storage, nodes, reps, gbs);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "layout copy probe");
+  return LBM_OK;
+}
+
 const char *lbm_version(void) { return "paper_2301_00228_amd lbm 0.1 (gfx950)"; }
 
 const char *lbm_last_error(const lbm_ctx *c) {

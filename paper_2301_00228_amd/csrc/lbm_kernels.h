@@ -41,6 +41,11 @@ hipError_t launch_cons_err(int storage, const DevState &s, int plate, int64_t no
 // averaged over reps launches after 3 untimed ones; allocates and frees
 // its two buffers.
 hipError_t copy_rate(size_t bytes, int reps, double *gbs);
+// Rate in GB/s (read + write) of a copy with the array structure of
+// `storage`'s state over `nodes` nodes (rounded up to 8192 x 16), marched
+// like the interior tiles; averaged over reps launches after 2 untimed
+// ones; allocates and frees its arrays.
+hipError_t layout_copy_rate(int storage, int64_t nodes, int reps, double *gbs);
 
 // Size of the fixed device staging area of lbm_fields_noalloc (per GPU).
 constexpr size_t kNoAllocBytes = (size_t)48 << 20;

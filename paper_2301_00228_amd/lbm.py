@@ -27,7 +27,8 @@ READ_FLUX_STREAMED, READ_EQ_OLD = 1, 2
 EXPORTS = ["lbm_create", "lbm_set_bc", "lbm_step", "lbm_fields", "lbm_fields_device", "lbm_info",
            "lbm_set_tiling", "lbm_autotune", "lbm_profile", "lbm_use_graphs", "lbm_use_overlap", "lbm_destroy",
            "lbm_last_error", "lbm_version", "lbm_exact_cells", "lbm_consistency_error",
-           "lbm_fields_noalloc", "lbm_prepare_steps", "lbm_copy_rate"]
+           "lbm_fields_noalloc", "lbm_prepare_steps", "lbm_copy_rate",
+           "lbm_layout_copy_rate"]
 SHAPE_HOLE, SHAPE_BOUND = 0, 1
 
 
@@ -102,6 +103,8 @@ def library():
     L.lbm_step.argtypes = [vp, C.c_int64]
     L.lbm_copy_rate.restype = C.c_int
     L.lbm_copy_rate.argtypes = [C.c_size_t, C.c_int32, dp]
+    L.lbm_layout_copy_rate.restype = C.c_int
+    L.lbm_layout_copy_rate.argtypes = [C.c_int32, C.c_int64, C.c_int32, dp]
     L.lbm_prepare_steps.restype = C.c_int
     L.lbm_prepare_steps.argtypes = [vp, C.c_int64]
     L.lbm_fields.restype = C.c_int
@@ -167,6 +170,17 @@ def exact_cells(nx, ny, shapes, xy, dh=1.0, periodic=(False, False)):
     if st != OK:
         raise LbmError(st, "lbm_exact_cells rejected its arguments")
     return cell, ext
+
+
+def layout_copy_rate(storage, nodes, reps=10):
+    """lbm_layout_copy_rate: GB/s of a copy with the array structure of the
+    storage's state over `nodes` nodes."""
+    st = STORAGES[storage] if isinstance(storage, str) else int(storage)
+    out = C.c_double(0)
+    rc = library().lbm_layout_copy_rate(st, int(nodes), int(reps), C.byref(out))
+    if rc != OK:
+        raise LbmError(rc, library().lbm_last_error(None).decode())
+    return out.value
 
 
 def copy_rate(nbytes=2 << 30, reps=10):

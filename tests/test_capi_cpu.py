@@ -129,3 +129,19 @@ def test_copy_rate_reports_missing_device():
     with pytest.raises(lbm.LbmError) as ei:
         lbm.copy_rate(1 << 20, 1)
     assert ei.value.code == lbm.E_DEVICE
+
+
+def test_layout_copy_rate_rejects_bad_arguments():
+    for storage, nodes, reps in ((5, 1 << 20, 1), (-1, 1 << 20, 1), (0, 0, 1), (0, (1 << 32) + 1, 1),
+                                 (0, 1 << 20, 0)):
+        with pytest.raises(lbm.LbmError) as ei:
+            lbm.layout_copy_rate(storage, nodes, reps)
+        assert ei.value.code == lbm.E_INVAL
+    assert lbm.library().lbm_layout_copy_rate(0, 1 << 20, 1, None) == lbm.E_INVAL
+
+
+@pytest.mark.skipif(_gpu_present(), reason="checks the no-GPU error path")
+def test_layout_copy_rate_reports_missing_device():
+    with pytest.raises(lbm.LbmError) as ei:
+        lbm.layout_copy_rate("f64", 1 << 20, 1)
+    assert ei.value.code == lbm.E_DEVICE

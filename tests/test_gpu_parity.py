@@ -537,3 +537,12 @@ def test_reading_switches_change_the_result_and_reject_autotune():
         with pytest.raises(lbm.LbmError) as ei:
             ctx.autotune(2)
         assert ei.value.code == lbm.E_STATE
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f32dev", "f16dev"])
+def test_copy_probes_give_plausible_rates(storage):
+    # a node count that is not a multiple of the probe's 8192 x 16 block
+    rate = lbm.layout_copy_rate(storage, (1 << 22) + 5, 3)
+    assert 100.0 < rate < 8000.0, rate
+    if storage == "f64":
+        assert 100.0 < lbm.copy_rate(1 << 28, 3) < 8000.0

@@ -48,6 +48,10 @@ hipError_t copy_rate(size_t, int, double *gbs) {
   *gbs = 0;
   return hipErrorInvalidValue;
 }
+hipError_t layout_copy_rate(int, int64_t, int, double *gbs) {
+  *gbs = 0;
+  return hipErrorInvalidValue;
+}
 hipError_t noalloc_staging(int, void **ptr) {
   *ptr = nullptr;
   return hipErrorInvalidValue;
