@@ -105,7 +105,8 @@ def oracle_plate(case):
 def cpu_baseline(case, budget_s):
     """Time the FP64 oracle on a bounded sample of the same workload (the
     same plate from t = 0, as many steps as fit the budget, all its OpenMP
-    threads).  Returns the record and the oracle plate (at its last step)."""
+    threads; then one step on one thread).  Returns the record and the
+    oracle plate (at its last step)."""
     from oracle import oracle
 
     t0 = time.perf_counter()
@@ -121,10 +122,18 @@ def cpu_baseline(case, budget_s):
     t0 = time.perf_counter()
     p.step(steps)
     dt = time.perf_counter() - t0
+    # one step on one thread beside it (the serial rate the threads scale from)
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    p.step(1)
+    dt1 = time.perf_counter() - t0
+    oracle.set_threads(threads)
     rec = {"value": nodes * steps / dt / 1e9, "unit": "GLUPS", "cores": threads, "kind": "oracle",
            "sample": f"the same {case.nx}x{case.ny} holed plate from t = 0, {steps} steps "
                      f"(steps 3..{steps + 2}) timed, {dt:.1f} s wall ({setup:.0f} s set-up "
                      f"not counted)",
+           "single_thread": {"value": nodes / dt1 / 1e9, "unit": "GLUPS", "steps": 1,
+                             "wall_s": round(dt1, 2)},
            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
            "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS")}
     return rec, p
