@@ -312,7 +312,8 @@ def main():
             roofline[f"{k}_launch_avg_us"] = round(ms / n * 1e3, 2)
 
     # ---- untimed leg: on to step 2000, the fields the errors are taken on
-    done = info["steps_done"]
+    # (info was read before the profiled steps: take the count as it is now)
+    done = ctx.info()["steps_done"]
     fields = {}
     if not args.no_precision and done <= PRECISION_STEPS:
         ctx.step(PRECISION_STEPS - done)
@@ -345,8 +346,9 @@ def main():
             if t2:
                 v["kernel_measured_frac"] = round(t2 / per2 / 1e9 / HBM_PEAK_GBS, 4)
                 v["kernel_measured_frac_of_layout_copy"] = round(t2 / per2 / 1e9 / lc2, 4)
-            if not args.no_precision and i2["steps_done"] <= PRECISION_STEPS:
-                c2.step(PRECISION_STEPS - i2["steps_done"])
+            done2 = c2.info()["steps_done"]
+            if not args.no_precision and done2 <= PRECISION_STEPS:
+                c2.step(PRECISION_STEPS - done2)
                 fields[st] = c2.fields(0, want=("e", "omega", "u"))
             c2.close()
             del c2
