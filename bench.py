@@ -200,8 +200,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(plates shard across GPUs with no communication; see DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
+              "(a batch of plates would shard across GPUs with no communication)", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -16,7 +16,7 @@ its checkpoint is reached, so a run cut short still leaves every earlier one.
 Or in two parts on two machines, compared on sampled rows (every
 `--row-every`-th row, all columns) after all steps:
 
-    python -u tests/full_size_oracle.py --rows gpu --out gpu_rows/       # GPU machine
+    python -u tests/full_size_oracle.py --rows gpu --out gpu_rows/       # the GPU machine
     python -u tests/full_size_oracle.py --rows oracle --out oracle_rows/ # any host
     python tests/full_size_oracle.py --compare gpu_rows/ oracle_rows/
 """
