@@ -102,3 +102,74 @@ def test_hole8192_f16dev_within_1e3_of_fp64_at_step_2000(hole8192):
         err = float(np.linalg.norm(fields["f16dev"][k] - fields["f64"][k]) / np.linalg.norm(fields["f64"][k]))
         print("hole8192 f16dev vs fp64 at", PRECISION_STEPS, k, f"{err:.3e}", flush=True)
         assert err <= 1e-3, (k, err)
+
+
+# The batched workloads at full size, in the tilings their measurements use
+# (the autotuner's picks, pinned): the FP64 batched path against the oracle
+# plate by plate after a synchronization, and the reduced storage against it
+# at its stated step count.
+BATCH256_TILING = (64, 16, 3, 8, 16, 2, 16, 1)
+STRIP_TILING = (128, 32, 0, 16, 16, 2, 16, 1)
+
+
+def _batched(cases, storage, tiling, steps, want=("e", "omega", "u", "v")):
+    with lbm.context_for(cases, storage) as ctx:
+        ctx.set_tiling(*tiling)
+        ctx.use_overlap(False)
+        ctx.step(steps)
+        return [ctx.fields(p, want=want) for p in range(len(cases))]
+
+
+def test_batch256_fp64_batched_matches_the_oracle_plate_by_plate():
+    import torch
+    torch.cuda.set_device(0)
+    cases = I.plate_batch(count=256, steps=HOLE_STEPS)
+    got = _batched(cases, "f64", BATCH256_TILING, HOLE_STEPS)
+    print("256 plates, %d body nodes; oracle plate by plate" % sum(c.in_body_nodes() for c in cases),
+          flush=True)
+    worst = 0.0
+    for c, g in zip(cases, got):
+        ref, _ = run_case(c, steps=HOLE_STEPS)
+        for k in ("e", "omega", "u", "v"):
+            err = np.abs(g[k] - ref[k]).max() / max(np.abs(ref[k]).max(), 1e-300)
+            worst = max(worst, err)
+            assert err <= 1e-12, (c.name, k, err)
+    print("batch256 fp64 vs oracle, worst rel max-norm %.3e" % worst, flush=True)
+
+
+def test_batch256_f32dev_batched_within_1e3_of_fp64_at_step_1000():
+    cases = I.plate_batch(count=256, steps=1000)
+    want = ("e", "omega", "u")
+    ref = _batched(cases, "f64", BATCH256_TILING, 1000, want)
+    got = _batched(cases, "f32dev", BATCH256_TILING, 1000, want)
+    worst = {k: 0.0 for k in want}
+    for c, g, r in zip(cases, got, ref):
+        for k in want:
+            nb = np.linalg.norm(r[k])
+            err = float(np.linalg.norm(g[k] - r[k]) / (nb if nb > 0 else 1.0))
+            worst[k] = max(worst[k], err)
+            assert err <= 1e-3, (c.name, k, err)
+    print("batch256 f32dev vs fp64 at 1000, worst", worst, flush=True)
+
+
+def test_strip_with_holes_fp64_matches_the_oracle():
+    # the 65536 x 2048 strip with seeded elliptic holes of the 1.2 G-node batch
+    case = I.strip_with_holes(steps=20, seed_index=4)
+    (got,) = _batched([case], "f64", STRIP_TILING, 20)
+    print("strip: oracle, 20 steps", flush=True)
+    ref, _ = run_case(case, steps=20)
+    for k in ("e", "omega", "u", "v"):
+        err = np.abs(got[k] - ref[k]).max() / np.abs(ref[k]).max()
+        print("strip fp64 20 steps", k, f"{err:.3e}", flush=True)
+        assert err <= 1e-12, (k, err)
+
+
+def test_strip_with_holes_f16dev_within_1e3_of_fp64_at_step_2000():
+    case = I.strip_with_holes(steps=PRECISION_STEPS, seed_index=4)
+    want = ("e", "omega", "u")
+    (ref,) = _batched([case], "f64", STRIP_TILING, PRECISION_STEPS, want)
+    (got,) = _batched([case], "f16dev", STRIP_TILING, PRECISION_STEPS, want)
+    for k in want:
+        err = float(np.linalg.norm(got[k] - ref[k]) / np.linalg.norm(ref[k]))
+        print("strip f16dev vs fp64 at", PRECISION_STEPS, k, f"{err:.3e}", flush=True)
+        assert err <= 1e-3, (k, err)
