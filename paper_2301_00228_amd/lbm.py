@@ -317,8 +317,15 @@ class Context:
         current state, without running them."""
         self._check(library().lbm_prepare_steps(self._h, int(n)))
 
+    def _shape(self, plate):
+        # (the output arrays are sized from the plate: an index outside the
+        # context is the library's LBM_E_INVAL, not a Python IndexError)
+        if not 0 <= int(plate) < len(self.shapes):
+            raise LbmError(E_INVAL, f"bad plate index {plate}")
+        return self.shapes[int(plate)]
+
     def fields(self, plate=0, want=("e", "omega", "u", "v")):
-        nx, ny = self.shapes[plate]
+        nx, ny = self._shape(plate)
         e = np.zeros((ny, nx)) if "e" in want else None
         w = np.zeros((ny, nx)) if "omega" in want else None
         u = np.zeros((2, ny, nx)) if "u" in want else None
@@ -331,7 +338,7 @@ class Context:
     def fields_noalloc(self, plate=0, want=("e", "omega", "u", "v")):
         """lbm_fields_noalloc: as fields(), staged through the library's fixed
         device area (no device allocation)."""
-        nx, ny = self.shapes[plate]
+        nx, ny = self._shape(plate)
         e = np.zeros((ny, nx)) if "e" in want else None
         w = np.zeros((ny, nx)) if "omega" in want else None
         u = np.zeros((2, ny, nx)) if "u" in want else None
@@ -343,7 +350,7 @@ class Context:
 
     def consistency_error(self, plate=0):
         """lbm_consistency_error: (ny, nx) array of the consistency error."""
-        nx, ny = self.shapes[plate]
+        nx, ny = self._shape(plate)
         err = np.zeros((ny, nx))
         self._check(library().lbm_consistency_error(self._h, int(plate), _dptr(err)))
         return err

@@ -145,3 +145,10 @@ def test_layout_copy_rate_reports_missing_device():
     with pytest.raises(lbm.LbmError) as ei:
         lbm.layout_copy_rate("f64", 1 << 20, 1)
     assert ei.value.code == lbm.E_DEVICE
+
+
+def test_no_plates_rejected():
+    with pytest.raises(lbm.LbmError) as ei:
+        lbm.Context([])
+    assert ei.value.code == lbm.E_INVAL
+    assert lbm.library().lbm_step(None, 1) == lbm.E_INVAL

@@ -546,3 +546,26 @@ def test_copy_probes_give_plausible_rates(storage):
     assert 100.0 < rate < 8000.0, rate
     if storage == "f64":
         assert 100.0 < lbm.copy_rate(1 << 28, 3) < 8000.0
+
+
+def test_initial_state_step_zero_and_bad_indices():
+    # t = 0 against the oracle, step(0) a no-op, negative counts and plate
+    # indices outside the context rejected without touching the state
+    case = I.plate_with_hole(n=72, radius=10, sigma=3.0, steps=0)
+    ref, _ = run_case(case, steps=0)
+    with lbm.context_for(case) as ctx:
+        f0 = ctx.fields(0)
+        ctx.step(0)
+        assert ctx.info()["steps_done"] == 0
+        assert lbm.library().lbm_step(ctx._h, -1) == lbm.E_INVAL
+        for bad in (1, -1):
+            assert lbm.library().lbm_fields(ctx._h, bad, None, None, None, None) == lbm.E_INVAL
+            with pytest.raises(lbm.LbmError) as ei:
+                ctx.fields(bad)
+            assert ei.value.code == lbm.E_INVAL
+        f1 = ctx.fields(0)
+        ctx.step(3)
+        assert ctx.info()["steps_done"] == 3
+    for k in FIELDS:
+        assert np.array_equal(f0[k], f1[k]), k
+    assert_parity(f0, ref, what="t = 0")
