@@ -127,12 +127,20 @@ def main():
     ctx, res = timed(cases, args.storage, args.steps, args.warmup, tiling=tiling, overlap=overlap)
     res["workload"] = args.workload
     print(json.dumps(res), flush=True)
+    nodes_allocated = ctx.info()["nodes_allocated"]
+    ctx.close()
+    del ctx
+    # the ceiling the state layout sets: a plain copy of the storage's own
+    # arrays over as many nodes (after the context is gone, so that both
+    # need not fit in memory at once)
+    lc = lbm.layout_copy_rate(args.storage, nodes_allocated, 5)
+    print(json.dumps({"workload": args.workload, "storage": args.storage,
+                      "layout_copy_GBs": round(lc, 1),
+                      "interior_frac_of_layout_copy": round(res["interior_GBs"] / lc, 4)}), flush=True)
     if args.ref:
         # Reference and reduced run plate by plate from t = 0 for the same
         # number of steps (bounds memory: the FP64 state of the whole batch
         # may not fit next to the reduced one).
-        ctx.close()
-        del ctx
         picks = list(range(len(cases)))
         if args.ref_plates and len(cases) > args.ref_plates + 1:
             picks = list(range(args.ref_plates)) + [len(cases) - 1]
